@@ -1,0 +1,205 @@
+/*
+ * hs.h -- C ABI of the MI355X (gfx950) implementation of the matrix-free Hermite
+ * Galerkin method on hyperbolically reduced index sets (Brumm, arXiv 1403.3511).
+ *
+ * Conventions for every entry point
+ *   - Every call returns an int32 status: HS_OK (0), an informational code (> 0) or an
+ *     error (< 0).  No call aborts or throws across this boundary.  The text of the
+ *     last error of the calling thread is available from hs_last_error().
+ *   - "host" pointers are ordinary CPU memory owned by the caller; "device" pointers are
+ *     caller-owned GPU allocations (e.g. the data of a PyTorch CUDA/HIP tensor) that must
+ *     stay alive and unmodified while work that uses them is in flight.  Device pointers
+ *     must be 16-byte aligned (256 recommended).
+ *   - Work is enqueued on the caller's hipStream_t (passed as void*; NULL means the
+ *     default stream).  Nothing synchronises unless its name ends in _sync.
+ *   - Handles (hs_index, hs_pot, hs_plan, hs_batch, hs_mlp) are host objects owned by the
+ *     library; destroy them with the matching *_destroy call.  A handle may be used by
+ *     one thread at a time.
+ *   - Complex vectors are interleaved (re, im): complex128 = 2 x float64 (HS_C128) or
+ *     complex64 = 2 x float32 (HS_C64).
+ *
+ * Notation.  N is the dimension, B the product bound of the index set
+ *     K = { k in N_0^N : prod_l (1 + k_l) <= B }              (paper Sec. 1.2),
+ * i.e. B = K_paper + 1.  H = D + W^pol(X_K) with D = diag(sum_l (k_l + 1/2)) and W the
+ * potential minus |x|^2/2 (Sec. 1.2), W^pol(X_K) the formal insertion of the coordinate
+ * matrices X_K^(l) (Sec. 3.1-3.2, eq. Horner), axis N applied first, axis 1 last.
+ */
+#ifndef HS_H
+#define HS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------- */
+#define HS_OK 0
+#define HS_INFO_BREAKDOWN 1   /* Lanczos stopped early; see m_eff                       */
+#define HS_E_INVALID -1       /* bad argument (null handle/pointer, N/B out of range ...) */
+#define HS_E_OVERFLOW -2      /* a size does not fit the index types                    */
+#define HS_E_NOMEM -3         /* host allocation failed                                 */
+#define HS_E_WORKSPACE -4     /* caller buffer smaller than the size query returned     */
+#define HS_E_UNSUPPORTED -5   /* combination not implemented (e.g. basis/kernel class)  */
+#define HS_E_HIP -6           /* a HIP runtime call failed; text in hs_last_error        */
+#define HS_E_NONFINITE -7     /* non-finite coefficients                                */
+
+/* ---- dtypes, bases ------------------------------------------------------------ */
+#define HS_C128 0 /* complex float64 */
+#define HS_C64 1  /* complex float32 (float32 arithmetic in the matvec) */
+
+#define HS_BASIS_MONO 0 /* p_a(x) = x^a                                              */
+#define HS_BASIS_CHEB 1 /* p_a(x) = T_a(x / scale), Chebyshev 1st kind (Sec. 1.3)     */
+#define HS_BASIS_HERM 2 /* p_a(x) = H_a(x / scale), physicists' Hermite polynomials   */
+
+#define HS_NMAX 16
+
+typedef struct hs_index_s *hs_index;
+typedef struct hs_pot_s *hs_pot;
+typedef struct hs_batch_s *hs_batch;
+typedef struct hs_mlp_s *hs_mlp;
+
+/* Text of the last error on this thread (truncated to len-1 bytes, NUL-terminated). */
+int32_t hs_last_error(char *buf, size_t len);
+/* Library version string, e.g. "1.0 gfx950". */
+const char *hs_version(void);
+
+/* ---- index set (paper Sec. 1.2; neighbour maps k +- e_l for Sec. 3.1) ------------
+ * hs_index_create enumerates K_N(B) on the host.  Layout: rows are grouped in tiles
+ * that share the prefix (k_1..k_{N-d}); inside a tile the suffix (k_{N-d+1}..k_N) runs
+ * over one global list of K_d(B) sorted by (prod(1+s), lex), so a tile with remaining
+ * bound b holds exactly the first |K_d(b)| entries of that list.  tile_dim d in 1..N
+ * (0 = library choice).  Requires 1 <= N <= HS_NMAX, 1 <= B <= 65536, |K| < 2^31.   */
+int32_t hs_index_create(int32_t N, int64_t B, int32_t tile_dim, hs_index *out);
+int32_t hs_index_destroy(hs_index idx);
+/* |K|, the number of rows of every vector over this set. */
+int32_t hs_index_size(hs_index idx, int64_t *n);
+/* tile_dim actually used, number of tiles, length of the global suffix list. */
+int32_t hs_index_info(hs_index idx, int32_t *tile_dim, int64_t *ntiles, int64_t *nsuffix);
+/* Multi-index of every row in library order: host_out has n*N uint16, row-major.     */
+int32_t hs_index_multi_indices(hs_index idx, uint16_t *host_out);
+/* Device metadata: query the size, then upload into a caller device buffer of at
+ * least that many bytes (stream-ordered host->device copy from pinned staging held by
+ * the handle).  Every compute call on this index takes the same device pointer.     */
+int32_t hs_index_device_bytes(hs_index idx, int64_t *bytes);
+int32_t hs_index_upload(hs_index idx, void *dev, int64_t bytes, void *stream);
+
+/* ---- potential (paper Sec. 1.3; W = V - |x|^2/2, Sec. 1.2) ---------------------
+ * Terms t = 0..nterms-1 with per-axis degrees degrees[t*N + l] in the given basis and
+ * time-dependent coefficients  beta_t(t) = base_t + amp_t * sin(freq_t * t + phase_t).
+ * subtract_harmonic != 0 (monomial basis only) turns V into W by lowering the x_l^2
+ * coefficient by 1/2 for every axis.  The compiler classifies the potential:
+ *   class HH (every monomial, after basis change, is x_l^a with a <= 3 or
+ *   x_l^a x_{l+1} with a <= 2): served by the fused row kernel;
+ *   otherwise: served by the generic recurrence-pass program.                       */
+int32_t hs_pot_create(int32_t N, int32_t basis, double scale, int32_t nterms,
+                      const uint16_t *degrees, const double *base, const double *amp,
+                      const double *freq, const double *phase, int32_t subtract_harmonic,
+                      hs_pot *out);
+int32_t hs_pot_destroy(hs_pot pot);
+/* 1 if the fused (class HH) kernel serves this potential, 0 for the generic program. */
+int32_t hs_pot_is_fused(hs_pot pot, int32_t *fused);
+/* Device parameter block of the potential: size query and stream-ordered upload.   */
+int32_t hs_pot_device_bytes(hs_pot pot, int64_t *bytes);
+int32_t hs_pot_upload(hs_pot pot, void *dev, int64_t bytes, void *stream);
+/* Evaluate the term coefficients at time t on the device (paper Fig. 4 step (1)),
+ * writing them into the device parameter block; graph-capturable (t is read from the
+ * device scalar t_dev when t_dev != NULL, else the host value t is used).           */
+int32_t hs_pot_set_time(hs_pot pot, void *pot_dev, double t, const double *t_dev, void *stream);
+/* Replace the time-dependent base coefficients by values already on the device
+ * (nterms doubles, e.g. written by the surrogate or the quadrature kernels).          */
+int32_t hs_pot_set_coeffs_device(hs_pot pot, void *pot_dev, const double *coef_dev, void *stream);
+
+/* ---- H application (paper Sec. 3.2, eq. Horner; Fig. 4 step (2)) ----------------
+ * y = (D + W^pol(X_K)) c for the coefficients currently in pot_dev.  c and y are
+ * device vectors of |K| complex values in library row order, of the given dtype;
+ * c != y.  ws is a device workspace of hs_workspace_bytes(..., m = 0) bytes (may be
+ * NULL when that size is 0).                                                         */
+int32_t hs_workspace_bytes(hs_index idx, hs_pot pot, int32_t dtype, int32_t m, int64_t *bytes);
+int32_t hs_apply_h(hs_index idx, const void *idx_dev, hs_pot pot, const void *pot_dev,
+                   int32_t dtype, const void *c, void *y, void *ws, void *stream);
+
+/* ---- time step (paper Sec. 2, eq. expMPR; Fig. 4) ----------------------------
+ * One exponential-midpoint step of length h with an m-step Lanczos exponential:
+ * coefficients at t + h/2, m applications of H, c <- V_m exp(-i h T_m) e_1 ||c||.
+ * c is complex128 (state) whatever dtype is; dtype selects the precision of the
+ * Krylov vectors and the matvec (HS_C64: complex64 vectors and float32 matvec,
+ * float64 dot products, norms, T_m eigensolve and combination).  reorth != 0 adds one
+ * classical Gram-Schmidt pass per Lanczos step.  m <= 32.  ws holds
+ * hs_workspace_bytes(..., m) bytes.  t_dev (device double, may be NULL) supplies t
+ * and is advanced by h on the device, so a captured graph can be replayed per step.
+ * diag_dev (device, may be NULL) receives the (m_eff, alpha[0..m), beta[0..m))
+ * record of the step as doubles: 1 + 2m values.                                     */
+int32_t hs_step(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev, int32_t dtype,
+                double t, double *t_dev, double h, int32_t m, int32_t reorth, void *c, void *ws,
+                double *diag_dev, void *stream);
+
+/* ---- batched form: many (index, potential) instances in one persistent launch ----
+ * Instances are described by handles plus their uploaded device blocks; vectors of
+ * all instances are packed back to back in one device buffer with offsets given by
+ * hs_batch_offsets (complex elements, host int64[n+1]).                              */
+int32_t hs_batch_create(int32_t n, const hs_index *idx, const void *const *idx_dev,
+                        const hs_pot *pot, void *const *pot_dev, hs_batch *out);
+int32_t hs_batch_destroy(hs_batch b);
+int32_t hs_batch_offsets(hs_batch b, int64_t *host_out);
+int32_t hs_batch_device_bytes(hs_batch b, int64_t *bytes);
+int32_t hs_batch_upload(hs_batch b, void *dev, int64_t bytes, void *stream);
+int32_t hs_batch_workspace_bytes(hs_batch b, int32_t m, int64_t *bytes);
+/* y = H_i c_i for every instance i, one persistent launch (complex128). */
+int32_t hs_batch_apply_h(hs_batch b, const void *batch_dev, const void *c, void *y, void *ws,
+                         void *stream);
+/* One exponential-midpoint Lanczos step for every instance (complex128). */
+int32_t hs_batch_step(hs_batch b, void *batch_dev, double t, double h, int32_t m,
+                      int32_t reorth, void *c, void *ws, void *stream);
+/* Launch-shape choice of the persistent kernel: workgroup size and rows per item.
+ * wg = 0 or chunk = 0 keep the current value.  hs_batch_autotune_sync times the
+ * candidates on the given buffers and keeps the fastest (synchronises the stream).  */
+int32_t hs_batch_set_launch(hs_batch b, int32_t wg, int32_t chunk);
+int32_t hs_batch_get_launch(hs_batch b, int32_t *wg, int32_t *chunk);
+int32_t hs_batch_autotune_sync(hs_batch b, const void *batch_dev, const void *c, void *y,
+                               void *ws, void *stream);
+
+/* ---- learned coefficients: Gauss-Hermite projection and a BF16-MFMA MLP --------
+ * Potential family W(x) = - sum_i a_i exp(-|x - c_i(t)|^2 / (2 sigma^2)) in N <= 8
+ * dimensions, c_i(t) = base_i + rho (cos(omega t + phi_i) u_i + sin(omega t + phi_i) w_i)
+ * with geometry (base, u, w, phi) fixed per family; parameters per sample
+ * p = (t, a_1..a_G, sigma, rho, omega).  Coefficients: Hermite polynomials
+ * H_a(x) = prod_l H_{a_l}(x_l) (physicists') with |a| <= D in lexicographic order of a.
+ *
+ * hs_gh_project: alpha_a = <W, H_a> / <H_a, H_a> with weight exp(-|x|^2), by product
+ * Gauss-Hermite quadrature with Q nodes per axis (paper Sec. 4.1), for nsamp parameter
+ * rows (device, nsamp x (3 + G) doubles) into coef (device, nsamp x ncoef doubles).
+ * geometry (host): base, u, w as G x N doubles each, then phase (G doubles).        */
+int32_t hs_gh_ncoef(int32_t N, int32_t D, int32_t *ncoef);
+int32_t hs_gh_project(int32_t N, int32_t G, int32_t D, int32_t Q, const double *geometry_host,
+                      int32_t nsamp, const double *params_dev, double *coef_dev, void *stream);
+
+/* MLP in -> hidden -> hidden -> out with SiLU; BF16 operands on MFMA, FP32 accumulate,
+ * FP32 master weights and Adam.  in <= 32, hidden a multiple of 64 (<= 512), out <= 512.
+ * The device block (hs_mlp_device_bytes) holds weights, Adam moments and the
+ * input/output normalisation; hs_mlp_upload_params sets weights (host float32:
+ * W1 (hid x in), b1, W2 (hid x hid), b2, W3 (out x hid), b3) and normalisation
+ * (in_lo[in], in_hi[in], out_mean[out], out_std[out]).                              */
+int32_t hs_mlp_create(int32_t in, int32_t hidden, int32_t out, hs_mlp *mlp);
+int32_t hs_mlp_destroy(hs_mlp mlp);
+int32_t hs_mlp_device_bytes(hs_mlp mlp, int32_t max_batch, int64_t *bytes);
+int32_t hs_mlp_upload_params(hs_mlp mlp, void *dev, const float *weights_host,
+                             const float *norm_host, void *stream);
+int32_t hs_mlp_download_params(hs_mlp mlp, const void *dev, float *weights_host, void *stream);
+/* Forward on raw parameters x (device, batch x in float64) -> coefficients (device,
+ * batch x out float64), de-normalised. */
+int32_t hs_mlp_predict(hs_mlp mlp, void *dev, int32_t batch, const double *x_dev,
+                       double *coef_dev, void *stream);
+/* One training step on (x, target coefficients) (device float64), MSE on normalised
+ * outputs, Adam(lr, 0.9, 0.999, 1e-8).  loss_dev (device float, may be NULL) receives
+ * the loss.  grads_dev (device, may be NULL) receives the float32 gradients in the
+ * weight layout above (before the update).                                          */
+int32_t hs_mlp_train_step(hs_mlp mlp, void *dev, int32_t batch, const double *x_dev,
+                          const double *target_dev, float lr, float *loss_dev,
+                          float *grads_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HS_H */

@@ -1,0 +1,133 @@
+// C ABI entry points: argument validation, device-block uploads and dispatch.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "hs_internal.h"
+
+namespace hs {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+int32_t fail(int32_t code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+int32_t hip_fail(hipError_t e, const char *what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return HS_E_HIP;
+}
+
+int32_t launch_copy_coeffs(const hs_pot_s *p, void *pot_dev, const double *coef, hipStream_t s);
+int32_t launch_apply(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p,
+                     const void *pot_dev, int32_t dtype, const void *x, void *y, void *ws,
+                     hipStream_t s, const double *out_scale, const void *prev,
+                     const double *prev_coef, const double *prev_scale);
+int32_t launch_step(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p, void *pot_dev,
+                    int32_t dtype, double t, double *t_dev, double h, int m, int reorth, void *c,
+                    void *ws, double *diag, hipStream_t s);
+int64_t step_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32_t dtype, int m);
+
+static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace hs
+
+extern "C" int32_t hs_last_error(char *buf, size_t len) {
+  if (!buf || len == 0) return HS_E_INVALID;
+  const std::string &e = hs::g_last_error;
+  const size_t n = std::min(len - 1, e.size());
+  std::memcpy(buf, e.data(), n);
+  buf[n] = 0;
+  return HS_OK;
+}
+
+extern "C" const char *hs_version(void) { return "1.0 gfx950"; }
+
+extern "C" int32_t hs_pot_upload(hs_pot pot, void *dev, int64_t bytes, void *stream) {
+  if (!pot || !dev) return hs::fail(HS_E_INVALID, "hs_pot_upload: NULL argument");
+  if (bytes < pot->dev_bytes) return hs::fail(HS_E_WORKSPACE, "hs_pot_upload: device buffer too small");
+  if (!hs::aligned16(dev)) return hs::fail(HS_E_INVALID, "hs_pot_upload: device pointer not 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // host image of the static part (base, amp, freq, phase, M); pinned so the copy is
+  // asynchronous; kept alive by the handle until it is destroyed or re-uploaded
+  static_assert(sizeof(double) == 8, "");
+  std::vector<uint8_t> img(pot->dev_bytes, 0);
+  auto put = [&](int64_t off, const double *src, int64_t n) {
+    if (n > 0) std::memcpy(img.data() + off, src, n * 8);
+  };
+  put(pot->off_base, pot->base.data(), pot->nterms);
+  put(pot->off_amp, pot->amp.data(), pot->nterms);
+  put(pot->off_freq, pot->freq.data(), pot->nterms);
+  put(pot->off_phase, pot->phase.data(), pot->nterms);
+  if (pot->fused) put(pot->off_M, pot->M.data(), (int64_t)pot->nslots * pot->nterms);
+  void *pinned = nullptr;
+  HS_HIP(hipHostMalloc(&pinned, pot->dev_bytes, hipHostMallocDefault));
+  std::memcpy(pinned, img.data(), pot->dev_bytes);
+  hipError_t e = hipMemcpyAsync(dev, pinned, pot->dev_bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    (void)hipHostFree(pinned);
+    return hs::hip_fail(e, "hs_pot_upload: hipMemcpyAsync");
+  }
+  // the staging buffer must outlive the copy: wait for it here (upload is not hot)
+  e = hipStreamSynchronize(s);
+  (void)hipHostFree(pinned);
+  if (e != hipSuccess) return hs::hip_fail(e, "hs_pot_upload: hipStreamSynchronize");
+  return hs::launch_set_time(pot, dev, 0.0, nullptr, 0.0, s);
+}
+
+extern "C" int32_t hs_pot_set_time(hs_pot pot, void *pot_dev, double t, const double *t_dev,
+                                   void *stream) {
+  if (!pot || !pot_dev) return hs::fail(HS_E_INVALID, "hs_pot_set_time: NULL argument");
+  if (!t_dev && !std::isfinite(t)) return hs::fail(HS_E_NONFINITE, "hs_pot_set_time: t not finite");
+  return hs::launch_set_time(pot, pot_dev, t, t_dev, 0.0, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int32_t hs_pot_set_coeffs_device(hs_pot pot, void *pot_dev, const double *coef_dev,
+                                            void *stream) {
+  if (!pot || !pot_dev || !coef_dev) return hs::fail(HS_E_INVALID, "hs_pot_set_coeffs_device: NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int32_t st = hs::launch_copy_coeffs(pot, pot_dev, coef_dev, s);
+  if (st != HS_OK) return st;
+  return hs::launch_set_time(pot, pot_dev, 0.0, nullptr, 0.0, s);
+}
+
+extern "C" int32_t hs_workspace_bytes(hs_index idx, hs_pot pot, int32_t dtype, int32_t m,
+                                      int64_t *bytes) {
+  if (!idx || !pot || !bytes) return hs::fail(HS_E_INVALID, "hs_workspace_bytes: NULL argument");
+  if (dtype != HS_C128 && dtype != HS_C64) return hs::fail(HS_E_INVALID, "hs_workspace_bytes: bad dtype");
+  if (m < 0 || m > 32) return hs::fail(HS_E_INVALID, "hs_workspace_bytes: m out of range 0..32");
+  if (pot->N != idx->N) return hs::fail(HS_E_INVALID, "hs_workspace_bytes: potential and index differ in N");
+  *bytes = hs::step_workspace_bytes(idx, pot, dtype, m);
+  return HS_OK;
+}
+
+extern "C" int32_t hs_apply_h(hs_index idx, const void *idx_dev, hs_pot pot, const void *pot_dev,
+                              int32_t dtype, const void *c, void *y, void *ws, void *stream) {
+  if (!idx || !pot || !idx_dev || !pot_dev || !c || !y)
+    return hs::fail(HS_E_INVALID, "hs_apply_h: NULL argument");
+  if (pot->N != idx->N) return hs::fail(HS_E_INVALID, "hs_apply_h: potential and index differ in N");
+  if (dtype != HS_C128 && dtype != HS_C64) return hs::fail(HS_E_INVALID, "hs_apply_h: bad dtype");
+  if (c == y) return hs::fail(HS_E_INVALID, "hs_apply_h: input and output must differ");
+  if (!hs::aligned16(c) || !hs::aligned16(y) || !hs::aligned16(idx_dev) || !hs::aligned16(pot_dev))
+    return hs::fail(HS_E_INVALID, "hs_apply_h: device pointer not 16-byte aligned");
+  if (hs::apply_workspace_bytes(idx, pot, dtype) > 0 && (!ws || !hs::aligned16(ws)))
+    return hs::fail(HS_E_WORKSPACE, "hs_apply_h: this potential needs a workspace");
+  return hs::launch_apply(idx, idx_dev, pot, pot_dev, dtype, c, y, ws,
+                          static_cast<hipStream_t>(stream), nullptr, nullptr, nullptr, nullptr);
+}
+
+extern "C" int32_t hs_step(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev,
+                           int32_t dtype, double t, double *t_dev, double h, int32_t m,
+                           int32_t reorth, void *c, void *ws, double *diag_dev, void *stream) {
+  if (!idx || !pot || !idx_dev || !pot_dev || !c || !ws)
+    return hs::fail(HS_E_INVALID, "hs_step: NULL argument");
+  if (pot->N != idx->N) return hs::fail(HS_E_INVALID, "hs_step: potential and index differ in N");
+  if (dtype != HS_C128 && dtype != HS_C64) return hs::fail(HS_E_INVALID, "hs_step: bad dtype");
+  if (m < 1 || m > 32) return hs::fail(HS_E_INVALID, "hs_step: m out of range 1..32");
+  if (!std::isfinite(h) || (!t_dev && !std::isfinite(t))) return hs::fail(HS_E_NONFINITE, "hs_step: t or h not finite");
+  if (!hs::aligned16(c) || !hs::aligned16(ws) || !hs::aligned16(idx_dev) || !hs::aligned16(pot_dev))
+    return hs::fail(HS_E_INVALID, "hs_step: device pointer not 16-byte aligned");
+  return hs::launch_step(idx, idx_dev, pot, pot_dev, dtype, t, t_dev, h, m, reorth, c, ws, diag_dev,
+                         static_cast<hipStream_t>(stream));
+}

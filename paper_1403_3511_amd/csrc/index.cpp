@@ -1,0 +1,388 @@
+// Host-side construction of the tiled index layout of K_N(B) = {k : prod(1 + k_l) <= B}
+// (paper Sec. 1.2) with the neighbour maps k +- e_l needed by the direct operation with
+// the coordinate matrices (Sec. 3.1).
+//
+// Layout.  Rows are grouped into tiles sharing the prefix p = (k_1..k_{N-d}).  The tile
+// of p has remaining bound b_p = floor(B / prod(1 + p_i)); its rows are the suffixes
+// s in K_d(b_p).  All suffix lists are initial segments of ONE global list G = K_d(B)
+// sorted by (prod(1 + s), lex s), so the row (p, s) sits at tstart[p] + pos_G(s) and a
+// move along a prefix axis keeps the offset inside the tile.
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "hs_internal.h"
+
+namespace {
+
+constexpr int64_t kSat = INT64_C(1) << 62;
+
+// |K_n(b)| for every b in the set {floor(B / q)} that division keeps reaching.
+struct Counter {
+  int64_t B = 0;
+  int nmax = 0;
+  std::vector<int32_t> slot;                 // b -> position in vals (-1: unreachable)
+  std::vector<int64_t> vals;                 // reachable bounds, ascending
+  std::vector<std::vector<int64_t>> cnt;     // cnt[n][slot]
+  Counter(int64_t B_, int nmax_) : B(B_), nmax(nmax_), slot(B_ + 1, -1) {
+    for (int64_t q = 1; q <= B; ++q) {
+      int64_t b = B / q;
+      if (slot[b] < 0) slot[b] = 0;
+      if (b * b < B && q * q >= B) {  // remaining values are exactly 1..b
+        for (int64_t x = 1; x <= b; ++x) slot[x] = 0;
+        break;
+      }
+    }
+    for (int64_t b = 1; b <= B; ++b)
+      if (slot[b] >= 0) {
+        slot[b] = (int32_t)vals.size();
+        vals.push_back(b);
+      }
+    cnt.assign(nmax + 1, std::vector<int64_t>(vals.size(), 0));
+    for (size_t i = 0; i < vals.size(); ++i) cnt[0][i] = 1;
+    for (int n = 1; n <= nmax; ++n)
+      for (size_t i = 0; i < vals.size(); ++i) {
+        int64_t b = vals[i], s = 0;
+        // group the terms a with equal floor(b / a)
+        for (int64_t a = 1; a <= b;) {
+          int64_t v = b / a, a2 = b / v;
+          s += (a2 - a + 1) * cnt[n - 1][slot[v]];
+          if (s > kSat) s = kSat;
+          a = a2 + 1;
+        }
+        cnt[n][i] = s;
+      }
+  }
+  int64_t count(int n, int64_t b) const { return b < 1 ? 0 : cnt[n][slot[b]]; }
+};
+
+// Lexicographic rank inside K_n(B) for multi-indices of length n.
+struct LexRank {
+  const Counter *C;
+  int n;
+  int64_t B;
+  // cum[i][slot(b)][a] = sum_{a' < a} |K_{n-1-i}(floor(b / (1 + a')))|
+  std::vector<std::vector<std::vector<int64_t>>> cum;
+  LexRank(const Counter *C_, int n_, int64_t B_) : C(C_), n(n_), B(B_) {
+    cum.resize(n);
+    for (int i = 0; i < n; ++i) {
+      cum[i].resize(C->vals.size());
+      for (size_t si = 0; si < C->vals.size(); ++si) {
+        int64_t b = C->vals[si];
+        auto &v = cum[i][si];
+        v.resize(b + 1);
+        v[0] = 0;
+        for (int64_t a = 0; a < b; ++a) v[a + 1] = v[a] + C->count(n - 1 - i, b / (1 + a));
+      }
+    }
+  }
+  // k must be a member of K_n(B)
+  int64_t rank(const int32_t *k) const {
+    int64_t r = 0, b = B;
+    for (int i = 0; i < n; ++i) {
+      r += cum[i][C->slot[b]][k[i]];
+      b /= (1 + k[i]);
+    }
+    return r;
+  }
+};
+
+bool member(const int32_t *k, int n, int64_t B) {
+  int64_t p = 1;
+  for (int i = 0; i < n; ++i) {
+    if (k[i] < 0) return false;
+    p *= (1 + k[i]);
+    if (p > B) return false;
+  }
+  return true;
+}
+
+// Lexicographic enumeration of K_n(B): calls f(k) for each member.
+template <class F>
+void enumerate(int n, int64_t B, F &&f) {
+  std::vector<int32_t> k(n, 0);
+  if (n == 0) {
+    f(k.data());
+    return;
+  }
+  std::vector<int64_t> bound(n + 1);
+  bound[0] = B;
+  int lvl = 0;
+  k[0] = 0;
+  while (true) {
+    // descend with zeros
+    for (; lvl < n - 1; ++lvl) {
+      bound[lvl + 1] = bound[lvl] / (1 + k[lvl]);
+      k[lvl + 1] = 0;
+    }
+    // at the last level run over all admissible values
+    int64_t b = bound[n - 1];
+    for (int32_t a = 0; a < b; ++a) {
+      k[n - 1] = a;
+      f(k.data());
+    }
+    // advance the deepest level that can still grow
+    int up = n - 2;
+    while (up >= 0) {
+      k[up] += 1;
+      if (1 + k[up] <= bound[up]) break;
+      --up;
+    }
+    if (up < 0) return;
+    lvl = up;
+  }
+}
+
+}  // namespace
+
+hs::IndexDev hs_index_s::view(const void *dev) const {
+  const uint8_t *b = static_cast<const uint8_t *>(dev);
+  hs::IndexDev v;
+  v.N = N;
+  v.d = d;
+  v.np = np;
+  v.B = (int32_t)B;
+  v.size = size;
+  v.ntiles = ntiles;
+  v.ng = ng;
+  v.tstart = reinterpret_cast<const int64_t *>(b + off_tstart);
+  v.tlen = reinterpret_cast<const int32_t *>(b + off_tlen);
+  v.tnbr = reinterpret_cast<const int32_t *>(b + off_tnbr);
+  v.tpfx = reinterpret_cast<const uint16_t *>(b + off_tpfx);
+  v.tpsum = reinterpret_cast<const int32_t *>(b + off_tpsum);
+  v.gsidx = reinterpret_cast<const uint16_t *>(b + off_gsidx);
+  v.gnbr = reinterpret_cast<const int32_t *>(b + off_gnbr);
+  v.gssum = reinterpret_cast<const int32_t *>(b + off_gssum);
+  v.rowtile = reinterpret_cast<const int32_t *>(b + off_rowtile);
+  v.wtab = reinterpret_cast<const double *>(b + off_wtab);
+  v.wtabf = reinterpret_cast<const float *>(b + off_wtabf);
+  return v;
+}
+
+static int32_t default_tile_dim(int32_t N) { return N <= 2 ? N : (N <= 4 ? 2 : 3); }
+
+static int32_t build_index(hs_index_s *ix) {
+  const int N = ix->N, d = ix->d, np = ix->np;
+  const int64_t B = ix->B;
+  Counter C(B, N);
+  const int64_t total = C.count(N, B);
+  if (total >= (INT64_C(1) << 31) - 1) return hs::fail(HS_E_OVERFLOW, "index set has 2^31 or more rows");
+  const int64_t ntiles = C.count(np, B);
+  const int64_t ng = C.count(d, B);
+  ix->size = total;
+  ix->ntiles = ntiles;
+  ix->ng = ng;
+
+  // ---- global suffix list G = K_d(B), graded by (prod, lex) ----
+  std::vector<int32_t> glex((size_t)ng * d);
+  std::vector<int64_t> gprod(ng);
+  {
+    int64_t i = 0;
+    enumerate(d, B, [&](const int32_t *k) {
+      int64_t p = 1;
+      for (int a = 0; a < d; ++a) {
+        glex[i * d + a] = k[a];
+        p *= 1 + k[a];
+      }
+      gprod[i] = p;
+      ++i;
+    });
+  }
+  std::vector<int64_t> order(ng);
+  for (int64_t i = 0; i < ng; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return gprod[a] < gprod[b]; });
+  std::vector<int64_t> gpos_of_lex(ng);
+  for (int64_t g = 0; g < ng; ++g) gpos_of_lex[order[g]] = g;
+  ix->gsidx.resize((size_t)ng * d);
+  ix->gssum.resize(ng);
+  for (int64_t g = 0; g < ng; ++g) {
+    int32_t s = 0;
+    for (int a = 0; a < d; ++a) {
+      ix->gsidx[g * d + a] = (uint16_t)glex[order[g] * d + a];
+      s += glex[order[g] * d + a];
+    }
+    ix->gssum[g] = s;
+  }
+  // length of the initial segment with prod <= b
+  std::vector<int32_t> seglen(B + 1, 0);
+  for (int64_t g = 0; g < ng; ++g) seglen[gprod[order[g]]]++;
+  for (int64_t b = 1; b <= B; ++b) seglen[b] += seglen[b - 1];
+  // suffix neighbours
+  ix->gnbr.assign((size_t)ng * 2 * d, -1);
+  if (d > 0) {
+    LexRank R(&C, d, B);
+    std::vector<int32_t> k(d);
+    for (int64_t g = 0; g < ng; ++g) {
+      for (int a = 0; a < d; ++a) k[a] = ix->gsidx[g * d + a];
+      for (int a = 0; a < d; ++a)
+        for (int dir = 0; dir < 2; ++dir) {
+          k[a] += dir ? 1 : -1;
+          if (member(k.data(), d, B)) ix->gnbr[g * 2 * d + 2 * a + dir] = (int32_t)gpos_of_lex[R.rank(k.data())];
+          k[a] -= dir ? 1 : -1;
+        }
+    }
+  }
+
+  // ---- tiles: prefixes K_np(B) in lex order ----
+  ix->tpfx.resize((size_t)ntiles * np);
+  ix->tlen.resize(ntiles);
+  ix->tpsum.resize(ntiles);
+  ix->tstart.resize(ntiles + 1);
+  {
+    int64_t t = 0, start = 0;
+    enumerate(np, B, [&](const int32_t *p) {
+      int64_t prod = 1;
+      int32_t s = 0;
+      for (int i = 0; i < np; ++i) {
+        ix->tpfx[t * np + i] = (uint16_t)p[i];
+        prod *= 1 + p[i];
+        s += p[i];
+      }
+      ix->tlen[t] = seglen[B / prod];
+      ix->tpsum[t] = s;
+      ix->tstart[t] = start;
+      start += ix->tlen[t];
+      ++t;
+    });
+    ix->tstart[ntiles] = start;
+    if (start != total) return hs::fail(HS_E_INVALID, "internal: tile lengths do not add up to |K|");
+  }
+  ix->tnbr.assign((size_t)ntiles * 2 * np, -1);
+  if (np > 0) {
+    LexRank R(&C, np, B);
+    std::vector<int32_t> p(np);
+    for (int64_t t = 0; t < ntiles; ++t) {
+      for (int i = 0; i < np; ++i) p[i] = ix->tpfx[t * np + i];
+      for (int i = 0; i < np; ++i)
+        for (int dir = 0; dir < 2; ++dir) {
+          p[i] += dir ? 1 : -1;
+          if (member(p.data(), np, B)) ix->tnbr[t * 2 * np + 2 * i + dir] = (int32_t)R.rank(p.data());
+          p[i] -= dir ? 1 : -1;
+        }
+    }
+  }
+  ix->rowtile.resize(total);
+  for (int64_t t = 0; t < ntiles; ++t)
+    for (int64_t r = ix->tstart[t]; r < ix->tstart[t + 1]; ++r) ix->rowtile[r] = (int32_t)t;
+
+  // ---- device image ----
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    int64_t o = off;
+    off = hs::align_up(off + std::max<int64_t>(bytes, 1), 256);
+    return o;
+  };
+  ix->off_tstart = take((ntiles + 1) * 8);
+  ix->off_tlen = take(ntiles * 4);
+  ix->off_tnbr = take(ntiles * 2 * np * 4);
+  ix->off_tpfx = take(ntiles * np * 2);
+  ix->off_tpsum = take(ntiles * 4);
+  ix->off_gsidx = take(ng * d * 2);
+  ix->off_gnbr = take(ng * 2 * d * 4);
+  ix->off_gssum = take(ng * 4);
+  ix->off_rowtile = take(total * 4);
+  ix->off_wtab = take((B + 8) * 8);
+  ix->off_wtabf = take((B + 8) * 4);
+  ix->dev_bytes = off;
+  ix->blob.assign(off, 0);
+  auto put = [&](int64_t o, const void *src, int64_t bytes) {
+    if (bytes > 0) std::memcpy(ix->blob.data() + o, src, bytes);
+  };
+  put(ix->off_tstart, ix->tstart.data(), (ntiles + 1) * 8);
+  put(ix->off_tlen, ix->tlen.data(), ntiles * 4);
+  put(ix->off_tnbr, ix->tnbr.data(), ntiles * 2 * np * 4);
+  put(ix->off_tpfx, ix->tpfx.data(), ntiles * np * 2);
+  put(ix->off_tpsum, ix->tpsum.data(), ntiles * 4);
+  put(ix->off_gsidx, ix->gsidx.data(), ng * d * 2);
+  put(ix->off_gnbr, ix->gnbr.data(), ng * 2 * d * 4);
+  put(ix->off_gssum, ix->gssum.data(), ng * 4);
+  put(ix->off_rowtile, ix->rowtile.data(), total * 4);
+  std::vector<double> w(B + 8);
+  std::vector<float> wf(B + 8);
+  for (int64_t k = 0; k < B + 8; ++k) {
+    w[k] = std::sqrt(0.5 * (double)k);
+    wf[k] = (float)w[k];
+  }
+  put(ix->off_wtab, w.data(), (B + 8) * 8);
+  put(ix->off_wtabf, wf.data(), (B + 8) * 4);
+  return HS_OK;
+}
+
+extern "C" int32_t hs_index_create(int32_t N, int64_t B, int32_t tile_dim, hs_index *out) {
+  if (!out) return hs::fail(HS_E_INVALID, "hs_index_create: out is NULL");
+  *out = nullptr;
+  if (N < 1 || N > HS_NMAX) return hs::fail(HS_E_INVALID, "hs_index_create: N out of range 1..16");
+  if (B < 1 || B > 65536) return hs::fail(HS_E_INVALID, "hs_index_create: B out of range 1..65536");
+  if (tile_dim < 0 || tile_dim > N) return hs::fail(HS_E_INVALID, "hs_index_create: tile_dim out of range 0..N");
+  hs_index_s *ix = new (std::nothrow) hs_index_s();
+  if (!ix) return hs::fail(HS_E_NOMEM, "hs_index_create: out of host memory");
+  ix->N = N;
+  ix->B = B;
+  ix->d = tile_dim ? tile_dim : default_tile_dim(N);
+  ix->np = N - ix->d;
+  int32_t st;
+  try {
+    st = build_index(ix);
+  } catch (const std::bad_alloc &) {
+    st = hs::fail(HS_E_NOMEM, "hs_index_create: out of host memory");
+  }
+  if (st != HS_OK) {
+    delete ix;
+    return st;
+  }
+  *out = ix;
+  return HS_OK;
+}
+
+extern "C" int32_t hs_index_destroy(hs_index idx) {
+  if (!idx) return HS_OK;
+  if (idx->pinned) (void)hipHostFree(idx->pinned);
+  delete idx;
+  return HS_OK;
+}
+
+extern "C" int32_t hs_index_size(hs_index idx, int64_t *n) {
+  if (!idx || !n) return hs::fail(HS_E_INVALID, "hs_index_size: NULL argument");
+  *n = idx->size;
+  return HS_OK;
+}
+
+extern "C" int32_t hs_index_info(hs_index idx, int32_t *tile_dim, int64_t *ntiles, int64_t *nsuffix) {
+  if (!idx) return hs::fail(HS_E_INVALID, "hs_index_info: NULL handle");
+  if (tile_dim) *tile_dim = idx->d;
+  if (ntiles) *ntiles = idx->ntiles;
+  if (nsuffix) *nsuffix = idx->ng;
+  return HS_OK;
+}
+
+extern "C" int32_t hs_index_multi_indices(hs_index idx, uint16_t *out) {
+  if (!idx || !out) return hs::fail(HS_E_INVALID, "hs_index_multi_indices: NULL argument");
+  const int N = idx->N, d = idx->d, np = idx->np;
+  for (int64_t t = 0; t < idx->ntiles; ++t)
+    for (int64_t r = idx->tstart[t]; r < idx->tstart[t + 1]; ++r) {
+      int64_t o = r - idx->tstart[t];
+      uint16_t *dst = out + r * N;
+      for (int i = 0; i < np; ++i) dst[i] = idx->tpfx[t * np + i];
+      for (int a = 0; a < d; ++a) dst[np + a] = idx->gsidx[o * d + a];
+    }
+  return HS_OK;
+}
+
+extern "C" int32_t hs_index_device_bytes(hs_index idx, int64_t *bytes) {
+  if (!idx || !bytes) return hs::fail(HS_E_INVALID, "hs_index_device_bytes: NULL argument");
+  *bytes = idx->dev_bytes;
+  return HS_OK;
+}
+
+extern "C" int32_t hs_index_upload(hs_index idx, void *dev, int64_t bytes, void *stream) {
+  if (!idx || !dev) return hs::fail(HS_E_INVALID, "hs_index_upload: NULL argument");
+  if (bytes < idx->dev_bytes) return hs::fail(HS_E_WORKSPACE, "hs_index_upload: device buffer too small");
+  if (reinterpret_cast<uintptr_t>(dev) % 16) return hs::fail(HS_E_INVALID, "hs_index_upload: device pointer not 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!idx->pinned) {
+    HS_HIP(hipHostMalloc(&idx->pinned, idx->dev_bytes, hipHostMallocDefault));
+    std::memcpy(idx->pinned, idx->blob.data(), idx->dev_bytes);
+  }
+  HS_HIP(hipMemcpyAsync(dev, idx->pinned, idx->dev_bytes, hipMemcpyHostToDevice, s));
+  return HS_OK;
+}

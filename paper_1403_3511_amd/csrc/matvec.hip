@@ -1,0 +1,367 @@
+// H application y = (D + W^pol(X_K)) c on gfx950 (paper Sec. 3.1-3.2, eq. Horner).
+//
+// Two kernels families:
+//  * hh_rows: one lane per row.  The potential is grouped by outer axis l; the group's
+//    operator  X_l(X_l(X_l(a3 c) + a2 c + g2 X_{l+1} c) + a1 c + g1 X_{l+1} c)  is the
+//    Horner form of a1 x_l + a2 x_l^2 + a3 x_l^3 + g1 x_l x_{l+1} + g2 x_l^2 x_{l+1} with
+//    X_{l+1} applied first, evaluated on the window j + s e_l, |s| <= 3, of the row's
+//    axis-l fibre (the layered binary tree of Sec. 5.3 restricted to one layer pair).
+//    Truncation at the fibre ends enters through absent edges: the edge between fibre
+//    positions k-1 and k carries sqrt(k/2) only if both lie in K (Sec. 3.1: a missing
+//    neighbour contributes nothing).
+//  * generic passes: one kernel per recurrence step p_{k+1} = A X_l p_k + B p_k - C p_{k-1}
+//    over the whole vector, following the program compiled from the term trie.
+//
+// No MFMA: the operator is a sparse stencil, not a dense contraction.
+#include "hs_internal.h"
+
+namespace hs {
+
+template <typename T> struct V2;
+template <> struct V2<double> { using t = double2; };
+template <> struct V2<float> { using t = float2; };
+
+template <typename T>
+__device__ __forceinline__ typename V2<T>::t vz() {
+  typename V2<T>::t r;
+  r.x = T(0);
+  r.y = T(0);
+  return r;
+}
+template <typename T, typename U>
+__device__ __forceinline__ void fma_rc(typename V2<T>::t &acc, U w, const typename V2<T>::t &x) {
+  acc.x = fma((T)w, x.x, acc.x);
+  acc.y = fma((T)w, x.y, acc.y);
+}
+template <typename T>
+__device__ __forceinline__ typename V2<T>::t scal(T w, const typename V2<T>::t &x) {
+  typename V2<T>::t r;
+  r.x = w * x.x;
+  r.y = w * x.y;
+  return r;
+}
+
+struct Pos {
+  int32_t t, o;
+};
+
+// move one step along axis (0-based) in direction up (1: +e, 0: -e); t < 0 = absent
+__device__ __forceinline__ Pos mv(const IndexDev &ix, Pos p, int axis, int up) {
+  if (p.t < 0) return p;
+  if (axis < ix.np) {
+    const int32_t t2 = ix.tnbr[(int64_t)p.t * (2 * ix.np) + 2 * axis + up];
+    if (t2 < 0 || (up && p.o >= ix.tlen[t2])) return Pos{-1, 0};
+    return Pos{t2, p.o};
+  }
+  const int a = axis - ix.np;
+  const int32_t o2 = ix.gnbr[(int64_t)p.o * (2 * ix.d) + 2 * a + up];
+  if (o2 < 0 || (up && o2 >= ix.tlen[p.t])) return Pos{-1, 0};
+  return Pos{p.t, o2};
+}
+
+__device__ __forceinline__ int coord(const IndexDev &ix, Pos p, int axis) {
+  return axis < ix.np ? (int)ix.tpfx[(int64_t)p.t * ix.np + axis]
+                      : (int)ix.gsidx[(int64_t)p.o * ix.d + (axis - ix.np)];
+}
+
+template <typename T>
+__device__ __forceinline__ typename V2<T>::t ld(const typename V2<T>::t *__restrict__ c,
+                                                const IndexDev &ix, Pos p) {
+  if (p.t < 0) return vz<T>();
+  return c[ix.tstart[p.t] + p.o];
+}
+
+// ---- coefficient update (paper Fig. 4 step (1)) -------------------------------------
+// beta_t = base_t + amp_t sin(freq_t (t + dt) + phase_t); hh[s] = sum_t M[s][t] beta_t
+__global__ void k_set_time(int nterms, int nslots, const double *__restrict__ base,
+                           const double *__restrict__ amp, const double *__restrict__ freq,
+                           const double *__restrict__ phase, const double *__restrict__ M,
+                           double *__restrict__ beta, double *__restrict__ hh, double t_host,
+                           const double *__restrict__ t_dev, double dt) {
+  __shared__ double sb[kMaxTerms];
+  const double t = (t_dev ? *t_dev : t_host) + dt;
+  for (int i = threadIdx.x; i < nterms; i += blockDim.x) {
+    const double b = base[i] + amp[i] * sin(freq[i] * t + phase[i]);
+    sb[i] = b;
+    beta[i] = b;
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
+    double acc = 0.0;
+    for (int i = 0; i < nterms; ++i) acc = fma(M[(int64_t)s * nterms + i], sb[i], acc);
+    hh[s] = acc;
+  }
+}
+
+__global__ void k_copy_coeffs(int n, const double *__restrict__ src, double *__restrict__ base,
+                              double *__restrict__ amp) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    base[i] = src[i];
+    amp[i] = 0.0;
+  }
+}
+
+// ---- fused row kernel ----------------------------------------------------------------
+// y = out_scale * (D + c0 + sum_l G_l) x  -  prev_coef * prev_scale * prev
+// out_scale / prev_coef / prev_scale are read from device scalars when given (Lanczos),
+// else taken as 1 / 0.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_hh_rows(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *__restrict__ x,
+          typename V2<T>::t *__restrict__ y, const double *__restrict__ out_scale,
+          const typename V2<T>::t *__restrict__ prev, const double *__restrict__ prev_coef,
+          const double *__restrict__ prev_scale) {
+  using C = typename V2<T>::t;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ix.size) return;
+  const T *wt;
+  if constexpr (sizeof(T) == 8) wt = (const T *)ix.wtab; else wt = (const T *)ix.wtabf;
+  const int32_t t0 = ix.rowtile[r];
+  const Pos p0{t0, (int32_t)(r - ix.tstart[t0])};
+  const int N = ix.N;
+  const C c0 = x[r];
+  const double dval = (double)(ix.tpsum[t0] + ix.gssum[p0.o]) + 0.5 * N + hh[5 * N];
+  C acc = scal<T>((T)dval, c0);
+
+  for (int l = 0; l < N; ++l) {
+    const T a1 = (T)hh[5 * l + 0], a2 = (T)hh[5 * l + 1], a3 = (T)hh[5 * l + 2];
+    const T g1 = (l + 1 < N) ? (T)hh[5 * l + 3] : T(0);
+    const T g2 = (l + 1 < N) ? (T)hh[5 * l + 4] : T(0);
+    const bool any2 = (a3 != T(0)) || (a2 != T(0)) || (g2 != T(0));
+    if (!any2 && a1 == T(0) && g1 == T(0)) continue;  // uniform across the grid
+    const int jl = coord(ix, p0, l);
+    Pos P[7];
+    P[3] = p0;
+    P[4] = mv(ix, P[3], l, 1);
+    P[2] = mv(ix, P[3], l, 0);
+    C u[7];
+    u[3] = c0;
+    u[4] = ld<T>(x, ix, P[4]);
+    u[2] = ld<T>(x, ix, P[2]);
+    T e[6];  // e[s + 2] = weight of the edge between window positions s-1 and s
+    e[2] = (P[2].t >= 0) ? wt[jl] : T(0);
+    e[3] = (P[4].t >= 0) ? wt[jl + 1] : T(0);
+    if (any2) {
+      P[5] = mv(ix, P[4], l, 1);
+      P[1] = mv(ix, P[2], l, 0);
+      u[5] = ld<T>(x, ix, P[5]);
+      u[1] = ld<T>(x, ix, P[1]);
+      e[1] = (P[1].t >= 0) ? wt[jl - 1] : T(0);
+      e[4] = (P[5].t >= 0) ? wt[jl + 2] : T(0);
+      if (a3 != T(0)) {
+        P[6] = mv(ix, P[5], l, 1);
+        P[0] = mv(ix, P[1], l, 0);
+        u[6] = ld<T>(x, ix, P[6]);
+        u[0] = ld<T>(x, ix, P[0]);
+        e[0] = (P[0].t >= 0) ? wt[jl - 2] : T(0);
+        e[5] = (P[6].t >= 0) ? wt[jl + 3] : T(0);
+      } else {
+        u[6] = vz<T>();
+        u[0] = vz<T>();
+        e[0] = e[5] = T(0);
+      }
+    } else {
+      u[5] = u[1] = u[6] = u[0] = vz<T>();
+      e[0] = e[1] = e[4] = e[5] = T(0);
+    }
+    // X_{l+1} c on the window (inner axis applied first)
+    C v[5];  // v[s + 2], s = -2..2
+    for (int s = 0; s < 5; ++s) v[s] = vz<T>();
+    if (g1 != T(0) || g2 != T(0)) {
+      const int jn = coord(ix, p0, l + 1);
+      const T wlo = wt[jn], whi = wt[jn + 1];
+      for (int s = -2; s <= 2; ++s) {
+        if ((s & 1) ? (g1 == T(0)) : (g2 == T(0))) continue;
+        const Pos q = P[3 + s];
+        if (q.t < 0) continue;
+        C vs = vz<T>();
+        if (jn > 0) fma_rc<T>(vs, wlo, ld<T>(x, ix, mv(ix, q, l + 1, 0)));
+        fma_rc<T>(vs, whi, ld<T>(x, ix, mv(ix, q, l + 1, 1)));
+        v[s + 2] = vs;
+      }
+    }
+    // Horner along axis l
+    C h2[3];  // s = -2, 0, 2
+    for (int q = 0; q < 3; ++q) {
+      const int s = 2 * q - 2;
+      C h = vz<T>();
+      if (any2) {
+        C xu = vz<T>();
+        fma_rc<T>(xu, e[s + 2], u[3 + s - 1]);
+        fma_rc<T>(xu, e[s + 3], u[3 + s + 1]);
+        h = scal<T>(a3, xu);
+        fma_rc<T>(h, a2, u[3 + s]);
+        fma_rc<T>(h, g2, v[s + 2]);
+      }
+      h2[q] = h;
+    }
+    C h1[2];  // s = -1, 1
+    for (int q = 0; q < 2; ++q) {
+      const int s = 2 * q - 1;
+      C h = vz<T>();
+      fma_rc<T>(h, e[s + 2], h2[q]);
+      fma_rc<T>(h, e[s + 3], h2[q + 1]);
+      fma_rc<T>(h, a1, u[3 + s]);
+      fma_rc<T>(h, g1, v[s + 2]);
+      h1[q] = h;
+    }
+    fma_rc<T>(acc, e[2], h1[0]);
+    fma_rc<T>(acc, e[3], h1[1]);
+  }
+  if (out_scale) acc = scal<T>((T)*out_scale, acc);
+  if (prev) {
+    const T pc = (T)(-(*prev_coef) * (prev_scale ? *prev_scale : 1.0));
+    fma_rc<T>(acc, pc, prev[r]);
+  }
+  y[r] = acc;
+}
+
+// ---- generic passes -------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_diag(IndexDev ix, const typename V2<T>::t *__restrict__ x, typename V2<T>::t *__restrict__ y) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ix.size) return;
+  const int32_t t0 = ix.rowtile[r];
+  const int32_t o = (int32_t)(r - ix.tstart[t0]);
+  const double dval = (double)(ix.tpsum[t0] + ix.gssum[o]) + 0.5 * ix.N;
+  y[r] = scal<T>((T)dval, x[r]);
+}
+
+// dst = A X_axis src + Bc src - C prev ; optionally y += beta[term] dst
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_pass(IndexDev ix, int axis, double A, double Bc, double Cc,
+       const typename V2<T>::t *__restrict__ src, const typename V2<T>::t *__restrict__ prev,
+       typename V2<T>::t *__restrict__ dst, typename V2<T>::t *__restrict__ y,
+       const double *__restrict__ beta, int term) {
+  using C = typename V2<T>::t;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ix.size) return;
+  const T *wt;
+  if constexpr (sizeof(T) == 8) wt = (const T *)ix.wtab; else wt = (const T *)ix.wtabf;
+  const int32_t t0 = ix.rowtile[r];
+  const Pos p{t0, (int32_t)(r - ix.tstart[t0])};
+  const int j = coord(ix, p, axis);
+  C xs = vz<T>();
+  if (j > 0) fma_rc<T>(xs, wt[j], ld<T>(src, ix, mv(ix, p, axis, 0)));
+  fma_rc<T>(xs, wt[j + 1], ld<T>(src, ix, mv(ix, p, axis, 1)));
+  const C s0 = src[r];
+  C out = scal<T>((T)A, xs);
+  fma_rc<T>(out, (T)Bc, s0);
+  if (prev) fma_rc<T>(out, (T)(-Cc), prev[r]);
+  dst[r] = out;
+  if (term >= 0) {
+    C yy = y[r];
+    fma_rc<T>(yy, (T)beta[term], out);
+    y[r] = yy;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_accum(int64_t n, const typename V2<T>::t *__restrict__ src, typename V2<T>::t *__restrict__ y,
+        const double *__restrict__ beta, int term) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  typename V2<T>::t yy = y[r];
+  fma_rc<T>(yy, (T)beta[term], src[r]);
+  y[r] = yy;
+}
+
+// y = out_scale * y - prev_coef * prev_scale * prev (epilogue of the generic program)
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_epilogue(int64_t n, typename V2<T>::t *__restrict__ y, const double *__restrict__ out_scale,
+           const typename V2<T>::t *__restrict__ prev, const double *__restrict__ prev_coef,
+           const double *__restrict__ prev_scale) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  typename V2<T>::t a = y[r];
+  if (out_scale) a = scal<T>((T)*out_scale, a);
+  if (prev) fma_rc<T>(a, (T)(-(*prev_coef) * (prev_scale ? *prev_scale : 1.0)), prev[r]);
+  y[r] = a;
+}
+
+// ---- host launchers -------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+int32_t launch_set_time(const hs_pot_s *p, void *pot_dev, double t, const double *t_dev,
+                        double dt, hipStream_t s) {
+  uint8_t *b = static_cast<uint8_t *>(pot_dev);
+  hipLaunchKernelGGL(k_set_time, dim3(1), dim3(256), 0, s, p->nterms, p->fused ? p->nslots : 0,
+                     (const double *)(b + p->off_base), (const double *)(b + p->off_amp),
+                     (const double *)(b + p->off_freq), (const double *)(b + p->off_phase),
+                     (const double *)(b + p->off_M), (double *)(b + p->off_beta),
+                     (double *)(b + p->off_hh), t, t_dev, dt);
+  HS_HIP(hipGetLastError());
+  return HS_OK;
+}
+
+int32_t launch_copy_coeffs(const hs_pot_s *p, void *pot_dev, const double *coef, hipStream_t s) {
+  uint8_t *b = static_cast<uint8_t *>(pot_dev);
+  hipLaunchKernelGGL(k_copy_coeffs, dim3(1), dim3(256), 0, s, p->nterms, coef,
+                     (double *)(b + p->off_base), (double *)(b + p->off_amp));
+  HS_HIP(hipGetLastError());
+  return HS_OK;
+}
+
+int64_t apply_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32_t dtype) {
+  if (p->fused) return 0;
+  const int64_t es = dtype == HS_C64 ? 8 : 16;
+  // slots 0 (input) and 1 (output) are the caller's vectors
+  return align_up(idx->size * es, 256) * std::max(0, p->nslots_vec - 2);
+}
+
+template <typename T>
+static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p,
+                          const void *pot_dev, const void *x, void *y, void *ws, hipStream_t s,
+                          const double *out_scale, const void *prev, const double *prev_coef,
+                          const double *prev_scale) {
+  using C = typename V2<T>::t;
+  const IndexDev ix = idx->view(idx_dev);
+  const uint8_t *pb = static_cast<const uint8_t *>(pot_dev);
+  const double *hh = (const double *)(pb + p->off_hh);
+  const double *beta = (const double *)(pb + p->off_beta);
+  const unsigned g = nblk(idx->size, 256);
+  if (idx->size == 0) return HS_OK;
+  if (p->fused) {
+    hipLaunchKernelGGL(k_hh_rows<T>, dim3(g), dim3(256), 0, s, ix, hh, (const C *)x, (C *)y,
+                       out_scale, (const C *)prev, prev_coef, prev_scale);
+    HS_HIP(hipGetLastError());
+    return HS_OK;
+  }
+  const int64_t stride = align_up(idx->size * (int64_t)sizeof(C), 256);
+  auto slot = [&](int k) -> C * {
+    if (k == 0) return (C *)x;
+    if (k == 1) return (C *)y;
+    return (C *)((uint8_t *)ws + (int64_t)(k - 2) * stride);
+  };
+  hipLaunchKernelGGL(k_diag<T>, dim3(g), dim3(256), 0, s, ix, (const C *)x, (C *)y);
+  for (const PassOp &op : p->prog) {
+    if (op.kind == 0) {
+      hipLaunchKernelGGL(k_pass<T>, dim3(g), dim3(256), 0, s, ix, op.axis, op.A, op.Bc, op.C,
+                         (const C *)slot(op.src), op.prev >= 0 ? (const C *)slot(op.prev) : nullptr,
+                         slot(op.dst), (C *)y, beta, op.term);
+    } else {
+      hipLaunchKernelGGL(k_accum<T>, dim3(g), dim3(256), 0, s, idx->size, (const C *)slot(op.src),
+                         (C *)y, beta, op.term);
+    }
+  }
+  if (out_scale || prev)
+    hipLaunchKernelGGL(k_epilogue<T>, dim3(g), dim3(256), 0, s, idx->size, (C *)y, out_scale,
+                       (const C *)prev, prev_coef, prev_scale);
+  HS_HIP(hipGetLastError());
+  return HS_OK;
+}
+
+int32_t launch_apply(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p,
+                     const void *pot_dev, int32_t dtype, const void *x, void *y, void *ws,
+                     hipStream_t s, const double *out_scale, const void *prev,
+                     const double *prev_coef, const double *prev_scale) {
+  if (dtype == HS_C128)
+    return apply_impl<double>(idx, idx_dev, p, pot_dev, x, y, ws, s, out_scale, prev, prev_coef, prev_scale);
+  return apply_impl<float>(idx, idx_dev, p, pot_dev, x, y, ws, s, out_scale, prev, prev_coef, prev_scale);
+}
+
+}  // namespace hs

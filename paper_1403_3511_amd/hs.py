@@ -1,0 +1,245 @@
+"""ctypes binding of libhs.so (include/hs.h) -- argument marshalling only.
+
+Every function of the C ABI is exposed under its own name with checked status codes
+(HSError on failure).  The helper classes below only allocate device memory through
+PyTorch and pass raw pointers and the current HIP stream; every step of the method
+runs in the library's kernels.  There is no fallback: if libhs.so is missing the
+import fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhs.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} not built: run __graft_entry__.build() or "
+                      "python -m paper_1403_3511_amd.build")
+_lib = C.CDLL(LIB_PATH)
+
+HS_OK, HS_INFO_BREAKDOWN = 0, 1
+HS_C128, HS_C64 = 0, 1
+HS_BASIS_MONO, HS_BASIS_CHEB, HS_BASIS_HERM = 0, 1, 2
+BASIS = {"mono": HS_BASIS_MONO, "cheb": HS_BASIS_CHEB, "herm": HS_BASIS_HERM}
+
+_vp, _i32, _i64, _f64, _f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_float
+_pi64, _pi32, _pf64, _pf32, _pu16 = (C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_float),
+                                     C.POINTER(C.c_uint16))
+
+_SIGS = {
+    "hs_last_error": [C.c_char_p, C.c_size_t],
+    "hs_index_create": [_i32, _i64, _i32, C.POINTER(_vp)],
+    "hs_index_destroy": [_vp],
+    "hs_index_size": [_vp, _pi64],
+    "hs_index_info": [_vp, _pi32, _pi64, _pi64],
+    "hs_index_multi_indices": [_vp, _pu16],
+    "hs_index_device_bytes": [_vp, _pi64],
+    "hs_index_upload": [_vp, _vp, _i64, _vp],
+    "hs_pot_create": [_i32, _i32, _f64, _i32, _pu16, _pf64, _pf64, _pf64, _pf64, _i32, C.POINTER(_vp)],
+    "hs_pot_destroy": [_vp],
+    "hs_pot_is_fused": [_vp, _pi32],
+    "hs_pot_device_bytes": [_vp, _pi64],
+    "hs_pot_upload": [_vp, _vp, _i64, _vp],
+    "hs_pot_set_time": [_vp, _vp, _f64, _vp, _vp],
+    "hs_pot_set_coeffs_device": [_vp, _vp, _vp, _vp],
+    "hs_workspace_bytes": [_vp, _vp, _i32, _i32, _pi64],
+    "hs_apply_h": [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
+    "hs_step": [_vp, _vp, _vp, _vp, _i32, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
+    "hs_batch_create": [_i32, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp)],
+    "hs_batch_destroy": [_vp],
+    "hs_batch_offsets": [_vp, _pi64],
+    "hs_batch_device_bytes": [_vp, _pi64],
+    "hs_batch_upload": [_vp, _vp, _i64, _vp],
+    "hs_batch_workspace_bytes": [_vp, _i32, _pi64],
+    "hs_batch_apply_h": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "hs_batch_step": [_vp, _vp, _f64, _f64, _i32, _i32, _vp, _vp, _vp],
+    "hs_batch_set_launch": [_vp, _i32, _i32],
+    "hs_batch_get_launch": [_vp, _pi32, _pi32],
+    "hs_batch_autotune_sync": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "hs_gh_ncoef": [_i32, _i32, _pi32],
+    "hs_gh_project": [_i32, _i32, _i32, _i32, _pf64, _i32, _vp, _vp, _vp],
+    "hs_mlp_create": [_i32, _i32, _i32, C.POINTER(_vp)],
+    "hs_mlp_destroy": [_vp],
+    "hs_mlp_device_bytes": [_vp, _i32, _pi64],
+    "hs_mlp_upload_params": [_vp, _vp, _pf32, _pf32, _vp],
+    "hs_mlp_download_params": [_vp, _vp, _pf32, _vp],
+    "hs_mlp_predict": [_vp, _vp, _i32, _vp, _vp, _vp],
+    "hs_mlp_train_step": [_vp, _vp, _i32, _vp, _vp, _f32, _vp, _vp, _vp],
+}
+
+EXPORTED = sorted(list(_SIGS) + ["hs_version"])
+
+
+class HSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def last_error() -> str:
+    buf = C.create_string_buffer(1024)
+    _lib.hs_last_error(buf, 1024)
+    return buf.value.decode(errors="replace")
+
+
+def _wrap(name, argtypes):
+    f = getattr(_lib, name)
+    f.argtypes = argtypes
+    f.restype = C.c_int32
+
+    def call(*args):
+        st = f(*args)
+        if st < 0:
+            raise HSError(st, f"{name}: {last_error()}")
+        return st
+
+    call.__name__ = name
+    return call
+
+
+_lib.hs_version.restype = C.c_char_p
+_lib.hs_version.argtypes = []
+for _n, _a in _SIGS.items():
+    globals()[_n] = _wrap(_n, _a)
+_lib_raw = _lib
+
+
+def hs_version() -> str:
+    return _lib.hs_version().decode()
+
+
+# ---------------------------------------------------------------------------------------
+# marshalling helpers (PyTorch only supplies device memory and the stream)
+# ---------------------------------------------------------------------------------------
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def dev_buffer(nbytes: int, device="cuda"):
+    """A 256-byte aligned uint8 device tensor of at least nbytes (>= 1)."""
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+class Index:
+    """Host handle + uploaded device block of K_N(B)."""
+
+    def __init__(self, N: int, B: int, tile_dim: int = 0, device="cuda", upload=True):
+        h = _vp()
+        hs_index_create(N, B, tile_dim, C.byref(h))
+        self.h, self.N, self.B = h, N, B
+        n = C.c_int64()
+        hs_index_size(h, C.byref(n))
+        self.size = n.value
+        d, nt, ng = C.c_int32(), C.c_int64(), C.c_int64()
+        hs_index_info(h, C.byref(d), C.byref(nt), C.byref(ng))
+        self.tile_dim, self.ntiles, self.nsuffix = d.value, nt.value, ng.value
+        self.dev = None
+        if upload:
+            nb = C.c_int64()
+            hs_index_device_bytes(h, C.byref(nb))
+            self.dev = dev_buffer(nb.value, device)
+            hs_index_upload(h, ptr(self.dev), nb.value, stream_ptr())
+
+    def multi_indices(self) -> np.ndarray:
+        out = np.empty((self.size, self.N), dtype=np.uint16)
+        hs_index_multi_indices(self.h, out.ctypes.data_as(_pu16))
+        return out
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                _lib.hs_index_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class Pot:
+    """Potential handle + device parameter block.
+
+    terms: list of (base, degrees) or (base, amp, freq, phase, degrees) tuples."""
+
+    def __init__(self, N, terms, basis="mono", scale=1.0, subtract_harmonic=False,
+                 device="cuda", upload=True):
+        deg, base, amp, freq, phase = [], [], [], [], []
+        for t in terms:
+            if len(t) == 2:
+                b, a = t
+                am = fr = ph = 0.0
+            else:
+                b, am, fr, ph, a = t
+            deg.append(list(a))
+            base.append(b)
+            amp.append(am)
+            freq.append(fr)
+            phase.append(ph)
+        nt = len(terms)
+        deg = np.ascontiguousarray(np.array(deg, dtype=np.uint16).reshape(nt, N))
+        arrs = [np.ascontiguousarray(np.array(x, dtype=np.float64)) for x in (base, amp, freq, phase)]
+        h = _vp()
+        hs_pot_create(N, BASIS[basis] if isinstance(basis, str) else int(basis), float(scale), nt,
+                      deg.ctypes.data_as(_pu16), *[x.ctypes.data_as(_pf64) for x in arrs],
+                      1 if subtract_harmonic else 0, C.byref(h))
+        self.h, self.N, self.nterms = h, N, nt + (N if subtract_harmonic else 0)
+        f = C.c_int32()
+        hs_pot_is_fused(h, C.byref(f))
+        self.fused = bool(f.value)
+        self.dev = None
+        if upload:
+            nb = C.c_int64()
+            hs_pot_device_bytes(h, C.byref(nb))
+            self.dev = dev_buffer(nb.value, device)
+            hs_pot_upload(h, ptr(self.dev), nb.value, stream_ptr())
+
+    def set_time(self, t: float):
+        hs_pot_set_time(self.h, ptr(self.dev), float(t), None, stream_ptr())
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                _lib.hs_pot_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def workspace(idx: Index, pot: Pot, dtype: int, m: int, device="cuda"):
+    nb = C.c_int64()
+    hs_workspace_bytes(idx.h, pot.h, dtype, m, C.byref(nb))
+    return dev_buffer(nb.value, device)
+
+
+def apply_h(idx: Index, pot: Pot, c, y, dtype: int = HS_C128, ws=None):
+    """y = H c; c, y complex device tensors in library row order."""
+    if ws is None:
+        ws = workspace(idx, pot, dtype, 0, c.device)
+    hs_apply_h(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, ptr(c), ptr(y), ptr(ws), stream_ptr())
+    return y
+
+
+def step(idx: Index, pot: Pot, c, t: float, h: float, m: int, dtype: int = HS_C128,
+         reorth: bool = True, ws=None, t_dev=None, diag=None):
+    """One exponential-midpoint Lanczos step in place on c (complex128 device tensor)."""
+    if ws is None:
+        ws = workspace(idx, pot, dtype, m, c.device)
+    hs_step(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, float(t), ptr(t_dev), float(h), int(m),
+            1 if reorth else 0, ptr(c), ptr(ws), ptr(diag), stream_ptr())
+    return c

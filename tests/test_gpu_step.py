@@ -1,0 +1,118 @@
+"""GPU parity of the exponential-midpoint Lanczos step (paper Fig. 4) against the oracle's
+propagator, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle.index import IndexSet
+from oracle.operators import fast_apply_H
+from oracle.propagate import lanczos_expm
+from synth import complex_normal_by_index, coherent_state
+from tests.hsutil import hh_workload, lib_terms, lib_to_lex, oracle_W, rel2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hs():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1403_3511_amd import hs as _hs
+    return _hs
+
+
+def oracle_steps(N, B, tt, c, t0, h, n, m, reorth=True):
+    ix = IndexSet(N, B)
+    t = t0
+    for _ in range(n):
+        W = oracle_W(N, tt, t + 0.5 * h)
+        c, _, _, _ = lanczos_expm(lambda v: fast_apply_H(ix, W, v), c, h, m, reorth)
+        t += h
+    return c
+
+
+def gpu_steps(hs, N, B, tt, c_lex, t0, h, n, m, dtype=0, reorth=True, use_tdev=False):
+    import torch
+    idx = hs.Index(N, B)
+    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    lexpos = lib_to_lex(idx, N, B)
+    c = torch.from_numpy(c_lex[lexpos].copy()).to("cuda")
+    ws = hs.workspace(idx, pot, dtype, m)
+    tdev = torch.tensor([t0], dtype=torch.float64, device="cuda") if use_tdev else None
+    diag = torch.zeros(1 + 2 * m, dtype=torch.float64, device="cuda")
+    t = t0
+    for _ in range(n):
+        hs.step(idx, pot, c, t, h, m, dtype=dtype, reorth=reorth, ws=ws, t_dev=tdev, diag=diag)
+        t += h
+    torch.cuda.synchronize()
+    out_lib = c.cpu().numpy()
+    out = np.empty_like(out_lib)
+    out[lexpos] = out_lib
+    return out, diag.cpu().numpy(), (tdev.cpu().numpy() if use_tdev else None)
+
+
+@pytest.mark.parametrize("nsteps", [1, 100])
+def test_small_config_steps(hs, nsteps):
+    """N = 2, B = 64, Henon-Heiles, complex normal start (seed 0), m = 10, h = 0.01."""
+    N, B = 2, 64
+    tt = hh_workload(N)
+    ix = IndexSet(N, B)
+    c0 = complex_normal_by_index(ix.k, 0)
+    ref = oracle_steps(N, B, tt, c0, 0.0, 0.01, nsteps, 10)
+    got, diag, _ = gpu_steps(hs, N, B, tt, c0, 0.0, 0.01, nsteps, 10)
+    assert int(diag[0]) == 10
+    assert rel2(got, ref) <= (1e-12 if nsteps == 1 else 1e-10)
+    # norm conservation
+    assert abs(np.linalg.norm(got) - np.linalg.norm(c0)) <= 1e-12 * nsteps * np.linalg.norm(c0)
+
+
+def test_time_dependent_laser_steps(hs):
+    N, B = 3, 300
+    tt = hh_workload(N, 0.111, 0.05)
+    ix = IndexSet(N, B)
+    c0 = coherent_state(ix.k, [1.0, 0.5, -0.5])
+    c0 /= np.linalg.norm(c0)
+    ref = oracle_steps(N, B, tt, c0, 0.1, 0.005, 5, 10)
+    got, _, tdev = gpu_steps(hs, N, B, tt, c0, 0.1, 0.005, 5, 10, use_tdev=True)
+    assert rel2(got, ref) <= 1e-12
+    assert tdev[0] == pytest.approx(0.1 + 5 * 0.005, abs=1e-15)
+
+
+def test_no_reorth_variant(hs):
+    N, B = 2, 200
+    tt = hh_workload(N)
+    ix = IndexSet(N, B)
+    c0 = complex_normal_by_index(ix.k, 5)
+    ref = oracle_steps(N, B, tt, c0, 0.0, 0.01, 3, 8, reorth=False)
+    got, _, _ = gpu_steps(hs, N, B, tt, c0, 0.0, 0.01, 3, 8, reorth=False)
+    assert rel2(got, ref) <= 1e-12
+
+
+def test_breakdown_on_eigenvector(hs):
+    """W = 0 and c = e_0: beta_1 = 0, the step stops at m_eff = 1 and is exact."""
+    import torch
+    N, B = 3, 50
+    tt = [x for x in hh_workload(N, 0.0) if sum(x.degrees) == 2]
+    idx = hs.Index(N, B)
+    k = idx.multi_indices()
+    c_lib = np.zeros(idx.size, dtype=np.complex128)
+    c_lib[np.nonzero(k.sum(axis=1) == 0)[0][0]] = 1.0
+    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    c = torch.from_numpy(c_lib).to("cuda")
+    diag = torch.zeros(21, dtype=torch.float64, device="cuda")
+    hs.step(idx, pot, c, 0.0, 0.1, 10, diag=diag)
+    torch.cuda.synchronize()
+    out = c.cpu().numpy()
+    assert int(diag[0].item()) == 1
+    assert np.allclose(out, c_lib * np.exp(-0.15j), atol=1e-15)
+
+
+def test_float32_krylov_error_stated(hs):
+    N, B = 3, 400
+    tt = hh_workload(N, 0.111, 0.05)
+    ix = IndexSet(N, B)
+    c0 = complex_normal_by_index(ix.k, 9)
+    ref = oracle_steps(N, B, tt, c0, 0.0, 0.005, 10, 10)
+    got, _, _ = gpu_steps(hs, N, B, tt, c0, 0.0, 0.005, 10, 10, dtype=1)
+    err = rel2(got, ref)
+    print(f"float32 Krylov form, 10 steps: relative error vs float64 oracle {err:.3e}")
+    assert err < 1e-4
