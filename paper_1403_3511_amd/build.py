@@ -1,5 +1,6 @@
 """Build the HIP library libhs.so for gfx950 in-tree (hipcc, no JIT cache).
 
+Each source is compiled to an object in parallel, then linked.  Every call rebuilds.
 Usage: python -m paper_1403_3511_amd.build  (or call build()).
 """
 from __future__ import annotations
@@ -7,30 +8,62 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhs.so")
-SOURCES = ["api.cpp", "index.cpp", "potential.cpp", "matvec.hip", "lanczos.hip", "batch.hip",
-           "surrogate.hip"]
-FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-fno-gpu-rdc", "-Wall", "-Wno-unused-function"]
+SOURCES = ["api.cpp", "index.cpp", "potential.cpp", "matvec.hip", "matvec_long_f64.hip",
+           "matvec_long_f32.hip", "lanczos.hip", "batch.hip", "surrogate.hip"]
+CFLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-fno-gpu-rdc", "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = OUT + ".tmp"
-    cmd = [hipcc, *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _hipcc():
+    return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def _compile(src: str, obj: str, defines=()) -> tuple[str, int, str]:
+    cmd = [_hipcc(), *CFLAGS, *["-D" + d for d in defines], "-I", os.path.join(HERE, "..", "include"), "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libhs.so")
-    os.replace(tmp, OUT)
-    return OUT
+    msg = "\n".join(line for line in (res.stdout + res.stderr).splitlines()
+                    if "packed-fp32-ops" not in line and "not a recognized feature" not in line)
+    return src, res.returncode, msg
+
+
+def build(verbose: bool = False, out: str | None = None, defines=()) -> str:
+    with tempfile.TemporaryDirectory(prefix="hs_build_") as tmp:
+        jobs = [(os.path.join(CSRC, s), os.path.join(tmp, s + ".o")) for s in SOURCES]
+        workers = min(len(jobs), max(1, (os.cpu_count() or 4)))
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            results = list(ex.map(lambda j: _compile(*j, defines), jobs))
+        bad = [(s, m) for s, rc, m in results if rc != 0]
+        for s, rc, m in results:
+            if verbose and m.strip():
+                print(m)
+        if bad:
+            for s, m in bad:
+                sys.stderr.write(f"--- {s}\n{m}\n")
+            raise RuntimeError("hipcc failed building libhs.so")
+        tmp_out = os.path.join(tmp, "libhs.so")
+        cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp_out,
+               *[o for _, o in jobs]]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("link of libhs.so failed")
+        _copy(tmp_out, out or OUT)
+    return out or OUT
+
+
+def _copy(src, dst):
+    import shutil
+    tmpdst = dst + ".tmp"
+    shutil.copyfile(src, tmpdst)
+    os.chmod(tmpdst, 0o755)
+    os.replace(tmpdst, dst)
 
 
 if __name__ == "__main__":

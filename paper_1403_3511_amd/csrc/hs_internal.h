@@ -41,7 +41,40 @@ struct IndexDev {
   const int32_t *rowtile;    // [size] tile of each row
   const double *wtab;        // [B + 8] sqrt(k / 2)
   const float *wtabf;        // [B + 8] sqrt(k / 2) in float32
+  // suffix stencil: gst[slot * ng + o] = graded offset of s(o) + displacement(slot), or -1
+  int32_t ns;                // number of stencil slots = 6 d + 8 (d - 1)
+  const int32_t *gst;
+  // work lists of the fused kernel
+  int64_t nchunks;           // 64-row chunks of the long tiles: (record, first offset)
+  const int32_t *chunks;     // [nchunks][2]
+  int32_t rstride;           // int32 per long-tile record
+  const int32_t *recs;       // long-tile records (layout: see rec_* below)
+  const int32_t *tile_rec;   // [ntiles] record of every tile, or NULL (long tiles only)
+  int64_t nsmall;            // rows of the short tiles
+  const int32_t *small_rows; // [nsmall]
 };
+
+// suffix stencil slots: axis a (0-based inside the suffix), step s in {-3..-1, 1..3}
+__host__ __device__ inline int gst_axis_slot(int a, int s) { return a * 6 + (s < 0 ? s + 3 : s + 2); }
+// pair (a, a+1): step s in {-2, -1, 1, 2} along a and r in {-1, 1} along a+1
+__host__ __device__ inline int gst_pair_slot(int d, int a, int s, int r) {
+  const int si = s < 0 ? s + 2 : s + 1;
+  return 6 * d + a * 8 + si * 2 + (r > 0 ? 1 : 0);
+}
+// Long-tile record (int32): [0] first row, [1] length, [2] sum of prefix coordinates,
+// [3] tile id, [4 .. 4+np) prefix coordinates, then (first row, length) pairs of the
+// neighbour tiles the two-axis stencil reaches: for each prefix axis l the tiles
+// p + s e_l, s in {-3,-2,-1,1,2,3}; for each prefix pair (l, l+1) the tiles
+// p + s e_l + r e_{l+1}, s in {-2..2}, r in {-1,1}.  Absent tiles have length 0.
+__host__ __device__ constexpr int rec_stride(int np) { return 4 + np + 2 * (6 * np + 10 * (np > 1 ? np - 1 : 0)); }
+__host__ __device__ constexpr int rec_axis(int np, int l, int s) {
+  return 4 + np + 2 * (l * 6 + (s < 0 ? s + 3 : s + 2));
+}
+__host__ __device__ constexpr int rec_pair(int np, int l, int s, int r) {
+  return 4 + np + 2 * (6 * np + l * 10 + (s + 2) * 2 + (r > 0 ? 1 : 0));
+}
+constexpr int kChunk = 64;       // rows per wave in the long-tile kernel
+constexpr int kLongTile = 32;    // tiles at least this long go to the long-tile kernel
 
 }  // namespace hs
 
@@ -54,10 +87,15 @@ struct hs_index_s {
   std::vector<uint16_t> gsidx;
   std::vector<int32_t> gnbr, gssum;
   std::vector<int32_t> rowtile;
+  std::vector<int32_t> gst, chunks, small_rows, recs, tile_rec;
+  int32_t ns = 0, rstride = 0;
+  bool recs_all = false;
+  int64_t nchunks = 0, nsmall = 0;
   // device blob layout (byte offsets)
   int64_t off_tstart = 0, off_tlen = 0, off_tnbr = 0, off_tpfx = 0, off_tpsum = 0,
           off_gsidx = 0, off_gnbr = 0, off_gssum = 0, off_rowtile = 0, off_wtab = 0,
-          off_wtabf = 0, dev_bytes = 0;
+          off_wtabf = 0, off_gst = 0, off_chunks = 0, off_small = 0, off_recs = 0, off_tile_rec = 0,
+          dev_bytes = 0;
   std::vector<uint8_t> blob;   // host image of the device block
   void *pinned = nullptr;      // pinned staging for the upload
   hs::IndexDev view(const void *dev) const;
@@ -94,6 +132,7 @@ struct hs_pot_s {
   std::vector<uint16_t> deg;          // nterms x N
   std::vector<double> base, amp, freq, phase;
   bool fused = false;
+  bool x2 = false;                    // fused form uses x_l^2 or x_l x_{l+1} monomials
   // fused: compiled monomial coefficient of each HH slot = sum_t M[slot][t] beta_t
   int32_t nslots = 0;
   std::vector<double> M;              // nslots x nterms

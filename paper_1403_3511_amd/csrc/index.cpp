@@ -156,10 +156,19 @@ hs::IndexDev hs_index_s::view(const void *dev) const {
   v.rowtile = reinterpret_cast<const int32_t *>(b + off_rowtile);
   v.wtab = reinterpret_cast<const double *>(b + off_wtab);
   v.wtabf = reinterpret_cast<const float *>(b + off_wtabf);
+  v.ns = ns;
+  v.gst = reinterpret_cast<const int32_t *>(b + off_gst);
+  v.nchunks = nchunks;
+  v.chunks = reinterpret_cast<const int32_t *>(b + off_chunks);
+  v.nsmall = nsmall;
+  v.small_rows = reinterpret_cast<const int32_t *>(b + off_small);
+  v.rstride = rstride;
+  v.recs = reinterpret_cast<const int32_t *>(b + off_recs);
+  v.tile_rec = recs_all ? reinterpret_cast<const int32_t *>(b + off_tile_rec) : nullptr;
   return v;
 }
 
-static int32_t default_tile_dim(int32_t N) { return N <= 2 ? N : (N <= 4 ? 2 : 3); }
+static int32_t default_tile_dim(int32_t N) { return N <= 2 ? N : (N <= 4 ? 2 : (N <= 8 ? 3 : 4)); }
 
 static int32_t build_index(hs_index_s *ix) {
   const int N = ix->N, d = ix->d, np = ix->np;
@@ -265,6 +274,80 @@ static int32_t build_index(hs_index_s *ix) {
   for (int64_t t = 0; t < ntiles; ++t)
     for (int64_t r = ix->tstart[t]; r < ix->tstart[t + 1]; ++r) ix->rowtile[r] = (int32_t)t;
 
+  // ---- suffix stencil (displacements used by the fused two-axis kernel) ----
+  ix->ns = 6 * d + 8 * (d - 1);
+  ix->gst.assign((size_t)ix->ns * ng, -1);
+  if (d > 0) {
+    LexRank R(&C, d, B);
+    std::vector<int32_t> k(d);
+    auto lookup = [&](int64_t g, int a, int s, int b, int r) -> int32_t {
+      for (int i = 0; i < d; ++i) k[i] = ix->gsidx[g * d + i];
+      k[a] += s;
+      if (b >= 0) k[b] += r;
+      if (!member(k.data(), d, B)) return -1;
+      return (int32_t)gpos_of_lex[R.rank(k.data())];
+    };
+    for (int64_t g = 0; g < ng; ++g) {
+      for (int a = 0; a < d; ++a)
+        for (int s = -3; s <= 3; ++s)
+          if (s != 0) ix->gst[(size_t)hs::gst_axis_slot(a, s) * ng + g] = lookup(g, a, s, -1, 0);
+      for (int a = 0; a + 1 < d; ++a)
+        for (int s : {-2, -1, 1, 2})
+          for (int r : {-1, 1}) ix->gst[(size_t)hs::gst_pair_slot(d, a, s, r) * ng + g] = lookup(g, a, s, a + 1, r);
+    }
+  }
+  // ---- work lists: 64-row chunks of long tiles, rows of short tiles ----
+  ix->chunks.clear();
+  ix->small_rows.clear();
+  ix->recs.clear();
+  ix->rstride = hs::rec_stride(np);
+  auto walk = [&](int64_t t, int l, int s) -> int64_t {  // tile p + s e_l or -1
+    for (int k = 0; k < (s < 0 ? -s : s) && t >= 0; ++k) t = ix->tnbr[t * 2 * np + 2 * l + (s > 0)];
+    return t;
+  };
+  // records for every tile when they are cheap next to one vector (then the short tiles
+  // use them too), else for the long tiles only
+  const int64_t nlong = std::count_if(ix->tlen.begin(), ix->tlen.end(), [](int32_t l) { return l >= hs::kLongTile; });
+  ix->recs_all = (int64_t)ix->rstride * 4 * ntiles <= std::max<int64_t>(total * 8, INT64_C(64) << 20);
+  ix->recs.reserve((size_t)ix->rstride * (ix->recs_all ? ntiles : nlong));
+  ix->tile_rec.assign(ix->recs_all ? ntiles : 0, -1);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int32_t len = ix->tlen[t];
+    if (len >= hs::kLongTile || ix->recs_all) {
+      const int32_t ri = (int32_t)(ix->recs.size() / ix->rstride);
+      if (ix->recs_all) ix->tile_rec[t] = ri;
+      ix->recs.resize(ix->recs.size() + ix->rstride, 0);
+      int32_t *rec = ix->recs.data() + (size_t)ri * ix->rstride;
+      rec[0] = (int32_t)ix->tstart[t];
+      rec[1] = len;
+      rec[2] = ix->tpsum[t];
+      rec[3] = (int32_t)t;
+      for (int i = 0; i < np; ++i) rec[4 + i] = ix->tpfx[t * np + i];
+      auto put = [&](int pos, int64_t tt) {
+        rec[pos] = tt >= 0 ? (int32_t)ix->tstart[tt] : 0;
+        rec[pos + 1] = tt >= 0 ? ix->tlen[tt] : 0;
+      };
+      for (int l = 0; l < np; ++l)
+        for (int s : {-3, -2, -1, 1, 2, 3}) put(hs::rec_axis(np, l, s), walk(t, l, s));
+      for (int l = 0; l + 1 < np; ++l)
+        for (int s = -2; s <= 2; ++s)
+          for (int r : {-1, 1}) {
+            int64_t tt = walk(t, l, s);
+            put(hs::rec_pair(np, l, s, r), tt >= 0 ? walk(tt, l + 1, r) : -1);
+          }
+      if (len >= hs::kLongTile)
+        for (int32_t o = 0; o < len; o += hs::kChunk) {
+          ix->chunks.push_back(ri);
+          ix->chunks.push_back(o);
+        }
+    }
+    if (len < hs::kLongTile) {
+      for (int32_t o = 0; o < len; ++o) ix->small_rows.push_back((int32_t)(ix->tstart[t] + o));
+    }
+  }
+  ix->nchunks = (int64_t)ix->chunks.size() / 2;
+  ix->nsmall = (int64_t)ix->small_rows.size();
+
   // ---- device image ----
   int64_t off = 0;
   auto take = [&](int64_t bytes) {
@@ -283,6 +366,11 @@ static int32_t build_index(hs_index_s *ix) {
   ix->off_rowtile = take(total * 4);
   ix->off_wtab = take((B + 8) * 8);
   ix->off_wtabf = take((B + 8) * 4);
+  ix->off_gst = take((int64_t)ix->ns * ng * 4);
+  ix->off_chunks = take(ix->nchunks * 8);
+  ix->off_small = take(ix->nsmall * 4);
+  ix->off_recs = take((int64_t)ix->recs.size() * 4);
+  ix->off_tile_rec = take((int64_t)ix->tile_rec.size() * 4);
   ix->dev_bytes = off;
   ix->blob.assign(off, 0);
   auto put = [&](int64_t o, const void *src, int64_t bytes) {
@@ -305,6 +393,11 @@ static int32_t build_index(hs_index_s *ix) {
   }
   put(ix->off_wtab, w.data(), (B + 8) * 8);
   put(ix->off_wtabf, wf.data(), (B + 8) * 4);
+  put(ix->off_gst, ix->gst.data(), (int64_t)ix->ns * ng * 4);
+  put(ix->off_chunks, ix->chunks.data(), ix->nchunks * 8);
+  put(ix->off_small, ix->small_rows.data(), ix->nsmall * 4);
+  put(ix->off_recs, ix->recs.data(), (int64_t)ix->recs.size() * 4);
+  put(ix->off_tile_rec, ix->tile_rec.data(), (int64_t)ix->tile_rec.size() * 4);
   return HS_OK;
 }
 

@@ -231,61 +231,93 @@ k_scale_next(int64_t n, const typename CT<T>::t *__restrict__ W, typename CT<T>:
   vn[i] = o;
 }
 
-// T = Q Lambda Q^T by cyclic Jacobi (one thread, m <= 32), y = beta0 Q e^{-i h Lambda} Q^T e1
-__global__ void k_small_expm(double h, double *__restrict__ sc) {
-  __shared__ double A[kMaxM][kMaxM], Q[kMaxM][kMaxM];
-  if (threadIdx.x != 0) return;
+// y = beta0 exp(-i h T) e1 for the real symmetric tridiagonal T (m <= 32) by scaling
+// and squaring: delta = h / 2^q with h ||T||_inf / 2^q <= 1/2, an 18-term Taylor
+// polynomial of exp(-i delta T) (truncation below 1e-22), then q squarings.  One
+// workgroup, one thread per matrix element.
+__global__ void __launch_bounds__(1024) k_small_expm(double h, double *__restrict__ sc) {
+  __shared__ double2 E[kMaxM][kMaxM + 1], P[kMaxM][kMaxM + 1];
+  __shared__ double td[kMaxM], to[kMaxM];
+  __shared__ double s_delta;
+  __shared__ int s_q;
   const int m = (int)sc[Scal::meff];
   if (m <= 0) return;
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) {
-      A[i][j] = 0.0;
-      Q[i][j] = (i == j) ? 1.0 : 0.0;
-    }
-  for (int i = 0; i < m; ++i) A[i][i] = sc[Scal::alpha + i];
-  for (int i = 0; i + 1 < m; ++i) A[i][i + 1] = A[i + 1][i] = sc[Scal::beta + i];
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int i = 0; i < m; ++i) {
-      dia += A[i][i] * A[i][i];
-      for (int j = i + 1; j < m; ++j) off += A[i][j] * A[i][j];
-    }
-    if (off <= 1e-34 * dia || off == 0.0) break;
-    for (int p = 0; p < m; ++p)
-      for (int q = p + 1; q < m; ++q) {
-        const double apq = A[p][q];
-        if (apq == 0.0) continue;
-        const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
-        const double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double c = 1.0 / sqrt(tt * tt + 1.0), s = tt * c;
-        for (int r = 0; r < m; ++r) {
-          const double arp = A[r][p], arq = A[r][q];
-          A[r][p] = c * arp - s * arq;
-          A[r][q] = s * arp + c * arq;
-        }
-        for (int r = 0; r < m; ++r) {
-          const double apr = A[p][r], aqr = A[q][r];
-          A[p][r] = c * apr - s * aqr;
-          A[q][r] = s * apr + c * aqr;
-        }
-        for (int r = 0; r < m; ++r) {
-          const double qrp = Q[r][p], qrq = Q[r][q];
-          Q[r][p] = c * qrp - s * qrq;
-          Q[r][q] = s * qrp + c * qrq;
-        }
-      }
+  const int tid = threadIdx.x;
+  const int i = tid / kMaxM, j = tid % kMaxM;
+  const bool act = (i < m) && (j < m);
+  if (tid < m) {
+    td[tid] = sc[Scal::alpha + tid];
+    to[tid] = (tid + 1 < m) ? sc[Scal::beta + tid] : 0.0;
   }
-  const double b0 = sc[Scal::beta0];
-  for (int k = 0; k < m; ++k) {
-    double yr = 0.0, yi = 0.0;
-    for (int j = 0; j < m; ++j) {
-      const double ph = -h * A[j][j];
-      const double w = Q[k][j] * Q[0][j];
-      yr += w * cos(ph);
-      yi += w * sin(ph);
+  __syncthreads();
+  if (tid == 0) {
+    double nrm = 0.0;
+    for (int r = 0; r < m; ++r) {
+      double row = fabs(td[r]) + fabs(to[r]);
+      if (r > 0) row += fabs(to[r - 1]);
+      nrm = fmax(nrm, row);
     }
-    sc[Scal::yre + k] = b0 * yr;
-    sc[Scal::yim + k] = b0 * yi;
+    double rho = fabs(h) * nrm;
+    int q = 0;
+    while (rho > 0.5 && q < 60) {
+      rho *= 0.5;
+      ++q;
+    }
+    s_q = q;
+    s_delta = ldexp(h, -q);
+  }
+  __syncthreads();
+  const double delta = s_delta;
+  const int q = s_q;
+  if (act) {
+    const double2 d = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    E[i][j] = d;
+    P[i][j] = d;
+  }
+  __syncthreads();
+  for (int k = 1; k <= 18; ++k) {
+    // P <- P (-i delta T) / k, T tridiagonal
+    double2 nv = make_double2(0.0, 0.0);
+    if (act) {
+      double sr = P[i][j].x * td[j], si = P[i][j].y * td[j];
+      if (j > 0) {
+        sr += P[i][j - 1].x * to[j - 1];
+        si += P[i][j - 1].y * to[j - 1];
+      }
+      if (j + 1 < m) {
+        sr += P[i][j + 1].x * to[j];
+        si += P[i][j + 1].y * to[j];
+      }
+      const double f = delta / k;
+      nv = make_double2(si * f, -sr * f);  // (-i f) (sr + i si)
+    }
+    __syncthreads();
+    if (act) {
+      P[i][j] = nv;
+      E[i][j].x += nv.x;
+      E[i][j].y += nv.y;
+    }
+    __syncthreads();
+  }
+  for (int r = 0; r < q; ++r) {
+    double2 nv = make_double2(0.0, 0.0);
+    if (act) {
+      double ar = 0.0, ai = 0.0;
+      for (int l = 0; l < m; ++l) {
+        const double2 a = E[i][l], b = E[l][j];
+        ar = fma(a.x, b.x, fma(-a.y, b.y, ar));
+        ai = fma(a.x, b.y, fma(a.y, b.x, ai));
+      }
+      nv = make_double2(ar, ai);
+    }
+    __syncthreads();
+    if (act) E[i][j] = nv;
+    __syncthreads();
+  }
+  if (act && j == 0) {
+    const double b0 = sc[Scal::beta0];
+    sc[Scal::yre + i] = b0 * E[i][0].x;
+    sc[Scal::yim + i] = b0 * E[i][0].y;
   }
 }
 
@@ -398,7 +430,7 @@ static int32_t step_impl(const hs_index_s *idx, const void *idx_dev, const hs_po
       hipLaunchKernelGGL(k_scale_next<T>, dim3(g), dim3(256), 0, s, n, (const C *)W,
                          V + (int64_t)(k + 1) * sv, k, (const double *)sc);
   }
-  hipLaunchKernelGGL(k_small_expm, dim3(1), dim3(64), 0, s, h, sc);
+  hipLaunchKernelGGL(k_small_expm, dim3(1), dim3(1024), 0, s, h, sc);
   hipLaunchKernelGGL(k_combine<T>, dim3(g), dim3(256), 0, s, n, (const C *)V, sv, m, c,
                      (const double *)sc);
   hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, s, t_dev, h, (const double *)sc, diag, m);

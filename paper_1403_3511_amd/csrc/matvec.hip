@@ -13,33 +13,18 @@
 //    over the whole vector, following the program compiled from the term trie.
 //
 // No MFMA: the operator is a sparse stencil, not a dense contraction.
-#include "hs_internal.h"
+#include "dev_common.h"
 
 namespace hs {
 
-template <typename T> struct V2;
-template <> struct V2<double> { using t = double2; };
-template <> struct V2<float> { using t = float2; };
-
-template <typename T>
-__device__ __forceinline__ typename V2<T>::t vz() {
-  typename V2<T>::t r;
-  r.x = T(0);
-  r.y = T(0);
-  return r;
-}
-template <typename T, typename U>
-__device__ __forceinline__ void fma_rc(typename V2<T>::t &acc, U w, const typename V2<T>::t &x) {
-  acc.x = fma((T)w, x.x, acc.x);
-  acc.y = fma((T)w, x.y, acc.y);
-}
-template <typename T>
-__device__ __forceinline__ typename V2<T>::t scal(T w, const typename V2<T>::t &x) {
-  typename V2<T>::t r;
-  r.x = w * x.x;
-  r.y = w * x.y;
-  return r;
-}
+// specialised fused kernels (compile-time N and prefix axes): 1 = long and short tiles
+// launched, 2 = long tiles only, 0 = no specialisation for this (N, NP)
+int launch_hh_long_f64(const IndexDev &ix, const double *hh, const void *x, void *y,
+                       const double *out_scale, const void *prev, const double *prev_coef,
+                       const double *prev_scale, hipStream_t s, bool x2);
+int launch_hh_long_f32(const IndexDev &ix, const double *hh, const void *x, void *y,
+                       const double *out_scale, const void *prev, const double *prev_coef,
+                       const double *prev_scale, hipStream_t s, bool x2);
 
 struct Pos {
   int32_t t, o;
@@ -110,10 +95,11 @@ __global__ void __launch_bounds__(256)
 k_hh_rows(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *__restrict__ x,
           typename V2<T>::t *__restrict__ y, const double *__restrict__ out_scale,
           const typename V2<T>::t *__restrict__ prev, const double *__restrict__ prev_coef,
-          const double *__restrict__ prev_scale) {
+          const double *__restrict__ prev_scale, const int32_t *__restrict__ rows, int64_t nrows) {
   using C = typename V2<T>::t;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= ix.size) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int64_t r = rows ? (int64_t)rows[i] : i;
   const T *wt;
   if constexpr (sizeof(T) == 8) wt = (const T *)ix.wtab; else wt = (const T *)ix.wtabf;
   const int32_t t0 = ix.rowtile[r];
@@ -196,6 +182,166 @@ k_hh_rows(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *_
       h2[q] = h;
     }
     C h1[2];  // s = -1, 1
+    for (int q = 0; q < 2; ++q) {
+      const int s = 2 * q - 1;
+      C h = vz<T>();
+      fma_rc<T>(h, e[s + 2], h2[q]);
+      fma_rc<T>(h, e[s + 3], h2[q + 1]);
+      fma_rc<T>(h, a1, u[3 + s]);
+      fma_rc<T>(h, g1, v[s + 2]);
+      h1[q] = h;
+    }
+    fma_rc<T>(acc, e[2], h1[0]);
+    fma_rc<T>(acc, e[3], h1[1]);
+  }
+  if (out_scale) acc = scal<T>((T)*out_scale, acc);
+  if (prev) {
+    const T pc = (T)(-(*prev_coef) * (prev_scale ? *prev_scale : 1.0));
+    fma_rc<T>(acc, pc, prev[r]);
+  }
+  y[r] = acc;
+}
+
+// ---- long-tile kernel ---------------------------------------------------------------
+// One wave per 64-row chunk of one tile: the tile id is uniform, so every move along a
+// prefix axis is a scalar chain through the tile-neighbour table and the loads of a
+// neighbour tile at the same offsets are contiguous.  Moves along suffix axes read the
+// precomputed suffix stencil of the row's offset (no dependent chains).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_hh_tiles(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *__restrict__ x,
+           typename V2<T>::t *__restrict__ y, const double *__restrict__ out_scale,
+           const typename V2<T>::t *__restrict__ prev, const double *__restrict__ prev_coef,
+           const double *__restrict__ prev_scale) {
+  using C = typename V2<T>::t;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= ix.nchunks) return;
+  const int32_t ri = __builtin_amdgcn_readfirstlane(ix.chunks[2 * wave]);
+  const int32_t t = ix.recs[(int64_t)ri * ix.rstride + 3];
+  const int32_t o0 = __builtin_amdgcn_readfirstlane(ix.chunks[2 * wave + 1]);
+  const int32_t len = ix.tlen[t];
+  const int32_t o = o0 + lane;
+  if (o >= len) return;
+  const T *wt;
+  if constexpr (sizeof(T) == 8) wt = (const T *)ix.wtab; else wt = (const T *)ix.wtabf;
+  const int N = ix.N, np = ix.np, d = ix.d;
+  const int64_t ng = ix.ng;
+  const int64_t base = ix.tstart[t];
+  const int64_t r = base + o;
+  const C c0 = x[r];
+  const double dval = (double)(ix.tpsum[t] + ix.gssum[o]) + 0.5 * N + hh[5 * N];
+  C acc = scal<T>((T)dval, c0);
+
+  for (int l = 0; l < N; ++l) {
+    const T a1 = (T)hh[5 * l + 0], a2 = (T)hh[5 * l + 1], a3 = (T)hh[5 * l + 2];
+    const T g1 = (l + 1 < N) ? (T)hh[5 * l + 3] : T(0);
+    const T g2 = (l + 1 < N) ? (T)hh[5 * l + 4] : T(0);
+    const bool any2 = (a3 != T(0)) || (a2 != T(0)) || (g2 != T(0));
+    if (!any2 && a1 == T(0) && g1 == T(0)) continue;
+    const int smax = (a3 != T(0)) ? 3 : (any2 ? 2 : 1);
+    const bool lp = l < np;
+    // window s = -3..3 along axis l: tile Ts (uniform for a prefix axis) and offset Os
+    int32_t Ts[7], Os[7];
+    bool val[7];
+    int jl;
+    for (int q = 0; q < 7; ++q) {
+      Ts[q] = -1;
+      Os[q] = -1;
+      val[q] = false;
+    }
+    Ts[3] = t;
+    Os[3] = o;
+    val[3] = true;
+    if (lp) {
+      jl = ix.tpfx[(int64_t)t * np + l];
+      int32_t up = t, dn = t;
+      for (int s = 1; s <= 3; ++s) {
+        if (s > smax) break;
+        up = (up >= 0) ? ix.tnbr[(int64_t)up * (2 * np) + 2 * l + 1] : -1;
+        dn = (dn >= 0) ? ix.tnbr[(int64_t)dn * (2 * np) + 2 * l] : -1;
+        Ts[3 + s] = up;
+        Ts[3 - s] = dn;
+        Os[3 + s] = o;
+        Os[3 - s] = o;
+        val[3 + s] = (up >= 0) && (o < ix.tlen[up]);
+        val[3 - s] = (dn >= 0);
+      }
+    } else {
+      const int a = l - np;
+      jl = ix.gsidx[(int64_t)o * d + a];
+      for (int s = 1; s <= 3; ++s) {
+        if (s > smax) break;
+        const int32_t ou = ix.gst[(int64_t)gst_axis_slot(a, s) * ng + o];
+        const int32_t od = ix.gst[(int64_t)gst_axis_slot(a, -s) * ng + o];
+        Ts[3 + s] = t;
+        Ts[3 - s] = t;
+        Os[3 + s] = ou;
+        Os[3 - s] = od;
+        val[3 + s] = (ou >= 0) && (ou < len);
+        val[3 - s] = (od >= 0);
+      }
+    }
+    C u[7];
+    for (int q = 0; q < 7; ++q) u[q] = vz<T>();
+    u[3] = c0;
+    for (int q = 0; q < 7; q += 2)  // s = -3, -1, 1, 3
+      if (val[q]) u[q] = x[ix.tstart[Ts[q]] + Os[q]];
+    if (a2 != T(0))
+      for (int q = 1; q < 7; q += 4)  // s = -2, +2 only needed for the x_l^2 term
+        if (val[q]) u[q] = x[ix.tstart[Ts[q]] + Os[q]];
+    T e[6];  // e[s + 2] = weight of the edge between window positions s-1 and s
+    for (int s = -2; s <= 3; ++s) e[s + 2] = (val[3 + s - 1] && val[3 + s]) ? wt[jl + s] : T(0);
+    // X_{l+1} c on the window (inner axis applied first)
+    C v[5];
+    for (int q = 0; q < 5; ++q) v[q] = vz<T>();
+    if (g1 != T(0) || g2 != T(0)) {
+      const int m = l + 1;
+      const bool mp = m < np;
+      const int jm = mp ? (int)ix.tpfx[(int64_t)t * np + m] : (int)ix.gsidx[(int64_t)o * d + (m - np)];
+      const T wlo = wt[jm], whi = wt[jm + 1];
+      for (int s = -2; s <= 2; ++s) {
+        if ((s & 1) ? (g1 == T(0)) : (g2 == T(0))) continue;
+        if (!val[3 + s]) continue;
+        C vs = vz<T>();
+        for (int r2 = -1; r2 <= 1; r2 += 2) {
+          int32_t tq, oq;
+          bool ok;
+          if (mp) {
+            tq = ix.tnbr[(int64_t)Ts[3 + s] * (2 * np) + 2 * m + (r2 > 0)];
+            oq = o;
+            ok = (tq >= 0) && (r2 < 0 || o < ix.tlen[tq]);
+          } else if (lp) {  // l prefix, m the first suffix axis
+            tq = Ts[3 + s];
+            oq = ix.gst[(int64_t)gst_axis_slot(0, r2) * ng + o];
+            ok = (oq >= 0) && (oq < ix.tlen[tq]);
+          } else {          // both suffix axes
+            const int a = l - np;
+            tq = t;
+            oq = (s == 0) ? ix.gst[(int64_t)gst_axis_slot(a + 1, r2) * ng + o]
+                          : ix.gst[(int64_t)gst_pair_slot(d, a, s, r2) * ng + o];
+            ok = (oq >= 0) && (oq < len);
+          }
+          if (ok) fma_rc<T>(vs, r2 < 0 ? wlo : whi, x[ix.tstart[tq] + oq]);
+        }
+        v[s + 2] = vs;
+      }
+    }
+    C h2[3];
+    for (int q = 0; q < 3; ++q) {
+      const int s = 2 * q - 2;
+      C h = vz<T>();
+      if (any2) {
+        C xu = vz<T>();
+        fma_rc<T>(xu, e[s + 2], u[3 + s - 1]);
+        fma_rc<T>(xu, e[s + 3], u[3 + s + 1]);
+        h = scal<T>(a3, xu);
+        fma_rc<T>(h, a2, u[3 + s]);
+        fma_rc<T>(h, g2, v[s + 2]);
+      }
+      h2[q] = h;
+    }
+    C h1[2];
     for (int q = 0; q < 2; ++q) {
       const int s = 2 * q - 1;
       C h = vz<T>();
@@ -326,8 +472,16 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
   const unsigned g = nblk(idx->size, 256);
   if (idx->size == 0) return HS_OK;
   if (p->fused) {
-    hipLaunchKernelGGL(k_hh_rows<T>, dim3(g), dim3(256), 0, s, ix, hh, (const C *)x, (C *)y,
-                       out_scale, (const C *)prev, prev_coef, prev_scale);
+    const int done = sizeof(T) == 8
+        ? launch_hh_long_f64(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, p->x2)
+        : launch_hh_long_f32(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, p->x2);
+    if (done == 0 && ix.nchunks > 0)
+      hipLaunchKernelGGL(k_hh_tiles<T>, dim3(nblk(ix.nchunks * kChunk, 256)), dim3(256), 0, s, ix, hh,
+                         (const C *)x, (C *)y, out_scale, (const C *)prev, prev_coef, prev_scale);
+    if (done != 1 && ix.nsmall > 0)
+      hipLaunchKernelGGL(k_hh_rows<T>, dim3(nblk(ix.nsmall, 256)), dim3(256), 0, s, ix, hh,
+                         (const C *)x, (C *)y, out_scale, (const C *)prev, prev_coef, prev_scale,
+                         ix.small_rows, ix.nsmall);
     HS_HIP(hipGetLastError());
     return HS_OK;
   }

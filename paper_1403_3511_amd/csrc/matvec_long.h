@@ -1,0 +1,306 @@
+// Fused two-axis H application specialised at compile time on the dimension N and the
+// number of prefix axes NP (paper Sec. 3.2, eq. Horner, for the potential class
+// a1 x_l + a2 x_l^2 + a3 x_l^3 + g1 x_l x_{l+1} + g2 x_l^2 x_{l+1}).
+//
+// Long tiles: one wave handles 64 consecutive rows (offsets o0..o0+63) of one tile.  The
+// tile's record gives, in one scalar fetch, the first row and length of every neighbour
+// tile that the stencil reaches along the prefix axes; there the neighbour of a row is
+// the same offset, so those loads are contiguous across the wave.  Neighbours along
+// suffix axes come from the per-offset suffix stencil.  Short tiles (PACKED): one lane
+// per listed row, the same code with the record fetched per lane.
+//
+// X2 = false drops the x_l^2 and x_l x_{l+1} monomials (absent in the Henon-Heiles
+// class) at compile time.
+#pragma once
+
+#include "dev_common.h"
+
+namespace hs {
+
+// Complex loads through a raw buffer resource with 32-bit element offsets: an absent
+// neighbour gets an offset beyond the buffer, for which the hardware returns zero, so
+// no predication or select is needed and no 64-bit address arithmetic is done.
+constexpr uint32_t kAbsent = 0x0FFFFFFFu;  // element offset that is always out of range
+
+template <typename T> struct BufLoad;
+template <> struct BufLoad<double> {
+  static __device__ __forceinline__ double2 ld(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(i << 4), 0, 0);
+    double2 d;
+    __builtin_memcpy(&d, &v, 16);
+    return d;
+  }
+};
+template <> struct BufLoad<float> {
+  static __device__ __forceinline__ float2 ld(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(i << 3), 0, 0);
+    float2 d;
+    __builtin_memcpy(&d, &v, 8);
+    return d;
+  }
+};
+
+// One group per axis l, skipped as a whole when its coefficients vanish (uniform
+// branch).  Coefficients are folded into the edge weights: with u_s = c(j + s e_l) and
+// v_s = (X_{l+1} c)(j + s e_l),
+//   h2_s = a3 (e_s u_{s-1} + e_{s+1} u_{s+1}) + a2 u_s + g2 v_s      (s = -2, 0, 2)
+//   h1_s = e_s h2_{s-1} + e_{s+1} h2_{s+1} + a1 u_s + g1 v_s          (s = -1, 1)
+//   G_l  = e_0 h1_{-1} + e_1 h1_1.
+template <typename T, int N, int NP, bool PACKED, bool X2>
+__global__ void __launch_bounds__(256)
+k_hh_long(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *__restrict__ x,
+          typename V2<T>::t *__restrict__ y, const double *__restrict__ out_scale,
+          const typename V2<T>::t *__restrict__ prev, const double *__restrict__ prev_coef,
+          const double *__restrict__ prev_scale) {
+  using C = typename V2<T>::t;
+  constexpr int D = N - NP;
+  constexpr int RS = rec_stride(NP);
+  // XCD-aware order: block b runs on XCD b % kXcd, so give XCD x the contiguous range
+  // [x * per, (x + 1) * per) of the tile-ordered work list; tiles and their neighbours
+  // then share one L2
+  const int64_t per = gridDim.x / kXcd;
+  const int64_t blk = (int64_t)(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
+  const int32_t *__restrict__ rec;
+  int32_t o;
+  if constexpr (!PACKED) {
+    const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
+    if (wave >= ix.nchunks) return;
+    const int32_t ri = __builtin_amdgcn_readfirstlane(ix.chunks[2 * wave]);
+    const int32_t o0 = __builtin_amdgcn_readfirstlane(ix.chunks[2 * wave + 1]);
+    rec = ix.recs + (int64_t)ri * RS;
+    o = o0 + (int32_t)(threadIdx.x & 63);
+    if (o >= rec[1]) return;
+  } else {
+    const int64_t i = blk * blockDim.x + threadIdx.x;
+    if (i >= ix.nsmall) return;
+    const int32_t r = ix.small_rows[i];
+    rec = ix.recs + (int64_t)ix.tile_rec[ix.rowtile[r]] * RS;
+    o = r - rec[0];
+  }
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)x, (short)0, (int)(ix.size * (int64_t)sizeof(C)), 0x00020000);
+  const uint32_t base = (uint32_t)rec[0];
+  const int32_t len = rec[1];
+  const T *__restrict__ wt;
+  if constexpr (sizeof(T) == 8) wt = (const T *)ix.wtab; else wt = (const T *)ix.wtabf;
+  const int64_t ng = ix.ng;
+  const int32_t *__restrict__ gst = ix.gst;
+  int sc[D];
+  static_for<0, D>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    sc[a] = ix.gsidx[(int64_t)o * D + a];
+  });
+  const uint32_t self = base + (uint32_t)o;
+  const C c0 = x[self];
+  const double dval = (double)(rec[2] + ix.gssum[o]) + 0.5 * N + hh[5 * N];
+  C acc = scal<T>((T)dval, c0);
+
+  static_for<0, N>([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    constexpr bool inner = (l + 1 < N);
+    const T a1 = (T)hh[5 * l + 0], a3 = (T)hh[5 * l + 2];
+    const T a2 = X2 ? (T)hh[5 * l + 1] : T(0);
+    const T g1 = (X2 && inner) ? (T)hh[5 * l + 3] : T(0);
+    const T g2 = inner ? (T)hh[5 * l + 4] : T(0);
+    const bool any2 = (a3 != T(0)) || (a2 != T(0)) || (g2 != T(0));
+    const bool need3 = (a3 != T(0));
+    if (!any2 && a1 == T(0) && g1 == T(0)) return;  // uniform: group absent
+    // ---- window j + s e_l, s = -3..3: element offset (kAbsent if outside K) ----
+    uint32_t id[7];
+    bool val[7];
+    int32_t stw[7], lnw[7];
+    int jl;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      id[q] = kAbsent;
+      val[q] = false;
+      stw[q] = (int32_t)base;
+      lnw[q] = len;
+    }
+    id[3] = self;
+    val[3] = true;
+    if constexpr (l < NP) {
+      jl = rec[4 + l];
+#pragma unroll
+      for (int s = -3; s <= 3; ++s) {
+        if (s == 0) continue;
+        const int p = rec_axis(NP, l, s);
+        const int32_t st = rec[p], ln = rec[p + 1];
+        stw[3 + s] = st;
+        lnw[3 + s] = ln;
+        val[3 + s] = o < ln;
+        id[3 + s] = val[3 + s] ? (uint32_t)(st + o) : kAbsent;
+      }
+    } else {
+      constexpr int a = l - NP;
+      jl = sc[a];
+#pragma unroll
+      for (int s = 1; s <= 3; ++s) {
+        if (s == 2 && !any2) continue;
+        if (s == 3 && !need3) continue;
+        const int32_t ou = gst[(int64_t)gst_axis_slot(a, s) * ng + o];
+        const int32_t od = gst[(int64_t)gst_axis_slot(a, -s) * ng + o];
+        val[3 + s] = (uint32_t)ou < (uint32_t)len;
+        val[3 - s] = od >= 0;
+        id[3 + s] = val[3 + s] ? base + (uint32_t)ou : kAbsent;
+        id[3 - s] = val[3 - s] ? base + (uint32_t)od : kAbsent;
+      }
+    }
+    if (!any2) val[1] = val[5] = false;
+    if (!need3) val[0] = val[6] = false;
+    // edge weights e_s (edge between s-1 and s), a3 folded in for the innermost level
+    T e[6], ea3[6];
+#pragma unroll
+    for (int s = -2; s <= 3; ++s) {
+      const int k = jl + s;
+      const T w = (val[3 + s - 1] && val[3 + s]) ? wt[k > 0 ? k : 0] : T(0);
+      e[s + 2] = w;
+      ea3[s + 2] = w * a3;
+    }
+    C u[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) u[q] = vz<T>();
+    u[3] = c0;
+    u[2] = BufLoad<T>::ld(xr, id[2]);
+    u[4] = BufLoad<T>::ld(xr, id[4]);
+    if (need3) {
+      u[0] = BufLoad<T>::ld(xr, id[0]);
+      u[6] = BufLoad<T>::ld(xr, id[6]);
+    }
+    if constexpr (X2) {
+      if (a2 != T(0)) {
+        u[1] = BufLoad<T>::ld(xr, id[1]);
+        u[5] = BufLoad<T>::ld(xr, id[5]);
+      }
+    }
+    // ---- h2 at s = -2, 0, 2 ----
+    C h2[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int s = 2 * q - 2;
+      C h = vz<T>();
+      fma_rc<T>(h, ea3[s + 2], u[3 + s - 1]);
+      fma_rc<T>(h, ea3[s + 3], u[3 + s + 1]);
+      if constexpr (X2) fma_rc<T>(h, a2, u[3 + s]);
+      h2[q] = h;
+    }
+    // inner axis: g2 (X_{l+1} c) at s = -2, 0, 2 into h2; g1 at s = -1, 1 into h1
+    C v1[2] = {vz<T>(), vz<T>()};
+    if constexpr (inner) {
+      if (g1 != T(0) || g2 != T(0)) {
+        constexpr int m = l + 1;
+        int jm;
+        if constexpr (m < NP) jm = rec[4 + m]; else jm = sc[m - NP];
+        const T wlo = wt[jm], whi = wt[jm + 1];
+        int32_t o_lo = -1, o_hi = -1;
+        if constexpr (m == NP) {  // l prefix, l+1 the first suffix axis
+          o_lo = gst[(int64_t)gst_axis_slot(0, -1) * ng + o];
+          o_hi = gst[(int64_t)gst_axis_slot(0, 1) * ng + o];
+        }
+#pragma unroll
+        for (int s = -2; s <= 2; ++s) {
+          if (!X2 && (s & 1)) continue;
+          const T gs = (s & 1) ? g1 : g2;
+          if (gs == T(0)) continue;
+          C vs = vz<T>();
+#pragma unroll
+          for (int r = -1; r <= 1; r += 2) {
+            uint32_t vid;
+            if constexpr (m < NP) {
+              const int p = rec_pair(NP, l, s, r);
+              vid = (val[3 + s] && o < rec[p + 1]) ? (uint32_t)(rec[p] + o) : kAbsent;
+            } else if constexpr (m == NP) {
+              const int32_t oq = r < 0 ? o_lo : o_hi;
+              vid = (val[3 + s] && (uint32_t)oq < (uint32_t)lnw[3 + s]) ? (uint32_t)(stw[3 + s] + oq) : kAbsent;
+            } else {
+              constexpr int a = l - NP;
+              const int32_t oq = (s == 0) ? gst[(int64_t)gst_axis_slot(a + 1, r) * ng + o]
+                                          : gst[(int64_t)gst_pair_slot(D, a, s, r) * ng + o];
+              vid = (val[3 + s] && (uint32_t)oq < (uint32_t)len) ? base + (uint32_t)oq : kAbsent;
+            }
+            fma_rc<T>(vs, (r < 0 ? wlo : whi) * gs, BufLoad<T>::ld(xr, vid));
+          }
+          if (s & 1) v1[(s + 1) / 2] = vs;
+          else {
+            h2[(s + 2) / 2].x += vs.x;
+            h2[(s + 2) / 2].y += vs.y;
+          }
+        }
+      }
+    }
+    // ---- h1 at s = -1, 1 and the group's contribution ----
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int s = 2 * q - 1;
+      C h = v1[q];
+      fma_rc<T>(h, a1, u[3 + s]);
+      fma_rc<T>(h, e[s + 2], h2[q]);
+      fma_rc<T>(h, e[s + 3], h2[q + 1]);
+      fma_rc<T>(acc, e[2 + q], h);  // e_0 for s = -1, e_1 for s = 1
+    }
+  });
+  if (out_scale) acc = scal<T>((T)*out_scale, acc);
+  if (prev) {
+    const T pc = (T)(-(*prev_coef) * (prev_scale ? *prev_scale : 1.0));
+    fma_rc<T>(acc, pc, prev[self]);
+  }
+  y[self] = acc;
+}
+
+template <typename T, int N, int NP, bool X2>
+static void launch_long_pair(const IndexDev &ix, const double *hh, const void *x, void *y,
+                             const double *out_scale, const void *prev, const double *prev_coef,
+                             const double *prev_scale, hipStream_t s, bool with_small) {
+  using C = typename V2<T>::t;
+  if (ix.nchunks > 0) {
+    const unsigned blocks = xcd_grid((ix.nchunks * kChunk + 255) / 256);
+    hipLaunchKernelGGL((k_hh_long<T, N, NP, false, X2>), dim3(blocks), dim3(256), 0, s, ix, hh,
+                       (const C *)x, (C *)y, out_scale, (const C *)prev, prev_coef, prev_scale);
+  }
+  if (with_small && ix.nsmall > 0) {
+    const unsigned blocks = xcd_grid((ix.nsmall + 255) / 256);
+    hipLaunchKernelGGL((k_hh_long<T, N, NP, true, X2>), dim3(blocks), dim3(256), 0, s, ix, hh,
+                       (const C *)x, (C *)y, out_scale, (const C *)prev, prev_coef, prev_scale);
+  }
+}
+
+// Returns 1 if long and short tiles were both launched, 2 if only the long tiles (the
+// caller handles the short ones), 0 if (N, NP) has no specialisation.
+template <typename T>
+int launch_hh_long_impl(const IndexDev &ix, const double *hh, const void *x, void *y,
+                        const double *out_scale, const void *prev, const double *prev_coef,
+                        const double *prev_scale, hipStream_t s, bool x2) {
+  if (ix.rstride != rec_stride(ix.np)) return 0;
+  const bool small = ix.tile_rec != nullptr;
+#define HS_LONG_CASE(NN, PP)                                                                    \
+  case NN * 32 + PP:                                                                            \
+    if (x2)                                                                                     \
+      launch_long_pair<T, NN, PP, true>(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, small);  \
+    else                                                                                        \
+      launch_long_pair<T, NN, PP, false>(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, small); \
+    return small ? 1 : 2;
+  switch (ix.N * 32 + ix.np) {
+    HS_LONG_CASE(1, 0)
+    HS_LONG_CASE(2, 0)
+    HS_LONG_CASE(2, 1)
+    HS_LONG_CASE(3, 0)
+    HS_LONG_CASE(3, 1)
+    HS_LONG_CASE(3, 2)
+    HS_LONG_CASE(4, 0)
+    HS_LONG_CASE(4, 1)
+    HS_LONG_CASE(4, 2)
+    HS_LONG_CASE(4, 3)
+    HS_LONG_CASE(5, 2)
+    HS_LONG_CASE(6, 2)
+    HS_LONG_CASE(6, 3)
+    HS_LONG_CASE(7, 4)
+    HS_LONG_CASE(8, 5)
+    HS_LONG_CASE(9, 5)
+    HS_LONG_CASE(10, 6)
+    default:
+      return 0;
+  }
+#undef HS_LONG_CASE
+}
+
+}  // namespace hs

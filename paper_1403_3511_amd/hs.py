@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhs.so")
+# HS_LIBRARY may name another build of the same library (launch-shape experiments)
+LIB_PATH = os.environ.get("HS_LIBRARY") or os.path.join(_HERE, "libhs.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} not built: run __graft_entry__.build() or "
                       "python -m paper_1403_3511_amd.build")

@@ -116,3 +116,49 @@ def test_float32_krylov_error_stated(hs):
     err = rel2(got, ref)
     print(f"float32 Krylov form, 10 steps: relative error vs float64 oracle {err:.3e}")
     assert err < 1e-4
+
+
+def test_graph_replay_matches_eager(hs):
+    """A step captured in a HIP graph (time read from and advanced on the device) gives the
+    eager result on every replay, with eager work and synchronisations in between."""
+    import torch
+    N, B, m, h = 3, 300, 10, 0.005
+    tt = hh_workload(N, 0.111, 0.05)
+    idx = hs.Index(N, B)
+    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    k = idx.multi_indices()
+    c0 = coherent_state(k, [1.0, 0.5, -0.5])
+    c0 /= np.linalg.norm(c0)
+    # eager reference: 4 steps
+    ce = torch.from_numpy(c0.copy()).to("cuda")
+    wse = hs.workspace(idx, pot, 0, m)
+    te = torch.zeros(1, dtype=torch.float64, device="cuda")
+    eager = []
+    for _ in range(4):
+        hs.step(idx, pot, ce, 0.0, h, m, ws=wse, t_dev=te)
+        eager.append(ce.cpu().numpy().copy())
+    # graph
+    cg = torch.from_numpy(c0.copy()).to("cuda")
+    wsg = hs.workspace(idx, pot, 0, m)
+    tg = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    snapshot = cg.clone()
+    with torch.cuda.stream(s2):
+        with torch.cuda.graph(g, stream=s2):
+            hs.step(idx, pot, cg, 0.0, h, m, ws=wsg, t_dev=tg)
+    torch.cuda.synchronize()
+    # capture does not execute: restore the start state and time
+    cg.copy_(snapshot)
+    tg.zero_()
+    torch.cuda.synchronize()
+    junk = torch.randn(1000, device="cuda")
+    for i in range(4):
+        g.replay()
+        torch.cuda.synchronize()
+        junk = junk * 1.0001 + 1.0  # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(cg.cpu().numpy(), eager[i]), f"replay {i} differs from eager"
+    assert tg.item() == pytest.approx(4 * h, abs=1e-15)
