@@ -136,9 +136,11 @@ int32_t hs_step(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev, in
                 double *diag_dev, void *stream);
 
 /* ---- batched form: many (index, potential) instances in one persistent launch ----
- * Instances are described by handles plus their uploaded device blocks; vectors of
- * all instances are packed back to back in one device buffer with offsets given by
- * hs_batch_offsets (complex elements, host int64[n+1]).                              */
+ * Instances are described by handles plus their uploaded device blocks (which must stay
+ * alive); vectors of all instances are packed back to back in one device buffer with
+ * offsets given by hs_batch_offsets (complex elements, host int64[n+1]).  Supported:
+ * fused-class potentials on index sets built with the default tile dimension, N 2..8,
+ * fewer than 2^31 rows in total (else HS_E_UNSUPPORTED / HS_E_OVERFLOW).            */
 int32_t hs_batch_create(int32_t n, const hs_index *idx, const void *const *idx_dev,
                         const hs_pot *pot, void *const *pot_dev, hs_batch *out);
 int32_t hs_batch_destroy(hs_batch b);
@@ -149,14 +151,18 @@ int32_t hs_batch_workspace_bytes(hs_batch b, int32_t m, int64_t *bytes);
 /* y = H_i c_i for every instance i, one persistent launch (complex128). */
 int32_t hs_batch_apply_h(hs_batch b, const void *batch_dev, const void *c, void *y, void *ws,
                          void *stream);
-/* One exponential-midpoint Lanczos step for every instance (complex128). */
-int32_t hs_batch_step(hs_batch b, void *batch_dev, double t, double h, int32_t m,
+/* One exponential-midpoint Lanczos step for every instance (complex128); the time is
+ * read from t_dev when it is not NULL and then advanced by h on the device.  ws holds
+ * hs_batch_workspace_bytes(b, m) bytes. */
+int32_t hs_batch_step(hs_batch b, void *batch_dev, double t, double *t_dev, double h, int32_t m,
                       int32_t reorth, void *c, void *ws, void *stream);
-/* Launch-shape choice of the persistent kernel: workgroup size and rows per item.
- * wg = 0 or chunk = 0 keep the current value.  hs_batch_autotune_sync times the
- * candidates on the given buffers and keeps the fastest (synchronises the stream).  */
-int32_t hs_batch_set_launch(hs_batch b, int32_t wg, int32_t chunk);
-int32_t hs_batch_get_launch(hs_batch b, int32_t *wg, int32_t *chunk);
+/* Launch shape of the persistent kernel: workgroup size wg (64, 128, 256) and resident
+ * workgroups per compute unit per_cu (1..64); 0 keeps the current value.
+ * hs_batch_autotune_sync times the candidates on the given buffers and keeps the
+ * fastest (synchronises the stream).  Work items are 64 rows; the item queue is split
+ * into one contiguous range per XCD, largest instances first.                        */
+int32_t hs_batch_set_launch(hs_batch b, int32_t wg, int32_t per_cu);
+int32_t hs_batch_get_launch(hs_batch b, int32_t *wg, int32_t *per_cu);
 int32_t hs_batch_autotune_sync(hs_batch b, const void *batch_dev, const void *c, void *y,
                                void *ws, void *stream);
 

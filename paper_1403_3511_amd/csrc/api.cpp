@@ -87,6 +87,7 @@ extern "C" int32_t hs_pot_set_coeffs_device(hs_pot pot, void *pot_dev, const dou
                                             void *stream) {
   if (!pot || !pot_dev || !coef_dev) return hs::fail(HS_E_INVALID, "hs_pot_set_coeffs_device: NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  pot->x2 = pot->x2_struct;  // values now come from the device
   int32_t st = hs::launch_copy_coeffs(pot, pot_dev, coef_dev, s);
   if (st != HS_OK) return st;
   return hs::launch_set_time(pot, pot_dev, 0.0, nullptr, 0.0, s);

@@ -133,6 +133,7 @@ struct hs_pot_s {
   std::vector<double> base, amp, freq, phase;
   bool fused = false;
   bool x2 = false;                    // fused form uses x_l^2 or x_l x_{l+1} monomials
+  bool x2_struct = false;             // ... for some choice of the coefficients
   // fused: compiled monomial coefficient of each HH slot = sum_t M[slot][t] beta_t
   int32_t nslots = 0;
   std::vector<double> M;              // nslots x nterms

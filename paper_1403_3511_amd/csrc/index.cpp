@@ -305,10 +305,10 @@ static int32_t build_index(hs_index_s *ix) {
     for (int k = 0; k < (s < 0 ? -s : s) && t >= 0; ++k) t = ix->tnbr[t * 2 * np + 2 * l + (s > 0)];
     return t;
   };
-  // records for every tile when they are cheap next to one vector (then the short tiles
-  // use them too), else for the long tiles only
+  // records for every tile when they cost at most 96 bytes per row (then the short
+  // tiles use them too), else for the long tiles only
   const int64_t nlong = std::count_if(ix->tlen.begin(), ix->tlen.end(), [](int32_t l) { return l >= hs::kLongTile; });
-  ix->recs_all = (int64_t)ix->rstride * 4 * ntiles <= std::max<int64_t>(total * 8, INT64_C(64) << 20);
+  ix->recs_all = (int64_t)ix->rstride * 4 * ntiles <= std::max<int64_t>(total * 96, INT64_C(64) << 20);
   ix->recs.reserve((size_t)ix->rstride * (ix->recs_all ? ntiles : nlong));
   ix->tile_rec.assign(ix->recs_all ? ntiles : 0, -1);
   for (int64_t t = 0; t < ntiles; ++t) {

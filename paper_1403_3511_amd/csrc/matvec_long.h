@@ -46,37 +46,15 @@ template <> struct BufLoad<float> {
 //   h2_s = a3 (e_s u_{s-1} + e_{s+1} u_{s+1}) + a2 u_s + g2 v_s      (s = -2, 0, 2)
 //   h1_s = e_s h2_{s-1} + e_{s+1} h2_{s+1} + a1 u_s + g1 v_s          (s = -1, 1)
 //   G_l  = e_0 h1_{-1} + e_1 h1_1.
-template <typename T, int N, int NP, bool PACKED, bool X2>
-__global__ void __launch_bounds__(256)
-k_hh_long(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *__restrict__ x,
-          typename V2<T>::t *__restrict__ y, const double *__restrict__ out_scale,
-          const typename V2<T>::t *__restrict__ prev, const double *__restrict__ prev_coef,
-          const double *__restrict__ prev_scale) {
+// One row (offset o of the tile whose record is rec) of y = oscale (D + W) x - pcoef prev.
+template <typename T, int N, int NP, bool X2>
+__device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restrict__ hh,
+                                       const typename V2<T>::t *__restrict__ x,
+                                       typename V2<T>::t *__restrict__ y,
+                                       const int32_t *__restrict__ rec, int32_t o, T oscale,
+                                       const typename V2<T>::t *__restrict__ prev, T pcoef) {
   using C = typename V2<T>::t;
   constexpr int D = N - NP;
-  constexpr int RS = rec_stride(NP);
-  // XCD-aware order: block b runs on XCD b % kXcd, so give XCD x the contiguous range
-  // [x * per, (x + 1) * per) of the tile-ordered work list; tiles and their neighbours
-  // then share one L2
-  const int64_t per = gridDim.x / kXcd;
-  const int64_t blk = (int64_t)(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
-  const int32_t *__restrict__ rec;
-  int32_t o;
-  if constexpr (!PACKED) {
-    const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
-    if (wave >= ix.nchunks) return;
-    const int32_t ri = __builtin_amdgcn_readfirstlane(ix.chunks[2 * wave]);
-    const int32_t o0 = __builtin_amdgcn_readfirstlane(ix.chunks[2 * wave + 1]);
-    rec = ix.recs + (int64_t)ri * RS;
-    o = o0 + (int32_t)(threadIdx.x & 63);
-    if (o >= rec[1]) return;
-  } else {
-    const int64_t i = blk * blockDim.x + threadIdx.x;
-    if (i >= ix.nsmall) return;
-    const int32_t r = ix.small_rows[i];
-    rec = ix.recs + (int64_t)ix.tile_rec[ix.rowtile[r]] * RS;
-    o = r - rec[0];
-  }
   const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
       (void *)x, (short)0, (int)(ix.size * (int64_t)sizeof(C)), 0x00020000);
   const uint32_t base = (uint32_t)rec[0];
@@ -239,12 +217,43 @@ k_hh_long(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *_
       fma_rc<T>(acc, e[2 + q], h);  // e_0 for s = -1, e_1 for s = 1
     }
   });
-  if (out_scale) acc = scal<T>((T)*out_scale, acc);
-  if (prev) {
-    const T pc = (T)(-(*prev_coef) * (prev_scale ? *prev_scale : 1.0));
-    fma_rc<T>(acc, pc, prev[self]);
-  }
+  acc = scal<T>(oscale, acc);
+  if (prev) fma_rc<T>(acc, -pcoef, prev[self]);
   y[self] = acc;
+}
+
+template <typename T, int N, int NP, bool PACKED, bool X2>
+__global__ void __launch_bounds__(256)
+k_hh_long(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *__restrict__ x,
+          typename V2<T>::t *__restrict__ y, const double *__restrict__ out_scale,
+          const typename V2<T>::t *__restrict__ prev, const double *__restrict__ prev_coef,
+          const double *__restrict__ prev_scale) {
+  constexpr int RS = rec_stride(NP);
+  // XCD-aware order: block b runs on XCD b % kXcd, so give XCD x the contiguous range
+  // [x * per, (x + 1) * per) of the tile-ordered work list; tiles and their neighbours
+  // then share one L2
+  const int64_t per = gridDim.x / kXcd;
+  const int64_t blk = (int64_t)(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
+  const int32_t *__restrict__ rec;
+  int32_t o;
+  if constexpr (!PACKED) {
+    const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
+    if (wave >= ix.nchunks) return;
+    const int32_t ri = __builtin_amdgcn_readfirstlane(ix.chunks[2 * wave]);
+    const int32_t o0 = __builtin_amdgcn_readfirstlane(ix.chunks[2 * wave + 1]);
+    rec = ix.recs + (int64_t)ri * RS;
+    o = o0 + (int32_t)(threadIdx.x & 63);
+    if (o >= rec[1]) return;
+  } else {
+    const int64_t i = blk * blockDim.x + threadIdx.x;
+    if (i >= ix.nsmall) return;
+    const int32_t r = ix.small_rows[i];
+    rec = ix.recs + (int64_t)ix.tile_rec[ix.rowtile[r]] * RS;
+    o = r - rec[0];
+  }
+  const T oscale = out_scale ? (T)*out_scale : T(1);
+  const T pcoef = prev ? (T)((*prev_coef) * (prev_scale ? *prev_scale : 1.0)) : T(0);
+  hh_row<T, N, NP, X2>(ix, hh, x, y, rec, o, oscale, prev, pcoef);
 }
 
 template <typename T, int N, int NP, bool X2>

@@ -90,11 +90,25 @@ bool try_fused(hs_pot_s *P) {
       if (l < 0) break;
     }
   }
+  // x_l^2 and x_l x_{l+1} slots: needed if some contributing term is time dependent or
+  // the time-independent contributions do not cancel (the harmonic part of V cancels
+  // against the subtracted |x|^2 / 2 exactly)
   P->x2 = false;
+  P->x2_struct = false;
   for (int l = 0; l < N; ++l)
-    for (int t = 0; t < P->nterms; ++t)
-      if (P->M[(size_t)slot_a(l, 2) * P->nterms + t] != 0.0 || P->M[(size_t)slot_g(l, 1) * P->nterms + t] != 0.0)
-        P->x2 = true;
+    for (int slot : {slot_a(l, 2), slot_g(l, 1)}) {
+      double val = 0.0;
+      bool dyn = false, any = false;
+      for (int t = 0; t < P->nterms; ++t) {
+        const double m = P->M[(size_t)slot * P->nterms + t];
+        if (m == 0.0) continue;
+        any = true;
+        if (P->amp[t] != 0.0) dyn = true;
+        val += m * P->base[t];
+      }
+      if (any) P->x2_struct = true;
+      if (dyn || val != 0.0) P->x2 = true;
+    }
   return true;
 }
 
@@ -258,43 +272,6 @@ extern "C" int32_t hs_pot_create(int32_t N, int32_t basis, double scale, int32_t
   for (int l = 0; l < (subtract_harmonic ? N : 0); ++l) {  // W = V - x_l^2 / 2
     P->deg[(nterms + l) * N + l] = 2;
     P->base[nterms + l] = -0.5;
-  }
-  // merge time-independent terms with equal degrees (the operator is linear in the
-  // coefficients) and drop the ones that vanish, e.g. x_l^2 after the harmonic part of V
-  // has been subtracted
-  {
-    std::vector<int> keep;
-    std::map<std::vector<uint16_t>, int> first;
-    for (int t = 0; t < total; ++t) {
-      if (P->amp[t] != 0.0) {
-        keep.push_back(t);
-        continue;
-      }
-      std::vector<uint16_t> key(P->deg.begin() + (size_t)t * N, P->deg.begin() + (size_t)(t + 1) * N);
-      auto it = first.find(key);
-      if (it == first.end()) {
-        first[key] = t;
-        keep.push_back(t);
-      } else {
-        P->base[it->second] += P->base[t];
-      }
-    }
-    std::vector<uint16_t> deg;
-    std::vector<double> b, a, f, ph;
-    for (int t : keep) {
-      if (P->amp[t] == 0.0 && P->base[t] == 0.0) continue;
-      deg.insert(deg.end(), P->deg.begin() + (size_t)t * N, P->deg.begin() + (size_t)(t + 1) * N);
-      b.push_back(P->base[t]);
-      a.push_back(P->amp[t]);
-      f.push_back(P->freq[t]);
-      ph.push_back(P->phase[t]);
-    }
-    P->deg.swap(deg);
-    P->base.swap(b);
-    P->amp.swap(a);
-    P->freq.swap(f);
-    P->phase.swap(ph);
-    P->nterms = (int32_t)P->base.size();
   }
   int32_t st = hs::compile_potential(P);
   if (st != HS_OK) {

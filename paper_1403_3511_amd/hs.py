@@ -57,7 +57,7 @@ _SIGS = {
     "hs_batch_upload": [_vp, _vp, _i64, _vp],
     "hs_batch_workspace_bytes": [_vp, _i32, _pi64],
     "hs_batch_apply_h": [_vp, _vp, _vp, _vp, _vp, _vp],
-    "hs_batch_step": [_vp, _vp, _f64, _f64, _i32, _i32, _vp, _vp, _vp],
+    "hs_batch_step": [_vp, _vp, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp],
     "hs_batch_set_launch": [_vp, _i32, _i32],
     "hs_batch_get_launch": [_vp, _pi32, _pi32],
     "hs_batch_autotune_sync": [_vp, _vp, _vp, _vp, _vp, _vp],
@@ -199,7 +199,7 @@ class Pot:
         hs_pot_create(N, BASIS[basis] if isinstance(basis, str) else int(basis), float(scale), nt,
                       deg.ctypes.data_as(_pu16), *[x.ctypes.data_as(_pf64) for x in arrs],
                       1 if subtract_harmonic else 0, C.byref(h))
-        self.h, self.N, self.nterms = h, N, nt + (N if subtract_harmonic else 0)
+        self.h, self.N, self.nterms = h, N, nt + (N if subtract_harmonic else 0)  # terms as compiled
         f = C.c_int32()
         hs_pot_is_fused(h, C.byref(f))
         self.fused = bool(f.value)
@@ -244,3 +244,61 @@ def step(idx: Index, pot: Pot, c, t: float, h: float, m: int, dtype: int = HS_C1
     hs_step(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, float(t), ptr(t_dev), float(h), int(m),
             1 if reorth else 0, ptr(c), ptr(ws), ptr(diag), stream_ptr())
     return c
+
+
+class Batch:
+    """Many (Index, Pot) instances advanced by one persistent launch per H application.
+    Vectors are packed: instance i occupies elements offsets[i] .. offsets[i] + size_i."""
+
+    def __init__(self, indices, pots, device="cuda"):
+        n = len(indices)
+        VP = _vp * n
+        h = _vp()
+        hs_batch_create(n, VP(*[i.h for i in indices]), VP(*[i.dev.data_ptr() for i in indices]),
+                        VP(*[p.h for p in pots]), VP(*[p.dev.data_ptr() for p in pots]), C.byref(h))
+        self.h, self.n = h, n
+        self._keep = (list(indices), list(pots))  # device blocks must outlive the batch
+        off = np.zeros(n + 1, dtype=np.int64)
+        hs_batch_offsets(h, off.ctypes.data_as(_pi64))
+        self.offsets = off
+        self.total = int(off[-1])
+        nb = C.c_int64()
+        hs_batch_device_bytes(h, C.byref(nb))
+        self.dev = dev_buffer(nb.value, device)
+        hs_batch_upload(h, ptr(self.dev), nb.value, stream_ptr())
+
+    def workspace(self, m: int, device="cuda"):
+        nb = C.c_int64()
+        hs_batch_workspace_bytes(self.h, m, C.byref(nb))
+        return dev_buffer(nb.value, device)
+
+    def apply_h(self, c, y):
+        hs_batch_apply_h(self.h, ptr(self.dev), ptr(c), ptr(y), None, stream_ptr())
+        return y
+
+    def step(self, c, t: float, h: float, m: int, reorth: bool = True, ws=None, t_dev=None):
+        if ws is None:
+            ws = self.workspace(m, c.device)
+        hs_batch_step(self.h, ptr(self.dev), float(t), ptr(t_dev), float(h), int(m),
+                      1 if reorth else 0, ptr(c), ptr(ws), stream_ptr())
+        return c
+
+    def set_launch(self, wg: int = 0, per_cu: int = 0):
+        hs_batch_set_launch(self.h, wg, per_cu)
+
+    def get_launch(self):
+        a, b = C.c_int32(), C.c_int32()
+        hs_batch_get_launch(self.h, C.byref(a), C.byref(b))
+        return a.value, b.value
+
+    def autotune(self, c, y):
+        hs_batch_autotune_sync(self.h, ptr(self.dev), ptr(c), ptr(y), None, stream_ptr())
+        return self.get_launch()
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                _lib.hs_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
