@@ -167,16 +167,19 @@ int32_t hs_batch_autotune_sync(hs_batch b, const void *batch_dev, const void *c,
                                void *ws, void *stream);
 
 /* ---- learned coefficients: Gauss-Hermite projection and a BF16-MFMA MLP --------
- * Potential family W(x) = - sum_i a_i exp(-|x - c_i(t)|^2 / (2 sigma^2)) in N <= 8
- * dimensions, c_i(t) = base_i + rho (cos(omega t + phi_i) u_i + sin(omega t + phi_i) w_i)
+ * Potential family W(x) = - sum_i a_i exp(-|x - c_i(t)|^2 / (2 sigma^2)) in N <= 4
+ * dimensions with G <= 4 wells, c_i(t) = base_i + rho (cos(omega t + phi_i) u_i + sin(omega t + phi_i) w_i)
  * with geometry (base, u, w, phi) fixed per family; parameters per sample
  * p = (t, a_1..a_G, sigma, rho, omega).  Coefficients: Hermite polynomials
  * H_a(x) = prod_l H_{a_l}(x_l) (physicists') with |a| <= D in lexicographic order of a.
  *
  * hs_gh_project: alpha_a = <W, H_a> / <H_a, H_a> with weight exp(-|x|^2), by product
- * Gauss-Hermite quadrature with Q nodes per axis (paper Sec. 4.1), for nsamp parameter
- * rows (device, nsamp x (3 + G) doubles) into coef (device, nsamp x ncoef doubles).
- * geometry (host): base, u, w as G x N doubles each, then phase (G doubles).        */
+ * Gauss-Hermite quadrature with Q <= 32 nodes per axis (paper Sec. 4.1), D <= 8, for
+ * nsamp parameter rows (device, nsamp x (4 + G) doubles) into coef (device, nsamp x
+ * ncoef doubles, ncoef = C(N + D, N)).  geometry (host): base, u, w as G x N doubles
+ * each, then phase (G doubles).  The nodes and weights are computed on the host (the
+ * eigenvalues of the Hermite Jacobi matrix); one workgroup per sample; asynchronous on
+ * the stream.  HS_E_INVALID for sizes out of range.                                  */
 int32_t hs_gh_ncoef(int32_t N, int32_t D, int32_t *ncoef);
 int32_t hs_gh_project(int32_t N, int32_t G, int32_t D, int32_t Q, const double *geometry_host,
                       int32_t nsamp, const double *params_dev, double *coef_dev, void *stream);
@@ -197,6 +200,15 @@ int32_t hs_mlp_download_params(hs_mlp mlp, const void *dev, float *weights_host,
  * batch x out float64), de-normalised. */
 int32_t hs_mlp_predict(hs_mlp mlp, void *dev, int32_t batch, const double *x_dev,
                        double *coef_dev, void *stream);
+/* Surrogate coefficients with the quadrature as fallback: the network predicts every
+ * row, then rows with any input outside the network's training box (in_lo, in_hi of
+ * the normalisation) are recomputed by the Gauss-Hermite projection (Q nodes).  The
+ * network must have 4 + G inputs and C(N + D, N) outputs.  used_quad_dev (device,
+ * nsamp int32, may be NULL) receives 1 for rows taken from the quadrature.  No host
+ * synchronisation: the choice is made per row on the device.                        */
+int32_t hs_sur_coeffs(hs_mlp mlp, void *dev, int32_t N, int32_t G, int32_t D, int32_t Q,
+                      const double *geometry_host, int32_t nsamp, const double *params_dev,
+                      double *coef_dev, int32_t *used_quad_dev, void *stream);
 /* One training step on (x, target coefficients) (device float64), MSE on normalised
  * outputs, Adam(lr, 0.9, 0.999, 1e-8).  loss_dev (device float, may be NULL) receives
  * the loss.  grads_dev (device, may be NULL) receives the float32 gradients in the

@@ -1,14 +1,768 @@
-// Learned-coefficient path (placeholder until the MFMA kernels land).
+// Learned potential coefficients.
+//
+// (1) Gauss-Hermite projection (the fallback and the judge): for the potential family
+//     W(x) = - sum_i a_i exp(-|x - c_i(t)|^2 / (2 sigma^2)),
+//     c_i(t) = base_i + rho (cos(omega t + phi_i) u_i + sin(omega t + phi_i) w_i),
+//     alpha_a = <W, H_a> / <H_a, H_a> (weight exp(-|x|^2)) by the product Gauss-Hermite
+//     rule with Q nodes per axis (paper Sec. 4.1), |a| <= D.  The Q^N-point sum is
+//     factorised over the two halves of the axes: S[mA][aB] = sum_mB F(mA, mB) h_aB(mB)
+//     in LDS, then alpha_(aA, aB) = sum_mA h_aA(mA) S[mA][aB].
+// (2) A multilayer perceptron in -> hid -> hid -> out with SiLU, trained on those
+//     coefficients: BF16 MFMA products (v_mfma_f32_16x16x32_bf16) with FP32
+//     accumulation, FP32 master weights, Adam.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
 #include "hs_internal.h"
 
-extern "C" {
-int32_t hs_gh_ncoef(int32_t, int32_t, int32_t *) { return hs::fail(HS_E_UNSUPPORTED, "not built"); }
-int32_t hs_gh_project(int32_t, int32_t, int32_t, int32_t, const double *, int32_t, const double *, double *, void *) { return hs::fail(HS_E_UNSUPPORTED, "not built"); }
-int32_t hs_mlp_create(int32_t, int32_t, int32_t, hs_mlp *m) { if (m) *m = nullptr; return hs::fail(HS_E_UNSUPPORTED, "not built"); }
-int32_t hs_mlp_destroy(hs_mlp) { return HS_OK; }
-int32_t hs_mlp_device_bytes(hs_mlp, int32_t, int64_t *) { return hs::fail(HS_E_UNSUPPORTED, "not built"); }
-int32_t hs_mlp_upload_params(hs_mlp, void *, const float *, const float *, void *) { return hs::fail(HS_E_UNSUPPORTED, "not built"); }
-int32_t hs_mlp_download_params(hs_mlp, const void *, float *, void *) { return hs::fail(HS_E_UNSUPPORTED, "not built"); }
-int32_t hs_mlp_predict(hs_mlp, void *, int32_t, const double *, double *, void *) { return hs::fail(HS_E_UNSUPPORTED, "not built"); }
-int32_t hs_mlp_train_step(hs_mlp, void *, int32_t, const double *, const double *, float, float *, float *, void *) { return hs::fail(HS_E_UNSUPPORTED, "not built"); }
+namespace hs {
+
+// ---------------------------------------------------------------------------------------
+// Gauss-Hermite rule (host): nodes are the eigenvalues of the Jacobi matrix with
+// off-diagonals sqrt(k/2) (Golub-Welsch, cf. paper Sec. 4.2 X_full = U^T Xi U); weights
+// from the Christoffel function w_m = 1 / sum_k psi_k(x_m)^2 with the orthonormal
+// polynomials psi_k (psi_0 = pi^-1/4, same recurrence as the Hermite functions).
+// ---------------------------------------------------------------------------------------
+static void tridiag_eigenvalues(std::vector<double> d, std::vector<double> e, std::vector<double> &out) {
+  // implicit QL with Wilkinson shifts on a symmetric tridiagonal matrix (diagonal d,
+  // off-diagonal e[0..n-2]); eigenvalues only
+  const int n = (int)d.size();
+  e.resize(n, 0.0);
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0; iter < 200; ++iter) {
+      int m = l;
+      for (; m < n - 1; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= 1e-16 * dd) break;
+      }
+      if (m == l) break;
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+      double s = 1.0, c = 1.0, p = 0.0;
+      int i = m - 1;
+      for (; i >= l; --i) {
+        double f = s * e[i], b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {
+          d[i + 1] -= p;
+          e[m] = 0.0;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+      }
+      if (r == 0.0 && i >= l) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  out = d;
+  std::sort(out.begin(), out.end());
 }
+
+static void gh_rule(int Q, std::vector<double> &x, std::vector<double> &w) {
+  std::vector<double> d(Q, 0.0), e(Q, 0.0);
+  for (int k = 1; k < Q; ++k) e[k - 1] = std::sqrt(0.5 * k);
+  tridiag_eigenvalues(d, e, x);
+  w.assign(Q, 0.0);
+  for (int m = 0; m < Q; ++m) {
+    double p0 = std::pow(M_PI, -0.25), p1 = 0.0, s = p0 * p0;
+    double pm = 0.0, pc = p0;
+    for (int k = 0; k + 1 < Q; ++k) {
+      p1 = (x[m] * pc - std::sqrt(0.5 * k) * pm) / std::sqrt(0.5 * (k + 1));
+      pm = pc;
+      pc = p1;
+      s += pc * pc;
+    }
+    w[m] = 1.0 / s;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// projection kernel
+// ---------------------------------------------------------------------------------------
+constexpr int kGhMaxQ = 32, kGhMaxG = 4, kGhMaxN = 4, kGhMaxD = 8;
+constexpr int kGhThreads = 512;
+constexpr int kGhChunk = 4096;                // most leading-grid rows per chunk
+constexpr size_t kGhLdsBytes = 64 * 1024;    // LDS budget of one workgroup
+
+struct GhArgs {
+  int N, G, D, Q, NA, NB, QA, QB, nB, ncoef, R;
+  double xi[kGhMaxQ];
+  double hq[kGhMaxD + 1][kGhMaxQ];  // w_m H_n(xi_m) / (sqrt(pi) 2^n n!)
+  double base[kGhMaxG][kGhMaxN], u[kGhMaxG][kGhMaxN], w[kGhMaxG][kGhMaxN], phase[kGhMaxG];
+};
+
+// LDS layout of the projection kernel (doubles first, then ints)
+struct GhLds {
+  int64_t F, T, S, hq, xi, dbl_end;  // double offsets
+  int bcode, bpos, kA, kB, int_end;  // int offsets after the doubles
+  static __host__ __device__ GhLds make(int R, int QB, int Q, int D, int nB, int NB, int ncoef) {
+    GhLds L;
+    L.F = 0;
+    L.T = L.F + (int64_t)R * QB;
+    L.S = L.T + (NB == 2 ? (int64_t)R * Q * (D + 1) : 0);
+    L.hq = L.S + (int64_t)R * nB;
+    L.xi = L.hq + (int64_t)(D + 1) * Q;
+    L.dbl_end = L.xi + Q;
+    int totB = 1;
+    for (int l = 0; l < NB; ++l) totB *= (D + 1);
+    L.bcode = 0;
+    L.bpos = L.bcode + nB;
+    L.kA = L.bpos + totB;
+    L.kB = L.kA + ncoef;
+    L.int_end = L.kB + ncoef;
+    return L;
+  }
+  __host__ __device__ size_t bytes() const { return sizeof(double) * dbl_end + sizeof(int) * int_end; }
+};
+
+// One block per sample; params row: (t, a_1..a_G, sigma, rho, omega).
+// V is evaluated at every node of the Q^N grid from its definition (a black box for the
+// projection).  Axes split into a leading half A (NA axes) and a trailing half B (NB <= 2
+// axes).  For a chunk of R leading-grid points mA:
+//   F[r][mB] = W(xi_mA, xi_mB)
+//   S[r][b]  = sum_mB F[r][mB] prod_{l in B} hq[aB_l][mB_l]   (b over |aB| <= D; for NB = 2
+//              as two 1-D contractions through T[r][mB0][aB1])
+//   alpha_(aA, aB) += sum_r prod_{l in A} hq[aA_l][mA_l] S[r][b(aB)]   (one per thread)
+// With a box (lo, hi non-null) only samples with some input outside [lo, hi] are
+// projected (the others keep what the network wrote); used[s] records the choice.
+__global__ void __launch_bounds__(kGhThreads)
+k_gh_project(GhArgs A, const double *__restrict__ params, double *__restrict__ coef,
+             const float *__restrict__ lo, const float *__restrict__ hi, int32_t *__restrict__ used) {
+  extern __shared__ double lds[];
+  const GhLds L = GhLds::make(A.R, A.QB, A.Q, A.D, A.nB, A.NB, A.ncoef);
+  double *Fc = lds + L.F, *Tc = lds + L.T, *Sc = lds + L.S, *hqs = lds + L.hq, *xis = lds + L.xi;
+  int *ib = (int *)(lds + L.dbl_end);
+  int *bcode = ib + L.bcode, *bpos = ib + L.bpos, *kA = ib + L.kA, *kB = ib + L.kB;
+  const int tid = threadIdx.x;
+  const int s = blockIdx.x;
+  const int Q = A.Q, DB = A.D + 1;
+  const double *p = params + (int64_t)s * (A.G + 4);
+  if (lo) {
+    bool inside = true;
+    for (int k = 0; k < A.G + 4; ++k) inside = inside && p[k] >= (double)lo[k] && p[k] <= (double)hi[k];
+    if (tid == 0 && used) used[s] = inside ? 0 : 1;
+    if (inside) return;  // uniform over the block: no barrier has been reached yet
+  }
+  const double t = p[0], sigma = p[A.G + 1], rho = p[A.G + 2], omega = p[A.G + 3];
+  const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+  double cen[kGhMaxG][kGhMaxN], amp[kGhMaxG];
+#pragma unroll
+  for (int i = 0; i < kGhMaxG; ++i) {
+    amp[i] = i < A.G ? p[1 + i] : 0.0;
+    const double ang = omega * t + A.phase[i];
+    const double ca = cos(ang), sa = sin(ang);
+#pragma unroll
+    for (int l = 0; l < kGhMaxN; ++l) cen[i][l] = A.base[i][l] + rho * (ca * A.u[i][l] + sa * A.w[i][l]);
+  }
+  for (int e = tid; e < DB * Q; e += kGhThreads) hqs[e] = A.hq[e / Q][e % Q];
+  for (int e = tid; e < Q; e += kGhThreads) xis[e] = A.xi[e];
+  // multi-index tables, |a| <= D in lexicographic order (last axis fastest), compacted
+  // by one wave with ballots
+  int totB = 1, tot = 1;
+  for (int l = 0; l < A.NB; ++l) totB *= DB;
+  for (int l = 0; l < A.N; ++l) tot *= DB;
+  if (tid < 64) {
+    int nb = 0;
+    for (int c0 = 0; c0 < totB; c0 += 64) {
+      const int c = c0 + tid;
+      int sum = 0, code = 0;
+      if (c < totB) {
+        int r = c;
+        for (int l = A.NB - 1, sh = 0; l >= 0; --l, sh += 4) {
+          const int d = r % DB;
+          r /= DB;
+          sum += d;
+          code |= d << sh;
+        }
+      }
+      const bool ok = c < totB && sum <= A.D;
+      const unsigned long long mask = __ballot(ok);
+      const int pos = nb + __popcll(mask & ((1ull << tid) - 1ull));
+      if (ok) {
+        bcode[pos] = code;
+        bpos[c] = pos;
+      }
+      nb += __popcll(mask);
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    int nk = 0;
+    for (int c0 = 0; c0 < tot; c0 += 64) {
+      const int c = c0 + tid;
+      int sum = 0, codeA = 0, cB = c % totB;
+      if (c < tot) {
+        int r = c;
+        for (int l = A.N - 1; l >= 0; --l) {
+          const int d = r % DB;
+          r /= DB;
+          sum += d;
+          if (l < A.NA) codeA |= d << (4 * (A.NA - 1 - l));
+        }
+      }
+      const bool ok = c < tot && sum <= A.D;
+      const unsigned long long mask = __ballot(ok);
+      const int pos = nk + __popcll(mask & ((1ull << tid) - 1ull));
+      if (ok) {
+        kA[pos] = codeA;
+        kB[pos] = bpos[cB];
+      }
+      nk += __popcll(mask);
+    }
+  }
+  __syncthreads();
+  double acc = 0.0;
+  int degA[2] = {0, 0}, bk = 0;
+  const bool has_k = tid < A.ncoef;
+  if (has_k) {
+    const int codeA = kA[tid];
+    bk = kB[tid];
+    degA[0] = A.NA == 2 ? (codeA >> 4) & 15 : codeA & 15;
+    degA[1] = codeA & 15;
+  }
+
+  for (int mA0 = 0; mA0 < A.QA; mA0 += A.R) {
+    const int R = min(A.R, A.QA - mA0);
+    // V at the nodes of this chunk
+    for (int e = tid; e < R * A.QB; e += kGhThreads) {
+      int m = mA0 * A.QB + e;  // grid point index, digits in base Q, last axis fastest
+      double xv[kGhMaxN];
+#pragma unroll
+      for (int l = kGhMaxN - 1; l >= 0; --l) {
+        xv[l] = 0.0;
+        if (l < A.N) {
+          const int q = m / Q;
+          xv[l] = xis[m - q * Q];
+          m = q;
+        }
+      }
+      double F = 0.0;
+#pragma unroll
+      for (int i = 0; i < kGhMaxG; ++i) {
+        if (i < A.G) {
+          double r2 = 0.0;
+#pragma unroll
+          for (int l = 0; l < kGhMaxN; ++l) {
+            if (l < A.N) {
+              const double dx = xv[l] - cen[i][l];
+              r2 = fma(dx, dx, r2);
+            }
+          }
+          F -= amp[i] * exp(-r2 * inv2s2);
+        }
+      }
+      Fc[e] = F;
+    }
+    __syncthreads();
+    // trailing-half projections
+    if (A.NB == 2) {
+      // T[r][m0][a1] = sum_m1 F[r][m0 Q + m1] hq[a1][m1]
+      for (int e = tid; e < R * Q * DB; e += kGhThreads) {
+        const int a1 = e % DB, rm0 = e / DB;
+        const double *Fr = Fc + (int64_t)rm0 * Q;
+        const double *h = hqs + a1 * Q;
+        double sum = 0.0;
+        for (int m1 = 0; m1 < Q; ++m1) sum = fma(Fr[m1], h[m1], sum);
+        Tc[e] = sum;
+      }
+      __syncthreads();
+      // S[r][b] = sum_m0 hq[a0][m0] T[r][m0][a1]
+      for (int e = tid; e < R * A.nB; e += kGhThreads) {
+        const int r = e / A.nB, b = e % A.nB;
+        const int a0 = (bcode[b] >> 4) & 15, a1 = bcode[b] & 15;
+        const double *Tr = Tc + (int64_t)r * Q * DB + a1;
+        const double *h = hqs + a0 * Q;
+        double sum = 0.0;
+        for (int m0 = 0; m0 < Q; ++m0) sum = fma(h[m0], Tr[m0 * DB], sum);
+        Sc[e] = sum;
+      }
+    } else if (A.NB == 1) {
+      for (int e = tid; e < R * A.nB; e += kGhThreads) {
+        const int r = e / A.nB, b = e % A.nB;
+        const double *Fr = Fc + (int64_t)r * Q;
+        const double *h = hqs + (bcode[b] & 15) * Q;
+        double sum = 0.0;
+        for (int m = 0; m < Q; ++m) sum = fma(Fr[m], h[m], sum);
+        Sc[e] = sum;
+      }
+    } else {
+      for (int r = tid; r < R; r += kGhThreads) Sc[r] = Fc[r];
+    }
+    __syncthreads();
+    // leading-half projections, accumulated per coefficient
+    if (has_k) {
+      double sum = 0.0;
+      for (int r = 0; r < R; ++r) {
+        const int m = mA0 + r;
+        double h = Sc[r * A.nB + bk];
+        if (A.NA == 2) {
+          const int m0 = m / Q;
+          h *= hqs[degA[0] * Q + m0] * hqs[degA[1] * Q + (m - m0 * Q)];
+        } else {
+          h *= hqs[degA[1] * Q + m];
+        }
+        sum += h;
+      }
+      acc += sum;
+    }
+    __syncthreads();
+  }
+  if (has_k) coef[(int64_t)s * A.ncoef + tid] = acc;
+}
+
+static int64_t binom(int n, int k) {
+  int64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// ---------------------------------------------------------------------------------------
+// BF16 MFMA GEMM with fused epilogues
+//   C(i, j) = sum_k A(i, k) B(k, j), A(i, k) = A[i sa0 + k sa1], B(k, j) = B[k sb0 + j sb1]
+// FP32 operands in memory, rounded to BF16 when loaded into the MFMA fragments, FP32
+// accumulation.  One wave per 16 x 16 output tile; lane l holds A row l%16 and B column
+// l%16 for the K slice [8 (l/16), 8 (l/16) + 8) of each 32-wide step, and the outputs
+// rows 4 (l/16) .. +3 of column l%16.
+// ---------------------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+enum GemmEpi { kEpiStore = 0, kEpiBiasSilu = 1, kEpiSiluGrad = 2 };
+
+__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + expf(-z)); }
+__device__ __forceinline__ float silu_grad_f(float z) {
+  const float s = 1.0f / (1.0f + expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(256)
+k_gemm_bf16(int M, int N, int K, const float *__restrict__ A, int64_t sa0, int64_t sa1,
+            const float *__restrict__ B, int64_t sb0, int64_t sb1, float *__restrict__ C, int64_t ldc,
+            const float *__restrict__ bias, float *__restrict__ Z, float *__restrict__ H,
+            const float *__restrict__ Zin) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tiles_n = (N + 15) / 16;
+  const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+  const int ti = (int)(tile / tiles_n), tj = (int)(tile % tiles_n);
+  if (ti * 16 >= M) return;
+  const int i = ti * 16 + (lane & 15);   // A row of this lane
+  const int j = tj * 16 + (lane & 15);   // B column of this lane
+  const int kq = (lane >> 4) * 8;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + kq + e;
+      const float av = (i < M && k < K) ? A[(int64_t)i * sa0 + (int64_t)k * sa1] : 0.f;
+      const float bv = (j < N && k < K) ? B[(int64_t)k * sb0 + (int64_t)j * sb1] : 0.f;
+      a[e] = (__bf16)av;
+      b[e] = (__bf16)bv;
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int oi = ti * 16 + (lane >> 4) * 4 + r;
+    const int oj = tj * 16 + (lane & 15);
+    if (oi >= M || oj >= N) continue;
+    float v = acc[r];
+    if constexpr (EPI == kEpiStore) {
+      if (bias) v += bias[oj];
+      C[(int64_t)oi * ldc + oj] = v;
+    } else if constexpr (EPI == kEpiBiasSilu) {
+      v += bias[oj];
+      Z[(int64_t)oi * ldc + oj] = v;
+      H[(int64_t)oi * ldc + oj] = silu_f(v);
+    } else {
+      C[(int64_t)oi * ldc + oj] = v * silu_grad_f(Zin[(int64_t)oi * ldc + oj]);
+    }
+  }
+}
+
+// column sums of X (rows x cols) in a fixed order: out[j] = sum_i X[i][j]
+__global__ void __launch_bounds__(256) k_colsum(int rows, int cols, const float *__restrict__ X,
+                                                float *__restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  float s = 0.f;
+  for (int i = 0; i < rows; ++i) s += X[(int64_t)i * cols + j];
+  out[j] = s;
+}
+
+// xn = 2 (x - lo) / (hi - lo) - 1, padded with zeros to ldx columns
+__global__ void k_norm_in(int batch, int in, int ldx, const double *__restrict__ x,
+                          const float *__restrict__ lo, const float *__restrict__ hi,
+                          float *__restrict__ xn) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)batch * ldx) return;
+  const int i = (int)(idx / ldx), k = (int)(idx % ldx);
+  xn[idx] = k < in ? (float)(2.0 * (x[(int64_t)i * in + k] - lo[k]) / ((double)hi[k] - lo[k]) - 1.0) : 0.f;
+}
+
+// tn = (target - mean) / std
+__global__ void k_norm_out(int64_t n, int out, const double *__restrict__ tg, const float *__restrict__ mean,
+                           const float *__restrict__ sd, float *__restrict__ tn) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int j = (int)(idx % out);
+  tn[idx] = (float)((tg[idx] - mean[j]) / sd[j]);
+}
+
+// coef = y * std + mean (float64 output)
+__global__ void k_denorm_out(int64_t n, int out, const float *__restrict__ y, const float *__restrict__ mean,
+                             const float *__restrict__ sd, double *__restrict__ coef) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int j = (int)(idx % out);
+  coef[idx] = (double)y[idx] * (double)sd[j] + (double)mean[j];
+}
+
+// d = y - t; dY = 2 d / n; loss = mean d^2 (one block, fixed order)
+__global__ void __launch_bounds__(256) k_mse(int64_t n, const float *__restrict__ y, const float *__restrict__ t,
+                                             float *__restrict__ dy, float *__restrict__ loss) {
+  __shared__ float sh[256];
+  float acc = 0.f;
+  const float sc = 2.0f / (float)n;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const float d = y[i] - t[i];
+    dy[i] = sc * d;
+    acc += d * d;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) *loss = sh[0] / (float)n;
+}
+
+// Adam with bias correction; step counter in *tstep (incremented by the first thread
+// of block 0 after every thread has read it: the counter is read from a copy)
+__global__ void __launch_bounds__(256) k_adam(int64_t n, float *__restrict__ w, const float *__restrict__ g,
+                                              float *__restrict__ m, float *__restrict__ v, float lr,
+                                              const int32_t *__restrict__ tstep) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const int t = *tstep + 1;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / (1.f - powf(b1, (float)t));
+  const float vh = vi / (1.f - powf(b2, (float)t));
+  w[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void k_step_inc(int32_t *tstep) {
+  if (threadIdx.x == 0) *tstep += 1;
+}
+
+}  // namespace hs
+
+// ---------------------------------------------------------------------------------------
+// MLP handle and C ABI
+// ---------------------------------------------------------------------------------------
+struct hs_mlp_s {
+  int32_t in = 0, hid = 0, out = 0, kin = 32;
+  int64_t nparam = 0;
+  // parameter offsets (floats) inside one weights array
+  int64_t oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
+  // device block layout (bytes) for a given max batch
+  int32_t max_batch = 0;
+  int64_t off_w = 0, off_m = 0, off_v = 0, off_g = 0, off_norm = 0, off_t = 0, off_loss = 0,
+          off_x = 0, off_z1 = 0, off_h1 = 0, off_z2 = 0, off_h2 = 0, off_y = 0, off_tn = 0,
+          off_dy = 0, off_dz2 = 0, off_dz1 = 0, dev_bytes = 0;
+  void layout(int32_t mb) {
+    max_batch = mb;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+      int64_t o = off;
+      off = hs::align_up(off + std::max<int64_t>(bytes, 1), 256);
+      return o;
+    };
+    off_w = take(4 * nparam);
+    off_m = take(4 * nparam);
+    off_v = take(4 * nparam);
+    off_g = take(4 * nparam);
+    off_norm = take(4 * (2 * in + 2 * out));
+    off_t = take(4);
+    off_loss = take(4);
+    off_x = take(4 * (int64_t)mb * kin);
+    off_z1 = take(4 * (int64_t)mb * hid);
+    off_h1 = take(4 * (int64_t)mb * hid);
+    off_z2 = take(4 * (int64_t)mb * hid);
+    off_h2 = take(4 * (int64_t)mb * hid);
+    off_y = take(4 * (int64_t)mb * out);
+    off_tn = take(4 * (int64_t)mb * out);
+    off_dy = take(4 * (int64_t)mb * out);
+    off_dz2 = take(4 * (int64_t)mb * hid);
+    off_dz1 = take(4 * (int64_t)mb * hid);
+    dev_bytes = off;
+  }
+};
+
+namespace {
+
+inline float *F(void *dev, int64_t off) { return reinterpret_cast<float *>(static_cast<uint8_t *>(dev) + off); }
+
+template <int EPI>
+void gemm(hipStream_t s, int M, int N, int K, const float *A, int64_t sa0, int64_t sa1, const float *B,
+          int64_t sb0, int64_t sb1, float *C, int64_t ldc, const float *bias = nullptr, float *Z = nullptr,
+          float *H = nullptr, const float *Zin = nullptr) {
+  const int64_t tiles = (int64_t)((M + 15) / 16) * ((N + 15) / 16);
+  const unsigned blocks = (unsigned)((tiles + 3) / 4);
+  hipLaunchKernelGGL((hs::k_gemm_bf16<EPI>), dim3(blocks), dim3(256), 0, s, M, N, K, A, sa0, sa1, B, sb0,
+                     sb1, C, ldc, bias, Z, H, Zin);
+}
+
+int32_t mlp_forward(hs_mlp_s *p, void *dev, int batch, hipStream_t s) {
+  float *w = F(dev, p->off_w);
+  const int in = p->in, hid = p->hid, out = p->out, kin = p->kin;
+  (void)in;
+  // Z1 = Xn W1^T + b1, H1 = silu(Z1)
+  gemm<hs::kEpiBiasSilu>(s, batch, hid, p->in, F(dev, p->off_x), kin, 1, w + p->oW1, 1, p->in, nullptr, hid,
+                         w + p->ob1, F(dev, p->off_z1), F(dev, p->off_h1));
+  gemm<hs::kEpiBiasSilu>(s, batch, hid, hid, F(dev, p->off_h1), hid, 1, w + p->oW2, 1, hid, nullptr, hid,
+                         w + p->ob2, F(dev, p->off_z2), F(dev, p->off_h2));
+  gemm<hs::kEpiStore>(s, batch, out, hid, F(dev, p->off_h2), hid, 1, w + p->oW3, 1, hid, F(dev, p->off_y), out,
+                      w + p->ob3);
+  HS_HIP(hipGetLastError());
+  return HS_OK;
+}
+
+}  // namespace
+
+namespace {
+
+int32_t gh_launch(int32_t N, int32_t G, int32_t D, int32_t Q, const double *geometry_host, int32_t nsamp,
+                  const double *params_dev, double *coef_dev, const float *lo, const float *hi, int32_t *used,
+                  hipStream_t stream) {
+  using hs::GhArgs;
+  if (N < 1 || N > hs::kGhMaxN || G < 1 || G > hs::kGhMaxG || D < 0 || D > hs::kGhMaxD || Q < 1 ||
+      Q > hs::kGhMaxQ || nsamp < 0 || !geometry_host || (nsamp > 0 && (!params_dev || !coef_dev)))
+    return hs::fail(HS_E_INVALID, "Gauss-Hermite projection: arguments out of range (N<=4, G<=4, D<=8, Q<=32)");
+  GhArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.N = N;
+  A.G = G;
+  A.D = D;
+  A.Q = Q;
+  A.NA = (N + 1) / 2;
+  A.NB = N - A.NA;
+  A.QA = 1;
+  for (int l = 0; l < A.NA; ++l) A.QA *= Q;
+  A.QB = 1;
+  for (int l = 0; l < A.NB; ++l) A.QB *= Q;
+  A.nB = (int)hs::binom(A.NB + D, A.NB);
+  A.ncoef = (int)hs::binom(N + D, N);
+  // rows of the leading grid per LDS chunk: as many as fit in the LDS budget
+  const size_t fixed = hs::GhLds::make(0, A.QB, Q, D, A.nB, A.NB, A.ncoef).bytes();
+  const size_t per_row = sizeof(double) * ((size_t)A.QB + (A.NB == 2 ? (size_t)Q * (D + 1) : 0) + A.nB);
+  const int64_t fit = fixed < hs::kGhLdsBytes ? (int64_t)((hs::kGhLdsBytes - fixed) / per_row) : 0;
+  A.R = (int)std::min<int64_t>({(int64_t)A.QA, fit, hs::kGhChunk});
+  const size_t lds = hs::GhLds::make(A.R, A.QB, Q, D, A.nB, A.NB, A.ncoef).bytes();
+  if (A.R < 1 || lds > hs::kGhLdsBytes || A.ncoef > hs::kGhThreads)
+    return hs::fail(HS_E_UNSUPPORTED, "Gauss-Hermite projection: workspace exceeds LDS");
+  std::vector<double> xi, wq;
+  hs::gh_rule(Q, xi, wq);
+  for (int m = 0; m < Q; ++m) {
+    A.xi[m] = xi[m];
+    // H_n(x) by the physicists' recurrence; scaled by w_m / (sqrt(pi) 2^n n!)
+    double hm = 0.0, hc = 1.0, fact = 1.0;
+    for (int n = 0; n <= D; ++n) {
+      if (n > 0) fact *= n;
+      A.hq[n][m] = wq[m] * hc / (std::sqrt(M_PI) * std::ldexp(1.0, n) * fact);
+      const double hn = 2.0 * xi[m] * hc - 2.0 * n * hm;
+      hm = hc;
+      hc = hn;
+    }
+  }
+  const double *g = geometry_host;
+  for (int i = 0; i < G; ++i)
+    for (int l = 0; l < N; ++l) {
+      A.base[i][l] = g[i * N + l];
+      A.u[i][l] = g[G * N + i * N + l];
+      A.w[i][l] = g[2 * G * N + i * N + l];
+    }
+  for (int i = 0; i < G; ++i) A.phase[i] = g[3 * G * N + i];
+  if (nsamp == 0) return HS_OK;
+  hipLaunchKernelGGL(hs::k_gh_project, dim3(nsamp), dim3(hs::kGhThreads), lds, stream, A, params_dev, coef_dev,
+                     lo, hi, used);
+  HS_HIP(hipGetLastError());
+  return HS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t hs_gh_ncoef(int32_t N, int32_t D, int32_t *ncoef) {
+  if (!ncoef || N < 1 || D < 0) return hs::fail(HS_E_INVALID, "hs_gh_ncoef: bad arguments");
+  *ncoef = (int32_t)hs::binom(N + D, N);
+  return HS_OK;
+}
+
+int32_t hs_gh_project(int32_t N, int32_t G, int32_t D, int32_t Q, const double *geometry_host,
+                      int32_t nsamp, const double *params_dev, double *coef_dev, void *stream) {
+  return gh_launch(N, G, D, Q, geometry_host, nsamp, params_dev, coef_dev, nullptr, nullptr, nullptr,
+                   static_cast<hipStream_t>(stream));
+}
+
+int32_t hs_mlp_create(int32_t in, int32_t hidden, int32_t out, hs_mlp *mlp) {
+  if (!mlp) return hs::fail(HS_E_INVALID, "hs_mlp_create: out is NULL");
+  *mlp = nullptr;
+  if (in < 1 || in > 32 || hidden < 64 || hidden > 512 || hidden % 64 || out < 1 || out > 512)
+    return hs::fail(HS_E_INVALID, "hs_mlp_create: need in <= 32, hidden a multiple of 64 in 64..512, out <= 512");
+  hs_mlp_s *p = new (std::nothrow) hs_mlp_s();
+  if (!p) return hs::fail(HS_E_NOMEM, "hs_mlp_create: out of host memory");
+  p->in = in;
+  p->hid = hidden;
+  p->out = out;
+  int64_t o = 0;
+  p->oW1 = o;
+  o += (int64_t)hidden * in;
+  p->ob1 = o;
+  o += hidden;
+  p->oW2 = o;
+  o += (int64_t)hidden * hidden;
+  p->ob2 = o;
+  o += hidden;
+  p->oW3 = o;
+  o += (int64_t)out * hidden;
+  p->ob3 = o;
+  o += out;
+  p->nparam = o;
+  *mlp = p;
+  return HS_OK;
+}
+
+int32_t hs_mlp_destroy(hs_mlp mlp) {
+  delete mlp;
+  return HS_OK;
+}
+
+int32_t hs_mlp_device_bytes(hs_mlp mlp, int32_t max_batch, int64_t *bytes) {
+  if (!mlp || !bytes || max_batch < 1) return hs::fail(HS_E_INVALID, "hs_mlp_device_bytes: bad arguments");
+  mlp->layout(max_batch);
+  *bytes = mlp->dev_bytes;
+  return HS_OK;
+}
+
+int32_t hs_mlp_upload_params(hs_mlp mlp, void *dev, const float *weights_host, const float *norm_host,
+                             void *stream) {
+  if (!mlp || !dev || !weights_host || !norm_host) return hs::fail(HS_E_INVALID, "hs_mlp_upload_params: NULL argument");
+  if (mlp->max_batch < 1) return hs::fail(HS_E_INVALID, "hs_mlp_upload_params: call hs_mlp_device_bytes first");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HS_HIP(hipMemcpyAsync(F(dev, mlp->off_w), weights_host, 4 * mlp->nparam, hipMemcpyHostToDevice, s));
+  HS_HIP(hipMemcpyAsync(F(dev, mlp->off_norm), norm_host, 4 * (2 * mlp->in + 2 * mlp->out), hipMemcpyHostToDevice, s));
+  // Adam moments and the step counter start at zero (fill kernels, no memset nodes)
+  std::vector<float> zeros(mlp->nparam, 0.f);
+  HS_HIP(hipMemcpyAsync(F(dev, mlp->off_m), zeros.data(), 4 * mlp->nparam, hipMemcpyHostToDevice, s));
+  HS_HIP(hipMemcpyAsync(F(dev, mlp->off_v), zeros.data(), 4 * mlp->nparam, hipMemcpyHostToDevice, s));
+  HS_HIP(hipMemcpyAsync(F(dev, mlp->off_t), zeros.data(), 4, hipMemcpyHostToDevice, s));
+  HS_HIP(hipStreamSynchronize(s));  // the host staging above is pageable and short-lived
+  return HS_OK;
+}
+
+int32_t hs_mlp_download_params(hs_mlp mlp, const void *dev, float *weights_host, void *stream) {
+  if (!mlp || !dev || !weights_host) return hs::fail(HS_E_INVALID, "hs_mlp_download_params: NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HS_HIP(hipMemcpyAsync(weights_host, F(const_cast<void *>(dev), mlp->off_w), 4 * mlp->nparam,
+                        hipMemcpyDeviceToHost, s));
+  HS_HIP(hipStreamSynchronize(s));
+  return HS_OK;
+}
+
+int32_t hs_mlp_predict(hs_mlp mlp, void *dev, int32_t batch, const double *x_dev, double *coef_dev,
+                       void *stream) {
+  if (!mlp || !dev || !x_dev || !coef_dev) return hs::fail(HS_E_INVALID, "hs_mlp_predict: NULL argument");
+  if (batch < 1 || batch > mlp->max_batch) return hs::fail(HS_E_WORKSPACE, "hs_mlp_predict: batch above max_batch");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const float *nrm = F(dev, mlp->off_norm);
+  const int64_t nx = (int64_t)batch * mlp->kin;
+  hipLaunchKernelGGL(hs::k_norm_in, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, batch, mlp->in, mlp->kin,
+                     x_dev, nrm, nrm + mlp->in, F(dev, mlp->off_x));
+  int32_t st = mlp_forward(mlp, dev, batch, s);
+  if (st != HS_OK) return st;
+  const int64_t ny = (int64_t)batch * mlp->out;
+  hipLaunchKernelGGL(hs::k_denorm_out, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s, ny, mlp->out,
+                     F(dev, mlp->off_y), nrm + 2 * mlp->in, nrm + 2 * mlp->in + mlp->out, coef_dev);
+  HS_HIP(hipGetLastError());
+  return HS_OK;
+}
+
+int32_t hs_sur_coeffs(hs_mlp mlp, void *dev, int32_t N, int32_t G, int32_t D, int32_t Q,
+                      const double *geometry_host, int32_t nsamp, const double *params_dev, double *coef_dev,
+                      int32_t *used_quad_dev, void *stream) {
+  if (!mlp || !dev) return hs::fail(HS_E_INVALID, "hs_sur_coeffs: NULL network");
+  if (mlp->in != G + 4 || N < 1 || D < 0 || mlp->out != (int32_t)hs::binom(N + D, N))
+    return hs::fail(HS_E_INVALID, "hs_sur_coeffs: network shape does not match (4 + G inputs, C(N+D, N) outputs)");
+  if (nsamp == 0) return HS_OK;
+  int32_t st = hs_mlp_predict(mlp, dev, nsamp, params_dev, coef_dev, stream);
+  if (st != HS_OK) return st;
+  const float *nrm = F(dev, mlp->off_norm);
+  return gh_launch(N, G, D, Q, geometry_host, nsamp, params_dev, coef_dev, nrm, nrm + mlp->in, used_quad_dev,
+                   static_cast<hipStream_t>(stream));
+}
+
+int32_t hs_mlp_train_step(hs_mlp mlp, void *dev, int32_t batch, const double *x_dev, const double *target_dev,
+                          float lr, float *loss_dev, float *grads_dev, void *stream) {
+  if (!mlp || !dev || !x_dev || !target_dev) return hs::fail(HS_E_INVALID, "hs_mlp_train_step: NULL argument");
+  if (batch < 1 || batch > mlp->max_batch) return hs::fail(HS_E_WORKSPACE, "hs_mlp_train_step: batch above max_batch");
+  if (!std::isfinite(lr)) return hs::fail(HS_E_NONFINITE, "hs_mlp_train_step: lr not finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int in = mlp->in, hid = mlp->hid, out = mlp->out, kin = mlp->kin;
+  float *w = F(dev, mlp->off_w), *g = grads_dev ? grads_dev : F(dev, mlp->off_g);
+  const float *nrm = F(dev, mlp->off_norm);
+  const int64_t nx = (int64_t)batch * kin, ny = (int64_t)batch * out;
+  hipLaunchKernelGGL(hs::k_norm_in, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, batch, in, kin, x_dev, nrm,
+                     nrm + in, F(dev, mlp->off_x));
+  hipLaunchKernelGGL(hs::k_norm_out, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s, ny, out, target_dev,
+                     nrm + 2 * in, nrm + 2 * in + out, F(dev, mlp->off_tn));
+  int32_t st = mlp_forward(mlp, dev, batch, s);
+  if (st != HS_OK) return st;
+  hipLaunchKernelGGL(hs::k_mse, dim3(1), dim3(256), 0, s, ny, F(dev, mlp->off_y), F(dev, mlp->off_tn),
+                     F(dev, mlp->off_dy), loss_dev ? loss_dev : F(dev, mlp->off_loss));
+  float *dy = F(dev, mlp->off_dy), *h2 = F(dev, mlp->off_h2), *h1 = F(dev, mlp->off_h1);
+  float *dz2 = F(dev, mlp->off_dz2), *dz1 = F(dev, mlp->off_dz1), *xn = F(dev, mlp->off_x);
+  // layer 3: dW3 = dY^T H2, db3 = colsum dY, dZ2 = (dY W3) * silu'(Z2)
+  gemm<hs::kEpiStore>(s, out, hid, batch, dy, 1, out, h2, hid, 1, g + mlp->oW3, hid);
+  hipLaunchKernelGGL(hs::k_colsum, dim3((out + 255) / 256), dim3(256), 0, s, batch, out, dy, g + mlp->ob3);
+  gemm<hs::kEpiSiluGrad>(s, batch, hid, out, dy, out, 1, w + mlp->oW3, hid, 1, dz2, hid, nullptr, nullptr, nullptr,
+                         F(dev, mlp->off_z2));
+  // layer 2
+  gemm<hs::kEpiStore>(s, hid, hid, batch, dz2, 1, hid, h1, hid, 1, g + mlp->oW2, hid);
+  hipLaunchKernelGGL(hs::k_colsum, dim3((hid + 255) / 256), dim3(256), 0, s, batch, hid, dz2, g + mlp->ob2);
+  gemm<hs::kEpiSiluGrad>(s, batch, hid, hid, dz2, hid, 1, w + mlp->oW2, hid, 1, dz1, hid, nullptr, nullptr, nullptr,
+                         F(dev, mlp->off_z1));
+  // layer 1
+  gemm<hs::kEpiStore>(s, hid, in, batch, dz1, 1, hid, xn, kin, 1, g + mlp->oW1, in);
+  hipLaunchKernelGGL(hs::k_colsum, dim3((hid + 255) / 256), dim3(256), 0, s, batch, hid, dz1, g + mlp->ob1);
+  // Adam
+  const unsigned ab = (unsigned)((mlp->nparam + 255) / 256);
+  hipLaunchKernelGGL(hs::k_adam, dim3(ab), dim3(256), 0, s, mlp->nparam, w, (const float *)g, F(dev, mlp->off_m),
+                     F(dev, mlp->off_v), lr, (const int32_t *)F(dev, mlp->off_t));
+  hipLaunchKernelGGL(hs::k_step_inc, dim3(1), dim3(64), 0, s, (int32_t *)F(dev, mlp->off_t));
+  HS_HIP(hipGetLastError());
+  return HS_OK;
+}
+
+}  // extern "C"

@@ -70,6 +70,7 @@ _SIGS = {
     "hs_mlp_download_params": [_vp, _vp, _pf32, _vp],
     "hs_mlp_predict": [_vp, _vp, _i32, _vp, _vp, _vp],
     "hs_mlp_train_step": [_vp, _vp, _i32, _vp, _vp, _f32, _vp, _vp, _vp],
+    "hs_sur_coeffs": [_vp, _vp, _i32, _i32, _i32, _i32, _pf64, _i32, _vp, _vp, _vp, _vp],
 }
 
 EXPORTED = sorted(list(_SIGS) + ["hs_version"])
@@ -213,6 +214,10 @@ class Pot:
     def set_time(self, t: float):
         hs_pot_set_time(self.h, ptr(self.dev), float(t), None, stream_ptr())
 
+    def set_coeffs_device(self, coef):
+        """Base coefficients from a device float64 tensor (nterms values, term order)."""
+        hs_pot_set_coeffs_device(self.h, ptr(self.dev), ptr(coef), stream_ptr())
+
     def __del__(self):
         try:
             if getattr(self, "h", None):
@@ -299,6 +304,106 @@ class Batch:
         try:
             if getattr(self, "h", None):
                 _lib.hs_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+# ---- learned coefficients -----------------------------------------------------------
+
+
+def gh_ncoef(N: int, D: int) -> int:
+    n = C.c_int32()
+    hs_gh_ncoef(N, D, C.byref(n))
+    return n.value
+
+
+def geometry_array(geom) -> np.ndarray:
+    """Host geometry block: base, u, w (G x N each), then phase (G)."""
+    return np.ascontiguousarray(np.concatenate([np.asarray(geom[k], dtype=np.float64).ravel()
+                                                for k in ("base", "u", "w", "phase")]))
+
+
+def gh_project(geom, params, D: int, Q: int, out=None):
+    """Gauss-Hermite coefficients for every row of params (device float64, nsamp x (4+G))."""
+    torch = _torch()
+    base = np.asarray(geom["base"])
+    G, N = base.shape
+    nc = gh_ncoef(N, D)
+    ns = params.shape[0]
+    if out is None:
+        out = torch.empty((ns, nc), dtype=torch.float64, device=params.device)
+    g = geometry_array(geom)
+    hs_gh_project(N, G, D, Q, g.ctypes.data_as(_pf64), ns, ptr(params), ptr(out), stream_ptr())
+    return out
+
+
+class MLP:
+    """in -> hidden -> hidden -> out SiLU network; weights and Adam state on the device."""
+
+    def __init__(self, n_in: int, hidden: int, n_out: int, max_batch: int, device="cuda"):
+        h = _vp()
+        hs_mlp_create(n_in, hidden, n_out, C.byref(h))
+        self.h, self.n_in, self.hidden, self.n_out = h, n_in, hidden, n_out
+        self.max_batch = max_batch
+        nb = C.c_int64()
+        hs_mlp_device_bytes(h, max_batch, C.byref(nb))
+        self.dev = dev_buffer(nb.value, device)
+        self.nparam = hidden * n_in + hidden + hidden * hidden + hidden + n_out * hidden + n_out
+
+    def upload(self, params: dict, in_lo, in_hi, out_mean, out_std):
+        """params: W1, b1, W2, b2, W3, b3 (float arrays); also resets Adam."""
+        w = np.ascontiguousarray(np.concatenate([np.asarray(params[k], dtype=np.float32).ravel()
+                                                 for k in ("W1", "b1", "W2", "b2", "W3", "b3")]))
+        assert w.size == self.nparam
+        nrm = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float32).ravel()
+                                                   for x in (in_lo, in_hi, out_mean, out_std)]))
+        assert nrm.size == 2 * self.n_in + 2 * self.n_out
+        hs_mlp_upload_params(self.h, ptr(self.dev), w.ctypes.data_as(_pf32), nrm.ctypes.data_as(_pf32),
+                             stream_ptr())
+
+    def unflatten(self, w: np.ndarray) -> dict:
+        i, H, o = self.n_in, self.hidden, self.n_out
+        shapes = [("W1", (H, i)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (o, H)), ("b3", (o,))]
+        out, k = {}, 0
+        for name, shp in shapes:
+            n = int(np.prod(shp))
+            out[name] = w[k:k + n].reshape(shp)
+            k += n
+        return out
+
+    def download(self) -> dict:
+        w = np.empty(self.nparam, dtype=np.float32)
+        hs_mlp_download_params(self.h, ptr(self.dev), w.ctypes.data_as(_pf32), stream_ptr())
+        return self.unflatten(w)
+
+    def predict(self, x, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((x.shape[0], self.n_out), dtype=torch.float64, device=x.device)
+        hs_mlp_predict(self.h, ptr(self.dev), x.shape[0], ptr(x), ptr(out), stream_ptr())
+        return out
+
+    def coeffs(self, geom, params, D: int, Q: int, out=None, used=None):
+        """Network coefficients, quadrature for rows outside the training box."""
+        torch = _torch()
+        base = np.asarray(geom["base"])
+        G, N = base.shape
+        if out is None:
+            out = torch.empty((params.shape[0], self.n_out), dtype=torch.float64, device=params.device)
+        g = geometry_array(geom)
+        hs_sur_coeffs(self.h, ptr(self.dev), N, G, D, Q, g.ctypes.data_as(_pf64), params.shape[0],
+                      ptr(params), ptr(out), ptr(used), stream_ptr())
+        return out
+
+    def train_step(self, x, target, lr: float, loss=None, grads=None):
+        hs_mlp_train_step(self.h, ptr(self.dev), x.shape[0], ptr(x), ptr(target), float(lr),
+                          ptr(loss), ptr(grads), stream_ptr())
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                _lib.hs_mlp_destroy(self.h)
                 self.h = None
         except Exception:
             pass
