@@ -7,18 +7,28 @@ harmonic-oscillator coherent state displaced to x_d = 2 normalised on K, exponen
 midpoint steps of h = 0.005 with m = 10 Lanczos vectors and one Gram-Schmidt pass.
 
 One timed "step" is one full time step: coefficient update, 10 applications of H,
-the Lanczos recurrences and reductions, the small eigensolve and the combination.
-value = H applications per second over the timed region.
+the Lanczos recurrences and reductions, the small eigensolve and the combination,
+replayed as one captured HIP graph.  value = H applications per second.
 
 Also measured inside this run:
-  roofline      -- the H-application kernel timed back to back with HIP events on its
-                   own stream; algorithmic bytes 32 |K| per launch (read c, write H c,
-                   complex128) against 8 TB/s.
+  roofline      -- the H-application kernel (one launch per application) timed back to
+                   back with HIP events on its own stream; algorithmic bytes 32 |K| per
+                   launch (read c, write H c, complex128) against 8 TB/s.  traffic comes
+                   from the committed counter summary, and only while the kernel sources
+                   still hash to the value recorded with it.
+  forms         -- the FP32 form (complex64 matvec, float64 reductions) on the same
+                   workload with its error against the float64 run, and the batched form
+                   (256 instances, one persistent launch per H application) against the
+                   same instances stepped one by one.
   cpu_baseline  -- the CPU oracle's fast algorithm on the same workload (rank 0 only).
+
+--calibrate-copy MIB runs only a device-to-device copy of that size (the reference
+kernel for scaling the byte counters) and exits.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +39,71 @@ sys.path.insert(0, ROOT)
 
 N_DIM, B_BOUND, M_KRYLOV, H_STEP = 6, 4096, 10, 0.005
 HBM_PEAK_GBS = 8000.0
+METRIC = "Galerkin matvecs/s + HBM GB/s (% peak), batched/FP32 vs plain FP64 at 1e-10"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hh_long_N6_B4096_traffic.json")
+# sources whose change invalidates the recorded counter traffic of the H kernel
+KERNEL_SOURCES = ["paper_1403_3511_amd/csrc/matvec_long.h", "paper_1403_3511_amd/csrc/matvec_long_f64.hip",
+                  "paper_1403_3511_amd/csrc/dev_common.h", "paper_1403_3511_amd/csrc/hs_internal.h",
+                  "paper_1403_3511_amd/csrc/index.cpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch from the committed counter runs, or None if absent or stale."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash() or rec.get("kernel") != kernel:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def event_time_ms(fn, reps, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def capture(fn, stream):
+    """One replayable HIP graph of fn (captured on a side stream)."""
+    import torch
+    g = torch.cuda.CUDAGraph()
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(stream)
+    with torch.cuda.stream(s2):
+        with torch.cuda.graph(g, stream=s2):
+            fn()
+    stream.wait_stream(s2)
+    torch.cuda.synchronize()
+    return g
+
+
+def calibrate_copy(mib: int, reps: int = 5):
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                      "reps": reps}), flush=True)
 
 
 def main():
@@ -40,11 +115,17 @@ def main():
     ap.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph")
     ap.add_argument("--tile-dim", type=int, default=0)
     ap.add_argument("--matvec-reps", type=int, default=50)
+    ap.add_argument("--forms", type=int, default=1, help="also measure the FP32 and batched forms")
+    ap.add_argument("--batch-log2-bmax", type=float, default=10.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU path is not built "
-              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        print("bench.py: this build runs on one GPU only; --gpus above 1 is not supported "
+              "(the sharded path is described but not built).", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
 
     import numpy as np
     import torch
@@ -61,75 +142,62 @@ def main():
     k = idx.multi_indices()
     c0 = coherent_state(k, 2.0)
     c0 /= np.linalg.norm(c0)
-    c = torch.from_numpy(c0).to(dev)
-    ws = hs.workspace(idx, pot, hs.HS_C128, M_KRYLOV)
-    t_dev = torch.zeros(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    def one_step():
-        hs.step(idx, pot, c, 0.0, H_STEP, M_KRYLOV, dtype=hs.HS_C128, reorth=True, ws=ws, t_dev=t_dev)
+    def stepper(dtype, c):
+        ws = hs.workspace(idx, pot, dtype, M_KRYLOV)
+        t_dev = torch.zeros(1, dtype=torch.float64, device=dev)
 
+        def one():
+            hs.step(idx, pot, c, 0.0, H_STEP, M_KRYLOV, dtype=dtype, reorth=True, ws=ws, t_dev=t_dev)
+        return one, t_dev
+
+    c = torch.from_numpy(c0).to(dev)
+    one_step, _ = stepper(hs.HS_C128, c)
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
-
-    graph = None
+    run = one_step
     if args.graph:
-        graph = torch.cuda.CUDAGraph()
-        s2 = torch.cuda.Stream()
-        s2.wait_stream(stream)
-        with torch.cuda.stream(s2):
-            with torch.cuda.graph(graph, stream=s2):
-                hs.step(idx, pot, c, 0.0, H_STEP, M_KRYLOV, dtype=hs.HS_C128, reorth=True,
-                        ws=ws, t_dev=t_dev)
-        stream.wait_stream(s2)
-        torch.cuda.synchronize()
-        graph.replay()  # one more warm step through the graph
-        torch.cuda.synchronize()
-
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        if graph is not None:
-            graph.replay()
-        else:
-            one_step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_total = e0.elapsed_time(e1)
+        g = capture(one_step, stream)
+        g.replay()  # one more warm step through the graph
+        run = g.replay
+    ms_total = event_time_ms(run, args.steps, stream)
     ms_per_step = ms_total / args.steps
     value = args.steps * M_KRYLOV / (ms_total / 1e3)
     norm_err = abs(float(torch.linalg.norm(c).item()) - 1.0)
 
-    # ---- dominant kernel: H application, back to back on this stream ----
+    # ---- dominant kernel: H application (one launch), back to back on this stream ----
     x = torch.from_numpy(c0).to(dev)
     y = torch.empty_like(x)
     aws = hs.workspace(idx, pot, hs.HS_C128, 0)
     pot.set_time(0.1)
     for _ in range(3):
         hs.apply_h(idx, pot, x, y, hs.HS_C128, aws)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.matvec_reps):
-        hs.apply_h(idx, pot, x, y, hs.HS_C128, aws)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    us_matvec = e0.elapsed_time(e1) * 1e3 / args.matvec_reps
+    us_matvec = event_time_ms(lambda: hs.apply_h(idx, pot, x, y, hs.HS_C128, aws), args.matvec_reps,
+                              stream) * 1e3 / args.matvec_reps
     alg_bytes = 32.0 * idx.size
     achieved = alg_bytes / (us_matvec * 1e-6) / 1e9
+    np_axes = N_DIM - idx.tile_dim
+    kernel = f"hs::k_hh_long<double, {N_DIM}, {np_axes}, false>" if pot.fused else "hs::k_pass<double>"
+    traffic = recorded_traffic(kernel)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_hh_rows<double>" if pot.fused else "k_pass<double>",
-                "us_per_launch": round(us_matvec, 2), "alg_bytes_per_launch": int(alg_bytes)}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": kernel, "us_per_launch": round(us_matvec, 2),
+                "alg_bytes_per_launch": int(alg_bytes)}
+
+    forms = None
+    if args.forms:
+        forms = {"fp64": {"matvec_per_s": round(value, 1), "us_per_matvec": round(us_matvec, 2)}}
+        forms["fp32"] = fp32_form(hs, idx, pot, c0, stream, args)
+        forms["batched"] = batched_form(hs, stream, args)
 
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(np)
 
     line = {
-        "metric": "Galerkin matvecs/s (H applications per second inside full Magnus-Lanczos steps)",
+        "metric": METRIC,
         "value": round(value, 1),
         "unit": "matvec/s",
         "n_gpus": 1,
@@ -143,13 +211,114 @@ def main():
         "data": "synthetic",
         "config": {"workload": "N=6 B=4096 (|K|=%d) chained Henon-Heiles lambda=0.111 + laser "
                                "0.05 sin(2t); coherent packet x_d=2; m=10, h=0.005, one CGS pass; "
-                               "%s" % (idx.size, "HIP graph replay" if graph else "eager"),
+                               "%s" % (idx.size, "HIP graph replay" if args.graph else "eager"),
                    "rows": idx.size, "m": M_KRYLOV, "h": H_STEP, "tile_dim": idx.tile_dim,
                    "hbm_gbs_matvec": round(achieved, 1), "norm_drift": norm_err},
         "roofline": roofline,
+        "forms": forms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def fp32_form(hs, idx, pot, c0, stream, args, nsteps=20):
+    """complex64 matvec with float64 Lanczos reductions against the float64 path, both
+    from the same start vector for nsteps steps (graph replays)."""
+    import torch
+    out = {}
+    vec = {}
+    for name, dtype in (("fp64", hs.HS_C128), ("fp32", hs.HS_C64)):
+        # the state c is complex128 in both; dtype selects the Krylov vectors and matvec
+        c = torch.from_numpy(c0).to("cuda")
+        ws = hs.workspace(idx, pot, dtype, M_KRYLOV)
+        t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+        def one():
+            hs.step(idx, pot, c, 0.0, H_STEP, M_KRYLOV, dtype=dtype, reorth=True, ws=ws, t_dev=t_dev)
+        one()
+        torch.cuda.synchronize()
+        g = capture(one, stream)
+        c.copy_(torch.from_numpy(c0))
+        t_dev.zero_()
+        ms = event_time_ms(g.replay, nsteps, stream)
+        out[name] = nsteps * M_KRYLOV / (ms / 1e3)
+        vec[name] = c
+        del g
+    err = float(torch.linalg.norm(vec["fp32"] - vec["fp64"]) / torch.linalg.norm(vec["fp64"]))
+    return {"workload": "as the main line, %d steps from the same start" % nsteps,
+            "matvec_per_s": round(out["fp32"], 1), "fp64_matvec_per_s_same_run": round(out["fp64"], 1),
+            "speedup_vs_fp64": round(out["fp32"] / out["fp64"], 3), "rel_err_vs_fp64": err}
+
+
+def batched_form(hs, stream, args, nsteps=3):
+    """256 instances (N uniform in 3..8, B = floor(2^U(8, log2_bmax)), lambda in
+    [0.05, 0.15], laser-free chained Henon-Heiles), complex normal start vectors: the
+    batched step (persistent launch, graph replay) against the instances stepped one by
+    one with the single-instance path."""
+    import numpy as np
+    import torch
+    from synth import batch_instances, henon_heiles_chain
+
+    draws = batch_instances(256, seed=0, log2_bmax=args.batch_log2_bmax)
+    t0 = time.time()
+    idxs, pots = [], []
+    for d in draws:
+        tt = henon_heiles_chain(d["N"], d["lam"], 0.0)
+        idxs.append(hs.Index(d["N"], d["B"]))
+        pots.append(hs.Pot(d["N"], [(x[0], x[1], x[2], x[3], x.degrees) for x in tt], subtract_harmonic=True))
+    b = hs.Batch(idxs, pots)
+    build_s = time.time() - t0
+    off = b.offsets
+    gen = torch.Generator(device="cuda")
+    c_init = torch.empty(b.total, dtype=torch.complex128, device="cuda")
+    for i, d in enumerate(draws):
+        gen.manual_seed(d["seed"])
+        seg = torch.randn(int(off[i + 1] - off[i]), dtype=torch.complex128, device="cuda", generator=gen)
+        c_init[off[i]:off[i + 1]] = seg / torch.linalg.norm(seg)
+    # batched
+    c = c_init.clone()
+    y = torch.empty_like(c)
+    b.autotune(c, y)
+    ws = b.workspace(M_KRYLOV)
+    t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = capture(lambda: b.step(c, 0.0, H_STEP, M_KRYLOV, ws=ws, t_dev=t_dev), stream)
+    c.copy_(c_init)
+    t_dev.zero_()
+    ms_b = event_time_ms(g.replay, nsteps, stream)
+    del g
+    # one by one
+    singles = [c_init[off[i]:off[i + 1]].clone() for i in range(len(draws))]
+    wss = [hs.workspace(idxs[i], pots[i], hs.HS_C128, M_KRYLOV) for i in range(len(draws))]
+
+    def all_single(t):
+        for i in range(len(draws)):
+            hs.step(idxs[i], pots[i], singles[i], t, H_STEP, M_KRYLOV, ws=wss[i])
+
+    t = 0.0
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(nsteps):
+        all_single(t)
+        t += H_STEP
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_s = e0.elapsed_time(e1)
+    dev_max = 0.0
+    for i in range(len(draws)):
+        ref = singles[i]
+        d = float(torch.linalg.norm(c[off[i]:off[i + 1]] - ref) / torch.linalg.norm(ref))
+        dev_max = max(dev_max, d)
+    inst_mv = len(draws) * M_KRYLOV * nsteps
+    return {"workload": "256 instances, N in 3..8, B=floor(2^U(8,%g)), %d rows in total, %d steps"
+                        % (args.batch_log2_bmax, int(b.total), nsteps),
+            "instance_matvec_per_s": round(inst_mv / (ms_b / 1e3), 1),
+            "row_matvec_per_s": float("%.4g" % (b.total * M_KRYLOV * nsteps / (ms_b / 1e3))),
+            "one_by_one_instance_matvec_per_s": round(inst_mv / (ms_s / 1e3), 1),
+            "speedup_vs_one_by_one": round(ms_s / ms_b, 3),
+            "max_rel_dev_vs_one_by_one": dev_max, "launch": list(b.get_launch()),
+            "host_build_s": round(build_s, 2)}
 
 
 def cpu_baseline(np):

@@ -6,8 +6,8 @@
 // tile's record gives, in one scalar fetch, the first row and length of every neighbour
 // tile that the stencil reaches along the prefix axes; there the neighbour of a row is
 // the same offset, so those loads are contiguous across the wave.  Neighbours along
-// suffix axes come from the per-offset suffix stencil.  Short tiles (PACKED): one lane
-// per listed row, the same code with the record fetched per lane.
+// suffix axes come from the per-offset suffix stencil.  Short tiles: one lane per listed
+// row, the same code with the record fetched per lane.  Both run in one launch.
 //
 // X2 = false drops the x_l^2 and x_l x_{l+1} monomials (absent in the Henon-Heiles
 // class) at compile time.
@@ -222,38 +222,49 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
   y[self] = acc;
 }
 
-template <typename T, int N, int NP, bool PACKED, bool X2>
+// One launch covers both kinds of work.  The grid is kXcd equal ranges; block b runs on
+// XCD b % kXcd and takes position b / kXcd of that XCD's range.  Each range holds a
+// contiguous share of the long-tile chunks (tiles and their neighbours then share one
+// L2), followed by a contiguous share of the packed short-tile rows, so every XCD gets
+// the same mix of the two.
+template <typename T, int N, int NP, bool X2>
 __global__ void __launch_bounds__(256)
 k_hh_long(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *__restrict__ x,
           typename V2<T>::t *__restrict__ y, const double *__restrict__ out_scale,
           const typename V2<T>::t *__restrict__ prev, const double *__restrict__ prev_coef,
-          const double *__restrict__ prev_scale) {
+          const double *__restrict__ prev_scale, int32_t long_per_xcd, int32_t small_per_xcd) {
   constexpr int RS = rec_stride(NP);
-  // XCD-aware order: block b runs on XCD b % kXcd, so give XCD x the contiguous range
-  // [x * per, (x + 1) * per) of the tile-ordered work list; tiles and their neighbours
-  // then share one L2
-  const int64_t per = gridDim.x / kXcd;
-  const int64_t blk = (int64_t)(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
-  const int32_t *__restrict__ rec;
-  int32_t o;
-  if constexpr (!PACKED) {
+  const int32_t xcd = blockIdx.x % kXcd, j = blockIdx.x / kXcd;
+  const T oscale = out_scale ? (T)*out_scale : T(1);
+  const T pcoef = prev ? (T)((*prev_coef) * (prev_scale ? *prev_scale : 1.0)) : T(0);
+  if (j < long_per_xcd) {
+    const int64_t blk = (int64_t)xcd * long_per_xcd + j;
     const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
     if (wave >= ix.nchunks) return;
     const int32_t ri = __builtin_amdgcn_readfirstlane(ix.chunks[2 * wave]);
     const int32_t o0 = __builtin_amdgcn_readfirstlane(ix.chunks[2 * wave + 1]);
-    rec = ix.recs + (int64_t)ri * RS;
-    o = o0 + (int32_t)(threadIdx.x & 63);
+    const int32_t *__restrict__ rec = ix.recs + (int64_t)ri * RS;
+    const int32_t o = o0 + (int32_t)(threadIdx.x & 63);
     if (o >= rec[1]) return;
+    hh_row<T, N, NP, X2>(ix, hh, x, y, rec, o, oscale, prev, pcoef);
   } else {
+    const int64_t blk = (int64_t)xcd * small_per_xcd + (j - long_per_xcd);
     const int64_t i = blk * blockDim.x + threadIdx.x;
     if (i >= ix.nsmall) return;
     const int32_t r = ix.small_rows[i];
-    rec = ix.recs + (int64_t)ix.tile_rec[ix.rowtile[r]] * RS;
-    o = r - rec[0];
+    const int32_t *__restrict__ rec = ix.recs + (int64_t)ix.tile_rec[ix.rowtile[r]] * RS;
+    hh_row<T, N, NP, X2>(ix, hh, x, y, rec, r - rec[0], oscale, prev, pcoef);
   }
-  const T oscale = out_scale ? (T)*out_scale : T(1);
-  const T pcoef = prev ? (T)((*prev_coef) * (prev_scale ? *prev_scale : 1.0)) : T(0);
-  hh_row<T, N, NP, X2>(ix, hh, x, y, rec, o, oscale, prev, pcoef);
+}
+
+// grid of the combined launch: kXcd ranges of (long share + short share) blocks
+inline void long_grid(const IndexDev &ix, bool with_small, int32_t &long_per, int32_t &small_per,
+                      unsigned &blocks) {
+  const int64_t lb = ix.nchunks > 0 ? (ix.nchunks * kChunk + 255) / 256 : 0;
+  const int64_t sb = (with_small && ix.nsmall > 0) ? (ix.nsmall + 255) / 256 : 0;
+  long_per = (int32_t)((lb + kXcd - 1) / kXcd);
+  small_per = (int32_t)((sb + kXcd - 1) / kXcd);
+  blocks = (unsigned)((int64_t)(long_per + small_per) * kXcd);
 }
 
 template <typename T, int N, int NP, bool X2>
@@ -261,16 +272,12 @@ static void launch_long_pair(const IndexDev &ix, const double *hh, const void *x
                              const double *out_scale, const void *prev, const double *prev_coef,
                              const double *prev_scale, hipStream_t s, bool with_small) {
   using C = typename V2<T>::t;
-  if (ix.nchunks > 0) {
-    const unsigned blocks = xcd_grid((ix.nchunks * kChunk + 255) / 256);
-    hipLaunchKernelGGL((k_hh_long<T, N, NP, false, X2>), dim3(blocks), dim3(256), 0, s, ix, hh,
-                       (const C *)x, (C *)y, out_scale, (const C *)prev, prev_coef, prev_scale);
-  }
-  if (with_small && ix.nsmall > 0) {
-    const unsigned blocks = xcd_grid((ix.nsmall + 255) / 256);
-    hipLaunchKernelGGL((k_hh_long<T, N, NP, true, X2>), dim3(blocks), dim3(256), 0, s, ix, hh,
-                       (const C *)x, (C *)y, out_scale, (const C *)prev, prev_coef, prev_scale);
-  }
+  int32_t lp, sp;
+  unsigned blocks;
+  long_grid(ix, with_small, lp, sp, blocks);
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_hh_long<T, N, NP, X2>), dim3(blocks), dim3(256), 0, s, ix, hh, (const C *)x,
+                     (C *)y, out_scale, (const C *)prev, prev_coef, prev_scale, lp, sp);
 }
 
 // Returns 1 if long and short tiles were both launched, 2 if only the long tiles (the
