@@ -1,0 +1,151 @@
+"""Host-side checks of the C-ABI library: it loads, exports every function that
+include/hs.h declares, builds index sets that agree with the oracle's enumeration
+(paper Sec. 1.2), classifies potentials, and reports invalid arguments as status codes.
+No call here touches a GPU."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.index import count, enumerate_lex
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def hs():
+    from paper_1403_3511_amd import hs as _hs
+    return _hs
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "hs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported(hs):
+    names = declared_functions()
+    assert len(names) >= 35
+    for n in names:
+        assert hasattr(hs._lib, n), n          # dlsym through ctypes
+    assert sorted(hs.EXPORTED) == names        # the binding wraps exactly the header
+    assert "gfx950" in hs.hs_version()
+
+
+@pytest.mark.parametrize("N,B,d", [(1, 50, 0), (2, 64, 0), (3, 500, 1), (3, 500, 2), (4, 700, 0),
+                                   (4, 700, 4), (6, 300, 0), (10, 64, 0)])
+def test_host_index_matches_oracle(hs, N, B, d):
+    idx = hs.Index(N, B, d, upload=False)
+    assert idx.size == count(N, B)
+    k = idx.multi_indices().astype(np.int64)
+    # every row is a member, and the rows are exactly the oracle's set
+    assert np.all(np.prod(1 + k, axis=1) <= B)
+    ref = enumerate_lex(N, B).astype(np.int64)
+    assert sorted(map(tuple, k)) == sorted(map(tuple, ref))
+    # tiles: rows sharing the prefix are contiguous, and within a tile the suffixes run in
+    # graded order (prod(1 + s), lex)
+    dd = idx.tile_dim
+    assert 1 <= dd <= N
+    pre, suf = k[:, :N - dd], k[:, N - dd:]
+    keys = [tuple(p) for p in pre]
+    starts = [0] + [i for i in range(1, len(keys)) if keys[i] != keys[i - 1]]
+    assert len(set(keys)) == len(starts) == idx.ntiles
+    for a, b in zip(starts, starts[1:] + [len(keys)]):
+        g = [(int(np.prod(1 + s)), tuple(s)) for s in suf[a:b]]
+        assert g == sorted(g)
+
+
+def test_prefix_tiles_are_initial_segments(hs):
+    """A tile with remaining bound b holds the first |K_d(b)| suffixes of the global list."""
+    N, B = 5, 400
+    idx = hs.Index(N, B, 2, upload=False)
+    k = idx.multi_indices().astype(np.int64)
+    suf = k[:, 3:]
+    glob = sorted({(int(np.prod(1 + s)), tuple(s)) for s in suf})
+    pre = [tuple(p) for p in k[:, :3]]
+    i = 0
+    while i < len(pre):
+        j = i
+        while j < len(pre) and pre[j] == pre[i]:
+            j += 1
+        rem = B // int(np.prod(1 + np.array(pre[i])))
+        assert j - i == count(2, rem)
+        assert [tuple(s) for s in suf[i:j]] == [g[1] for g in glob[:j - i]]
+        i = j
+
+
+def test_potential_classification(hs):
+    from synth import henon_heiles_chain
+    tt = henon_heiles_chain(6, 0.111, 0.05)
+    p = hs.Pot(6, [(x[0], x[1], x[2], x[3], x.degrees) for x in tt], subtract_harmonic=True, upload=False)
+    assert p.fused
+    cheb = hs.Pot(3, [(0.3, (2, 1, 0)), (-0.2, (0, 3, 0))], basis="cheb", scale=6.0, upload=False)
+    assert cheb.fused
+    herm = hs.Pot(3, [(0.1, (2, 2, 2)), (0.2, (6, 0, 0))], basis="herm", upload=False)
+    assert not herm.fused
+    # x_1 x_3 couples non-adjacent axes: outside the fused class
+    assert not hs.Pot(3, [(1.0, (1, 0, 1))], upload=False).fused
+
+
+def test_error_paths(hs):
+    h = C.c_void_p()
+    codes = []
+
+    def expect(code, fn, *args):
+        with pytest.raises(hs.HSError) as e:
+            fn(*args)
+        assert e.value.code == code, (fn, hs.last_error())
+        assert hs.last_error()  # a message is left for the caller
+        codes.append(code)
+
+    expect(-1, hs.hs_index_create, 0, 10, 0, C.byref(h))          # N < 1
+    expect(-1, hs.hs_index_create, 17, 10, 0, C.byref(h))         # N > HS_NMAX
+    expect(-1, hs.hs_index_create, 2, 0, 0, C.byref(h))           # B < 1
+    expect(-1, hs.hs_index_create, 3, 10, 4, C.byref(h))          # tile_dim > N
+    deg = (C.c_uint16 * 2)(1, 0)
+    base = (C.c_double * 1)(1.0)
+    expect(-1, hs.hs_pot_create, 2, 7, 1.0, 1, deg, base, None, None, None, 0, C.byref(h))   # basis
+    expect(-1, hs.hs_pot_create, 2, 0, -1.0, 1, deg, base, None, None, None, 0, C.byref(h))  # scale
+    expect(-5, hs.hs_pot_create, 2, 2, 1.0, 1, deg, base, None, None, None, 1, C.byref(h))   # herm + harmonic
+    bad = (C.c_double * 1)(float("nan"))
+    expect(-7, hs.hs_pot_create, 2, 0, 1.0, 1, deg, bad, None, None, None, 0, C.byref(h))    # non-finite
+    big = (C.c_uint16 * 2)(65, 0)
+    expect(-5, hs.hs_pot_create, 2, 0, 1.0, 1, big, base, None, None, None, 0, C.byref(h))   # degree > 64
+    idx = hs.Index(2, 20, upload=False)
+    pot3 = hs.Pot(3, [(1.0, (1, 0, 0))], upload=False)
+    nb = C.c_int64()
+    expect(-1, hs.hs_workspace_bytes, idx.h, pot3.h, 0, 10, C.byref(nb))      # N mismatch
+    pot2 = hs.Pot(2, [(1.0, (1, 0))], upload=False)
+    expect(-1, hs.hs_workspace_bytes, idx.h, pot2.h, 0, 33, C.byref(nb))      # m > 32
+    expect(-1, hs.hs_workspace_bytes, idx.h, pot2.h, 5, 10, C.byref(nb))      # dtype
+    expect(-1, hs.hs_apply_h, idx.h, None, pot2.h, None, 0, None, None, None, None)  # NULL buffers
+    expect(-1, hs.hs_mlp_create, 7, 100, 210, C.byref(h))                    # hidden not a multiple of 64
+    expect(-1, hs.hs_mlp_create, 40, 256, 210, C.byref(h))                   # in > 32
+    n = C.c_int32()
+    expect(-1, hs.hs_gh_ncoef, 0, 6, C.byref(n))
+    g = np.zeros(4 * 3 * 5)
+    expect(-1, hs.hs_gh_project, 5, 3, 6, 16, g.ctypes.data_as(C.POINTER(C.c_double)), 1, None, None, None)
+    assert set(codes) == {-1, -5, -7}
+
+
+def test_sizes_and_counts(hs):
+    n = C.c_int32()
+    hs.hs_gh_ncoef(4, 6, C.byref(n))
+    assert n.value == math.comb(10, 4) == 210
+    h = C.c_void_p()
+    hs.hs_mlp_create(7, 256, 210, C.byref(h))
+    nb = C.c_int64()
+    hs.hs_mlp_device_bytes(h, 256, C.byref(nb))
+    nparam = 256 * 7 + 256 + 256 * 256 + 256 + 210 * 256 + 210
+    assert nparam == 121810
+    assert nb.value >= 4 * 4 * nparam  # weights, gradients, two Adam moments
+    hs.hs_mlp_destroy(h)
+    # workspace of the generic program: one vector per extra slot
+    idx = hs.Index(3, 200, upload=False)
+    herm = hs.Pot(3, [(0.1, (2, 2, 2)), (0.2, (6, 0, 0))], basis="herm", upload=False)
+    hs.hs_workspace_bytes(idx.h, herm.h, 0, 0, C.byref(nb))
+    assert nb.value >= 16 * idx.size
