@@ -117,6 +117,7 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--forms", type=int, default=1, help="also measure the FP32 and batched forms")
     ap.add_argument("--batch-log2-bmax", type=float, default=10.0)
+    ap.add_argument("--n10-steps", type=int, default=20, help="steps of the N=10 FP32/FP64 comparison")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -191,6 +192,7 @@ def main():
         forms = {"fp64": {"matvec_per_s": round(value, 1), "us_per_matvec": round(us_matvec, 2)}}
         forms["fp32"] = fp32_form(hs, idx, pot, c0, stream, args)
         forms["batched"] = batched_form(hs, stream, args)
+        forms["fp32_n10"] = fp32_n10_form(hs, stream, args)
 
     cpu = None
     if not args.no_cpu:
@@ -248,6 +250,55 @@ def fp32_form(hs, idx, pot, c0, stream, args, nsteps=20):
     return {"workload": "as the main line, %d steps from the same start" % nsteps,
             "matvec_per_s": round(out["fp32"], 1), "fp64_matvec_per_s_same_run": round(out["fp64"], 1),
             "speedup_vs_fp64": round(out["fp32"] / out["fp64"], 3), "rel_err_vs_fp64": err}
+
+
+def fp32_n10_form(hs, stream, args):
+    """N = 10, product bound 4096 (103,495,890 rows), HH + laser, packet at x_d = 0.5:
+    the FP32 form against the float64 path over the same steps (graph replays)."""
+    import numpy as np
+    import torch
+    from synth import coherent_state, henon_heiles_chain
+
+    N, B = 10, 4096
+    tt = henon_heiles_chain(N, 0.111, 0.05)
+    idx = hs.Index(N, B)
+    pot = hs.Pot(N, [(x[0], x[1], x[2], x[3], x.degrees) for x in tt], subtract_harmonic=True)
+    c0 = coherent_state(idx.multi_indices(), 0.5)
+    c0 /= np.linalg.norm(c0)
+    rate, vec, mv_us = {}, {}, {}
+    for name, dtype in (("fp64", hs.HS_C128), ("fp32", hs.HS_C64)):
+        c = torch.from_numpy(c0).to("cuda")
+        ws = hs.workspace(idx, pot, dtype, M_KRYLOV)
+        t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+        def one():
+            hs.step(idx, pot, c, 0.0, H_STEP, M_KRYLOV, dtype=dtype, reorth=True, ws=ws, t_dev=t_dev)
+        one()
+        torch.cuda.synchronize()
+        g = capture(one, stream)
+        c.copy_(torch.from_numpy(c0))
+        t_dev.zero_()
+        ms = event_time_ms(g.replay, args.n10_steps, stream)
+        rate[name] = args.n10_steps * M_KRYLOV / (ms / 1e3)
+        vec[name] = c
+        del g
+        # the H application alone
+        cdt = torch.complex128 if dtype == hs.HS_C128 else torch.complex64
+        x = vec[name].to(cdt)
+        y = torch.empty_like(x)
+        aws = hs.workspace(idx, pot, dtype, 0)
+        hs.apply_h(idx, pot, x, y, dtype, aws)
+        mv_us[name] = event_time_ms(lambda: hs.apply_h(idx, pot, x, y, dtype, aws), 5, stream) * 1e3 / 5
+        del ws, x, y
+    err = float(torch.linalg.norm(vec["fp32"] - vec["fp64"]) / torch.linalg.norm(vec["fp64"]))
+    S = {"fp64": 16, "fp32": 8}
+    return {"workload": "N=10 B=4096 (%d rows) HH lambda=0.111 + laser, packet x_d=0.5, %d steps, "
+                        "m=10, h=0.005" % (idx.size, args.n10_steps),
+            "fp32_matvec_per_s": round(rate["fp32"], 2), "fp64_matvec_per_s": round(rate["fp64"], 2),
+            "speedup_vs_fp64": round(rate["fp32"] / rate["fp64"], 3), "rel_err_vs_fp64": err,
+            "fp32_us_per_matvec": round(mv_us["fp32"], 1), "fp64_us_per_matvec": round(mv_us["fp64"], 1),
+            "fp32_alg_gbs": round(2 * S["fp32"] * idx.size / mv_us["fp32"] / 1e3, 1),
+            "fp64_alg_gbs": round(2 * S["fp64"] * idx.size / mv_us["fp64"] / 1e3, 1)}
 
 
 def batched_form(hs, stream, args, nsteps=3):
