@@ -32,14 +32,15 @@ constexpr int kQueues = kXcd;  // one work queue per XCD (L2 locality of an inst
 template <typename T, int N, int NP>
 __device__ __forceinline__ void batch_row(const BatchInst &B, const typename V2<T>::t *x,
                                           typename V2<T>::t *y, const int32_t *rec, int32_t o,
-                                          const typename V2<T>::t *prev, T pcoef) {
+                                          const typename V2<T>::t *prev, T oscale, T pcoef) {
   if (B.x2)
-    hh_row<T, N, NP, true>(B.ix, B.hh, x + B.off, y + B.off, rec, o, T(1), prev ? prev + B.off : nullptr, pcoef);
+    hh_row<T, N, NP, true>(B.ix, B.hh, x + B.off, y + B.off, rec, o, oscale, prev ? prev + B.off : nullptr, pcoef);
   else
-    hh_row<T, N, NP, false>(B.ix, B.hh, x + B.off, y + B.off, rec, o, T(1), prev ? prev + B.off : nullptr, pcoef);
+    hh_row<T, N, NP, false>(B.ix, B.hh, x + B.off, y + B.off, rec, o, oscale, prev ? prev + B.off : nullptr, pcoef);
 }
 
-// y = H x (- beta_{k-1} prev per instance when prev != nullptr)
+// y = H x, or inside a Lanczos step (scall != nullptr, km1 = k - 1 >= 0) with the stored
+// vectors unnormalised: y = s_k H x - beta_{k-1} s_{k-1} prev, s_q = 1 / beta_{q-1}, s_0 = 1
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_batch_hh(const BatchInst *__restrict__ insts, const int32_t *__restrict__ items,
@@ -75,11 +76,13 @@ k_batch_hh(const BatchInst *__restrict__ insts, const int32_t *__restrict__ item
       o = r - rec[0];
     }
     if (!act) continue;
-    const T pcoef = prev ? (T)scall[(int64_t)inst * Scal::size + Scal::beta + km1] : T(0);
+    const double *sI = scall ? scall + (int64_t)inst * Scal::size : nullptr;
+    const T oscale = (sI && km1 >= 0) ? (T)sI[Scal::inv + km1] : T(1);
+    const T pcoef = (prev && sI) ? (T)(sI[Scal::beta + km1] * (km1 >= 1 ? sI[Scal::inv + km1 - 1] : 1.0)) : T(0);
     switch (B.ix.N * 32 + B.ix.np) {
 #define HS_BCASE(NN, PP) \
   case NN * 32 + PP:     \
-    batch_row<T, NN, PP>(B, x, y, rec, o, prev, pcoef); \
+    batch_row<T, NN, PP>(B, x, y, rec, o, prev, oscale, pcoef); \
     break;
       HS_BCASE(2, 0)
       HS_BCASE(3, 1)

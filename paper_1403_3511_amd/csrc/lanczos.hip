@@ -18,14 +18,16 @@
 
 namespace hs {
 
+// Sum over the block in a fixed order: butterfly inside each wave, then the wave sums in
+// wave order.  Every thread receives the result.  sh needs blockDim.x / 64 doubles.
 __device__ __forceinline__ double block_sum(double v, double *sh) {
-  sh[threadIdx.x] = v;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[wave] = v;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double r = sh[0];
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r += sh[i];
   __syncthreads();
   return r;
 }
@@ -41,6 +43,12 @@ __device__ __forceinline__ double seg_sum(const double *__restrict__ part, int64
 template <typename T> struct CT;
 template <> struct CT<double> { using t = double2; };
 template <> struct CT<float> { using t = float2; };
+
+// Krylov vectors are stored unnormalised: v_q = s_q V_q with s_0 = 1 (the start vector
+// is normalised when written) and s_q = 1 / beta_{q-1}.
+__device__ __forceinline__ double vscale(const double *sc, int q) {
+  return q == 0 ? 1.0 : sc[Scal::inv + q - 1];
+}
 
 // ---- per-segment kernels -------------------------------------------------------------
 __global__ void __launch_bounds__(kSegThreads)
@@ -132,31 +140,34 @@ k_sdots_part(SegView sv, const typename CT<T>::t *__restrict__ V, int64_t stride
   }
 }
 
+// one block per (instance, partial sum q): q = 2 i + (0: real, 1: imaginary) of
+// <V_{lo+i}, W>
 __global__ void __launch_bounds__(kSegThreads)
 k_sfin_dots(SegView sv, const double *__restrict__ part, int lo, int cnt, int k,
             double *__restrict__ scall) {
-  __shared__ double sh[kSegThreads];
+  __shared__ double sh[kSegThreads / 64];
   double *sc = scall + (int64_t)blockIdx.x * Scal::size;
   if (sc[Scal::stop] != 0.0) return;
+  const int q = blockIdx.y;
   int64_t s0, s1;
   sv.range(blockIdx.x, s0, s1);
-  for (int q = 0; q < 2 * cnt; ++q) {
-    const double s = seg_sum(part + (int64_t)q * sv.nseg, s0, s1, sh);
-    if (threadIdx.x == 0) {
-      const int idx = lo + q / 2;
-      if (q & 1) sc[Scal::dim + idx] = s; else sc[Scal::dre + idx] = s;
-      if (!(q & 1) && idx == k) sc[Scal::alpha + k] = s;  // alpha_k = Re <v_k, w>
-    }
+  const int idx = lo + q / 2;
+  const double s = seg_sum(part + (int64_t)q * sv.nseg, s0, s1, sh) * vscale(sc, idx);
+  if (threadIdx.x == 0) {
+    if (q & 1) sc[Scal::dim + idx] = s; else sc[Scal::dre + idx] = s;
+    if (!(q & 1) && idx == k) sc[Scal::alpha + k] = s;  // alpha_k = Re <v_k, w>
   }
 }
 
-// W -= sum_q d_q V_q over q in [lo, k] (reorth) or W -= alpha_k V_k; ||W||^2 partials
+// Wout = W - sum_q d_q v_q over q in [lo, k] (reorth) or W - alpha_k v_k, with the
+// stored Krylov vectors scaled on read (v_q = s_q V_q); ||Wout||^2 partials.  Wout is the
+// next stored Krylov vector: it is never normalised in memory.
 template <typename T>
 __global__ void __launch_bounds__(kSegThreads)
 k_supdate(SegView sv, const typename CT<T>::t *__restrict__ V, int64_t stride, int lo, int k,
-          int reorth, typename CT<T>::t *__restrict__ W, double *__restrict__ part,
-          const double *__restrict__ scall) {
-  __shared__ double sh[kSegThreads];
+          int reorth, const typename CT<T>::t *__restrict__ W, typename CT<T>::t *__restrict__ Wout,
+          double *__restrict__ part, const double *__restrict__ scall) {
+  __shared__ double sh[kSegThreads / 64];
   int inst, len;
   int64_t r0;
   sv.get(blockIdx.x, inst, r0, len);
@@ -168,14 +179,15 @@ k_supdate(SegView sv, const typename CT<T>::t *__restrict__ V, int64_t stride, i
     double wr = W[r].x, wi = W[r].y;
     if (reorth) {
       for (int q = lo; q <= k; ++q) {
-        const double dr = sc[Scal::dre + q], di = sc[Scal::dim + q];
+        const double vs = vscale(sc, q);
+        const double dr = sc[Scal::dre + q] * vs, di = sc[Scal::dim + q] * vs;
         const typename CT<T>::t v = V[(int64_t)q * stride + r];
         const double vr = v.x, vi = v.y;
         wr -= dr * vr - di * vi;
         wi -= dr * vi + di * vr;
       }
     } else {
-      const double a = sc[Scal::alpha + k];
+      const double a = sc[Scal::alpha + k] * vscale(sc, k);
       const typename CT<T>::t v = V[(int64_t)k * stride + r];
       wr -= a * (double)v.x;
       wi -= a * (double)v.y;
@@ -183,7 +195,7 @@ k_supdate(SegView sv, const typename CT<T>::t *__restrict__ V, int64_t stride, i
     typename CT<T>::t o;
     o.x = (T)wr;
     o.y = (T)wi;
-    W[r] = o;
+    Wout[r] = o;
     const double qr = o.x, qi = o.y;
     acc = fma(qr, qr, fma(qi, qi, acc));
   }
@@ -221,25 +233,6 @@ k_sfin_beta(SegView sv, const double *__restrict__ part, int k, int m, double to
     }
     sc[Scal::beta + k] = b;
     sc[Scal::inv + k] = 1.0 / b;
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kSegThreads)
-k_sscale_next(SegView sv, const typename CT<T>::t *__restrict__ W, typename CT<T>::t *__restrict__ vn,
-              int k, const double *__restrict__ scall) {
-  int inst, len;
-  int64_t r0;
-  sv.get(blockIdx.x, inst, r0, len);
-  const double *sc = scall + (int64_t)inst * Scal::size;
-  if (sc[Scal::stop] != 0.0) return;
-  const double s = sc[Scal::inv + k];
-  for (int i = threadIdx.x; i < len; i += blockDim.x) {
-    const int64_t r = r0 + i;
-    typename CT<T>::t o;
-    o.x = (T)((double)W[r].x * s);
-    o.y = (T)((double)W[r].y * s);
-    vn[r] = o;
   }
 }
 
@@ -348,7 +341,8 @@ k_scombine(SegView sv, const typename CT<T>::t *__restrict__ V, int64_t stride, 
     const int64_t r = r0 + i;
     double cr = 0.0, ci = 0.0;
     for (int k = 0; k < me && k < m; ++k) {
-      const double yr = sc[Scal::yre + k], yi = sc[Scal::yim + k];
+      const double vs = vscale(sc, k);
+      const double yr = sc[Scal::yre + k] * vs, yi = sc[Scal::yim + k] * vs;
       const typename CT<T>::t v = V[(int64_t)k * stride + r];
       cr += yr * v.x - yi * v.y;
       ci += yr * v.y + yi * v.x;
@@ -418,21 +412,25 @@ int32_t run_step(const StepJob &J, int m, int reorth, double h, void *cvoid, voi
     C *Vk = V + (int64_t)k * sv_el;
     st = J.matvec(Vk, W, k > 0 ? (const void *)(V + (int64_t)(k - 1) * sv_el) : nullptr, k, sc, aws, s);
     if (st != HS_OK) return st;
-    const int lo = reorth ? 0 : k;
+    // the last step needs alpha_{m-1} only: no orthogonalisation against older vectors
+    const bool last = (k == m - 1);
+    const int lo = (reorth && !last) ? 0 : k;
     for (int c0 = lo; c0 <= k; c0 += kDotChunk) {
       const int cnt = std::min(kDotChunk, k + 1 - c0);
       hipLaunchKernelGGL(k_sdots_part<T>, dim3(nseg), dim3(kSegThreads), 0, s, J.sv, (const C *)V,
                          sv_el, c0, cnt, (const C *)W, part, (const double *)sc);
-      hipLaunchKernelGGL(k_sfin_dots, dim3(nin), dim3(kSegThreads), 0, s, J.sv, (const double *)part,
-                         c0, cnt, k, sc);
+      hipLaunchKernelGGL(k_sfin_dots, dim3(nin, 2 * cnt), dim3(kSegThreads), 0, s, J.sv,
+                         (const double *)part, c0, cnt, k, sc);
     }
-    hipLaunchKernelGGL(k_supdate<T>, dim3(nseg), dim3(kSegThreads), 0, s, J.sv, (const C *)V, sv_el,
-                       lo, k, reorth, W, part, (const double *)sc);
+    if (!last) {
+      hipLaunchKernelGGL(k_supdate<T>, dim3(nseg), dim3(kSegThreads), 0, s, J.sv, (const C *)V, sv_el,
+                         lo, k, reorth, (const C *)W, V + (int64_t)(k + 1) * sv_el, part,
+                         (const double *)sc);
+    }
+    // sets m_eff, and beta_k / breakdown for k < m - 1 (the partial sums are not read at
+    // the last step)
     hipLaunchKernelGGL(k_sfin_beta, dim3(nin), dim3(kSegThreads), 0, s, J.sv, (const double *)part,
                        k, m, tol, sc);
-    if (k + 1 < m)
-      hipLaunchKernelGGL(k_sscale_next<T>, dim3(nseg), dim3(kSegThreads), 0, s, J.sv, (const C *)W,
-                         V + (int64_t)(k + 1) * sv_el, k, (const double *)sc);
   }
   hipLaunchKernelGGL(k_small_expm, dim3(nin), dim3(1024), 0, s, h, sc);
   hipLaunchKernelGGL(k_scombine<T>, dim3(nseg), dim3(kSegThreads), 0, s, J.sv, (const C *)V, sv_el,
@@ -479,8 +477,11 @@ int32_t launch_step(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *
   J.set_time = [&](hipStream_t st) { return launch_set_time(p, pot_dev, t, t_dev, 0.5 * h, st); };
   J.matvec = [&](const void *vk, void *w, const void *vprev, int k, double *sc, void *aws,
                  hipStream_t st) {
-    return launch_apply(idx, idx_dev, p, pot_dev, dtype, vk, w, aws, st, nullptr, vprev,
-                        vprev ? sc + Scal::beta + (k - 1) : nullptr, nullptr);
+    // stored vectors are unnormalised: H v_k = s_k H V_k, v_{k-1} = s_{k-1} V_{k-1}
+    return launch_apply(idx, idx_dev, p, pot_dev, dtype, vk, w, aws, st,
+                        k > 0 ? sc + Scal::inv + (k - 1) : nullptr, vprev,
+                        vprev ? sc + Scal::beta + (k - 1) : nullptr,
+                        k > 1 ? sc + Scal::inv + (k - 2) : nullptr);
   };
   if (dtype == HS_C128) return run_step<double>(J, m, reorth, h, c, ws, t_dev, t_dev, diag, s);
   return run_step<float>(J, m, reorth, h, c, ws, t_dev, t_dev, diag, s);

@@ -70,6 +70,10 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
   });
   const uint32_t self = base + (uint32_t)o;
   const C c0 = x[self];
+  // the previous Lanczos vector is needed only at the end: issue its load now so that
+  // its latency overlaps the stencil work
+  C pv = vz<T>();
+  if (prev) pv = prev[self];
   const double dval = (double)(rec[2] + ix.gssum[o]) + 0.5 * N + hh[5 * N];
   C acc = scal<T>((T)dval, c0);
 
@@ -218,7 +222,7 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
     }
   });
   acc = scal<T>(oscale, acc);
-  if (prev) fma_rc<T>(acc, -pcoef, prev[self]);
+  if (prev) fma_rc<T>(acc, -pcoef, pv);
   y[self] = acc;
 }
 
