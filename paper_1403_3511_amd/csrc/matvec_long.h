@@ -77,8 +77,15 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
   const double dval = (double)(rec[2] + ix.gssum[o]) + 0.5 * N + hh[5 * N];
   C acc = scal<T>((T)dval, c0);
 
+  // Groups run from axis N down to axis 1.  Group l loads c(j -+ e_l) and the weights
+  // sqrt(j_l / 2), sqrt((j_l + 1) / 2) for its own window; group l - 1 needs exactly
+  // these as (X_l c)(j) ingredients, so they are carried instead of loaded again.
+  C car_lo = vz<T>(), car_hi = vz<T>();
+  T car_wlo = T(0), car_whi = T(0);
+  bool have_car = false;  // uniform: whether the previous group produced the carry
+
   static_for<0, N>([&](auto L) {
-    constexpr int l = decltype(L)::value;
+    constexpr int l = N - 1 - decltype(L)::value;
     constexpr bool inner = (l + 1 < N);
     const T a1 = (T)hh[5 * l + 0], a3 = (T)hh[5 * l + 2];
     const T a2 = X2 ? (T)hh[5 * l + 1] : T(0);
@@ -86,6 +93,10 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
     const T g2 = inner ? (T)hh[5 * l + 4] : T(0);
     const bool any2 = (a3 != T(0)) || (a2 != T(0)) || (g2 != T(0));
     const bool need3 = (a3 != T(0));
+    const bool in_car = have_car;
+    const C in_lo = car_lo, in_hi = car_hi;
+    const T in_wlo = car_wlo, in_whi = car_whi;
+    have_car = false;
     if (!any2 && a1 == T(0) && g1 == T(0)) return;  // uniform: group absent
     // ---- window j + s e_l, s = -3..3: element offset (kAbsent if outside K) ----
     uint32_t id[7];
@@ -131,11 +142,12 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
     if (!any2) val[1] = val[5] = false;
     if (!need3) val[0] = val[6] = false;
     // edge weights e_s (edge between s-1 and s), a3 folded in for the innermost level
-    T e[6], ea3[6];
+    T raw[6], e[6], ea3[6];
 #pragma unroll
     for (int s = -2; s <= 3; ++s) {
       const int k = jl + s;
-      const T w = (val[3 + s - 1] && val[3 + s]) ? wt[k > 0 ? k : 0] : T(0);
+      raw[s + 2] = wt[k > 0 ? k : 0];
+      const T w = (val[3 + s - 1] && val[3 + s]) ? raw[s + 2] : T(0);
       e[s + 2] = w;
       ea3[s + 2] = w * a3;
     }
@@ -155,6 +167,12 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
         u[5] = BufLoad<T>::ld(xr, id[5]);
       }
     }
+    // carry for group l - 1: c(j -+ e_l) and the weights at j_l, j_l + 1
+    car_lo = u[2];
+    car_hi = u[4];
+    car_wlo = raw[2];
+    car_whi = raw[3];
+    have_car = true;
     // ---- h2 at s = -2, 0, 2 ----
     C h2[3];
 #pragma unroll
@@ -171,9 +189,16 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
     if constexpr (inner) {
       if (g1 != T(0) || g2 != T(0)) {
         constexpr int m = l + 1;
-        int jm;
-        if constexpr (m < NP) jm = rec[4 + m]; else jm = sc[m - NP];
-        const T wlo = wt[jm], whi = wt[jm + 1];
+        T wlo, whi;
+        if (in_car) {
+          wlo = in_wlo;
+          whi = in_whi;
+        } else {
+          int jm;
+          if constexpr (m < NP) jm = rec[4 + m]; else jm = sc[m - NP];
+          wlo = wt[jm];
+          whi = wt[jm + 1];
+        }
         int32_t o_lo = -1, o_hi = -1;
         if constexpr (m == NP) {  // l prefix, l+1 the first suffix axis
           o_lo = gst[(int64_t)gst_axis_slot(0, -1) * ng + o];
@@ -185,22 +210,28 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
           const T gs = (s & 1) ? g1 : g2;
           if (gs == T(0)) continue;
           C vs = vz<T>();
+          if (s == 0 && in_car) {
+            // (X_{l+1} c)(j) from the carried neighbours
+            fma_rc<T>(vs, wlo * gs, in_lo);
+            fma_rc<T>(vs, whi * gs, in_hi);
+          } else {
 #pragma unroll
-          for (int r = -1; r <= 1; r += 2) {
-            uint32_t vid;
-            if constexpr (m < NP) {
-              const int p = rec_pair(NP, l, s, r);
-              vid = (val[3 + s] && o < rec[p + 1]) ? (uint32_t)(rec[p] + o) : kAbsent;
-            } else if constexpr (m == NP) {
-              const int32_t oq = r < 0 ? o_lo : o_hi;
-              vid = (val[3 + s] && (uint32_t)oq < (uint32_t)lnw[3 + s]) ? (uint32_t)(stw[3 + s] + oq) : kAbsent;
-            } else {
-              constexpr int a = l - NP;
-              const int32_t oq = (s == 0) ? gst[(int64_t)gst_axis_slot(a + 1, r) * ng + o]
-                                          : gst[(int64_t)gst_pair_slot(D, a, s, r) * ng + o];
-              vid = (val[3 + s] && (uint32_t)oq < (uint32_t)len) ? base + (uint32_t)oq : kAbsent;
+            for (int r = -1; r <= 1; r += 2) {
+              uint32_t vid;
+              if constexpr (m < NP) {
+                const int p = rec_pair(NP, l, s, r);
+                vid = (val[3 + s] && o < rec[p + 1]) ? (uint32_t)(rec[p] + o) : kAbsent;
+              } else if constexpr (m == NP) {
+                const int32_t oq = r < 0 ? o_lo : o_hi;
+                vid = (val[3 + s] && (uint32_t)oq < (uint32_t)lnw[3 + s]) ? (uint32_t)(stw[3 + s] + oq) : kAbsent;
+              } else {
+                constexpr int a = l - NP;
+                const int32_t oq = (s == 0) ? gst[(int64_t)gst_axis_slot(a + 1, r) * ng + o]
+                                            : gst[(int64_t)gst_pair_slot(D, a, s, r) * ng + o];
+                vid = (val[3 + s] && (uint32_t)oq < (uint32_t)len) ? base + (uint32_t)oq : kAbsent;
+              }
+              fma_rc<T>(vs, (r < 0 ? wlo : whi) * gs, BufLoad<T>::ld(xr, vid));
             }
-            fma_rc<T>(vs, (r < 0 ? wlo : whi) * gs, BufLoad<T>::ld(xr, vid));
           }
           if (s & 1) v1[(s + 1) / 2] = vs;
           else {
