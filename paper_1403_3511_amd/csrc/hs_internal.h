@@ -41,8 +41,12 @@ struct IndexDev {
   const int32_t *rowtile;    // [size] tile of each row
   const double *wtab;        // [B + 8] sqrt(k / 2)
   const float *wtabf;        // [B + 8] sqrt(k / 2) in float32
-  // suffix stencil: gst[slot * ng + o] = graded offset of s(o) + displacement(slot), or -1
-  int32_t ns;                // number of stencil slots = 6 d + 8 (d - 1)
+  const double *wtp;         // [B + 10] sqrt((k - 2) / 2) for k >= 2, 0 below (window loads)
+  const float *wtpf;         // the same in float32
+  const uint64_t *gsp;       // [ng] suffix multi-index packed 16 bits per axis (d <= 4), else NULL
+  // suffix stencil (graded offset of s(o) + displacement, or -1), stored in pairs that the
+  // fused kernel reads together: gst[2 (p ng + o) + side], see gst_axis_at / gst_cross_at
+  int32_t ns;                // number of entries per suffix = 6 d + 8 (d - 1)
   const int32_t *gst;
   // work lists of the fused kernel
   int64_t nchunks;           // 64-row chunks of the long tiles: (record, first offset)
@@ -54,12 +58,22 @@ struct IndexDev {
   const int32_t *small_rows; // [nsmall]
 };
 
-// suffix stencil slots: axis a (0-based inside the suffix), step s in {-3..-1, 1..3}
-__host__ __device__ inline int gst_axis_slot(int a, int s) { return a * 6 + (s < 0 ? s + 3 : s + 2); }
-// pair (a, a+1): step s in {-2, -1, 1, 2} along a and r in {-1, 1} along a+1
-__host__ __device__ inline int gst_pair_slot(int d, int a, int s, int r) {
-  const int si = s < 0 ? s + 2 : s + 1;
-  return 6 * d + a * 8 + si * 2 + (r > 0 ? 1 : 0);
+// Suffix stencil pairs.  Axis pairs p = 3 a + (|s| - 1) hold the displacements -|s|
+// (side 0) and +|s| (side 1) along suffix axis a, |s| = 1..3.  Cross pairs
+// p = 3 d + 4 a + i(s) hold s along a and r = -1 (side 0) / +1 (side 1) along a + 1, for
+// s in {-2, -1, 1, 2}.
+__host__ __device__ inline int gst_axis_pair(int a, int sabs) { return 3 * a + sabs - 1; }
+__host__ __device__ inline int gst_cross_pair(int d, int a, int s) {
+  return 3 * d + 4 * a + (s < 0 ? s + 2 : s + 1);
+}
+__host__ __device__ inline int64_t gst_elem(int pair, int side, int64_t o, int64_t ng) {
+  return 2 * ((int64_t)pair * ng + o) + side;
+}
+__host__ __device__ inline int64_t gst_axis_at(int a, int s, int64_t o, int64_t ng) {
+  return gst_elem(gst_axis_pair(a, s < 0 ? -s : s), s > 0 ? 1 : 0, o, ng);
+}
+__host__ __device__ inline int64_t gst_cross_at(int d, int a, int s, int r, int64_t o, int64_t ng) {
+  return gst_elem(gst_cross_pair(d, a, s), r > 0 ? 1 : 0, o, ng);
 }
 // Long-tile record (int32): [0] first row, [1] length, [2] sum of prefix coordinates,
 // [3] tile id, [4 .. 4+np) prefix coordinates, then (first row, length) pairs of the
@@ -94,7 +108,7 @@ struct hs_index_s {
   // device blob layout (byte offsets)
   int64_t off_tstart = 0, off_tlen = 0, off_tnbr = 0, off_tpfx = 0, off_tpsum = 0,
           off_gsidx = 0, off_gnbr = 0, off_gssum = 0, off_rowtile = 0, off_wtab = 0,
-          off_wtabf = 0, off_gst = 0, off_chunks = 0, off_small = 0, off_recs = 0, off_tile_rec = 0,
+          off_wtabf = 0, off_wtp = 0, off_wtpf = 0, off_gsp = 0, off_gst = 0, off_chunks = 0, off_small = 0, off_recs = 0, off_tile_rec = 0,
           dev_bytes = 0;
   std::vector<uint8_t> blob;   // host image of the device block
   void *pinned = nullptr;      // pinned staging for the upload

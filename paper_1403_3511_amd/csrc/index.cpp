@@ -156,6 +156,9 @@ hs::IndexDev hs_index_s::view(const void *dev) const {
   v.rowtile = reinterpret_cast<const int32_t *>(b + off_rowtile);
   v.wtab = reinterpret_cast<const double *>(b + off_wtab);
   v.wtabf = reinterpret_cast<const float *>(b + off_wtabf);
+  v.wtp = reinterpret_cast<const double *>(b + off_wtp);
+  v.wtpf = reinterpret_cast<const float *>(b + off_wtpf);
+  v.gsp = d <= 4 ? reinterpret_cast<const uint64_t *>(b + off_gsp) : nullptr;
   v.ns = ns;
   v.gst = reinterpret_cast<const int32_t *>(b + off_gst);
   v.nchunks = nchunks;
@@ -290,10 +293,10 @@ static int32_t build_index(hs_index_s *ix) {
     for (int64_t g = 0; g < ng; ++g) {
       for (int a = 0; a < d; ++a)
         for (int s = -3; s <= 3; ++s)
-          if (s != 0) ix->gst[(size_t)hs::gst_axis_slot(a, s) * ng + g] = lookup(g, a, s, -1, 0);
+          if (s != 0) ix->gst[hs::gst_axis_at(a, s, g, ng)] = lookup(g, a, s, -1, 0);
       for (int a = 0; a + 1 < d; ++a)
         for (int s : {-2, -1, 1, 2})
-          for (int r : {-1, 1}) ix->gst[(size_t)hs::gst_pair_slot(d, a, s, r) * ng + g] = lookup(g, a, s, a + 1, r);
+          for (int r : {-1, 1}) ix->gst[hs::gst_cross_at(d, a, s, r, g, ng)] = lookup(g, a, s, a + 1, r);
     }
   }
   // ---- work lists: 64-row chunks of long tiles, rows of short tiles ----
@@ -366,6 +369,9 @@ static int32_t build_index(hs_index_s *ix) {
   ix->off_rowtile = take(total * 4);
   ix->off_wtab = take((B + 8) * 8);
   ix->off_wtabf = take((B + 8) * 4);
+  ix->off_wtp = take((B + 10) * 8);
+  ix->off_wtpf = take((B + 10) * 4);
+  ix->off_gsp = take(d <= 4 ? ng * 8 : 0);
   ix->off_gst = take((int64_t)ix->ns * ng * 4);
   ix->off_chunks = take(ix->nchunks * 8);
   ix->off_small = take(ix->nsmall * 4);
@@ -393,6 +399,20 @@ static int32_t build_index(hs_index_s *ix) {
   }
   put(ix->off_wtab, w.data(), (B + 8) * 8);
   put(ix->off_wtabf, wf.data(), (B + 8) * 4);
+  std::vector<double> wp(B + 10, 0.0);
+  std::vector<float> wpf(B + 10, 0.0f);
+  for (int64_t k = 2; k < B + 10; ++k) {
+    wp[k] = std::sqrt(0.5 * (double)(k - 2));
+    wpf[k] = (float)wp[k];
+  }
+  put(ix->off_wtp, wp.data(), (B + 10) * 8);
+  put(ix->off_wtpf, wpf.data(), (B + 10) * 4);
+  if (d <= 4) {
+    std::vector<uint64_t> pk(ng, 0);
+    for (int64_t g = 0; g < ng; ++g)
+      for (int a = 0; a < d; ++a) pk[g] |= (uint64_t)ix->gsidx[g * d + a] << (16 * a);
+    put(ix->off_gsp, pk.data(), ng * 8);
+  }
   put(ix->off_gst, ix->gst.data(), (int64_t)ix->ns * ng * 4);
   put(ix->off_chunks, ix->chunks.data(), ix->nchunks * 8);
   put(ix->off_small, ix->small_rows.data(), ix->nsmall * 4);

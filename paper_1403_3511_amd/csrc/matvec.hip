@@ -272,8 +272,8 @@ k_hh_tiles(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *
       jl = ix.gsidx[(int64_t)o * d + a];
       for (int s = 1; s <= 3; ++s) {
         if (s > smax) break;
-        const int32_t ou = ix.gst[(int64_t)gst_axis_slot(a, s) * ng + o];
-        const int32_t od = ix.gst[(int64_t)gst_axis_slot(a, -s) * ng + o];
+        const int32_t ou = ix.gst[gst_axis_at(a, s, o, ng)];
+        const int32_t od = ix.gst[gst_axis_at(a, -s, o, ng)];
         Ts[3 + s] = t;
         Ts[3 - s] = t;
         Os[3 + s] = ou;
@@ -313,13 +313,13 @@ k_hh_tiles(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *
             ok = (tq >= 0) && (r2 < 0 || o < ix.tlen[tq]);
           } else if (lp) {  // l prefix, m the first suffix axis
             tq = Ts[3 + s];
-            oq = ix.gst[(int64_t)gst_axis_slot(0, r2) * ng + o];
+            oq = ix.gst[gst_axis_at(0, r2, o, ng)];
             ok = (oq >= 0) && (oq < ix.tlen[tq]);
           } else {          // both suffix axes
             const int a = l - np;
             tq = t;
-            oq = (s == 0) ? ix.gst[(int64_t)gst_axis_slot(a + 1, r2) * ng + o]
-                          : ix.gst[(int64_t)gst_pair_slot(d, a, s, r2) * ng + o];
+            oq = (s == 0) ? ix.gst[gst_axis_at(a + 1, r2, o, ng)]
+                          : ix.gst[gst_cross_at(d, a, s, r2, o, ng)];
             ok = (oq >= 0) && (oq < len);
           }
           if (ok) fma_rc<T>(vs, r2 < 0 ? wlo : whi, x[ix.tstart[tq] + oq]);

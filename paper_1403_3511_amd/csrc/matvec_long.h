@@ -40,6 +40,27 @@ template <> struct BufLoad<float> {
   }
 };
 
+// Window weights sqrt((j + s) / 2), s = -2..3, from the zero-padded table (entry k + 2
+// holds sqrt(k / 2)): six consecutive values in two or three vector loads.
+template <typename T> struct WinLoad;
+template <> struct WinLoad<double> {
+  static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, int j, double *w) {
+    static_for<0, 3>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (j + 2 * i) << 3, 0, 0);
+      __builtin_memcpy(w + 2 * i, &v, 16);
+    });
+  }
+};
+template <> struct WinLoad<float> {
+  static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, int j, float *w) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, j << 2, 0, 0);
+    __builtin_memcpy(w, &v, 16);
+    const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, (j + 4) << 2, 0, 0);
+    __builtin_memcpy(w + 4, &u, 8);
+  }
+};
+
 // One group per axis l, skipped as a whole when its coefficients vanish (uniform
 // branch).  Coefficients are folded into the edge weights: with u_s = c(j + s e_l) and
 // v_s = (X_{l+1} c)(j + s e_l),
@@ -62,19 +83,27 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
   const T *__restrict__ wt;
   if constexpr (sizeof(T) == 8) wt = (const T *)ix.wtab; else wt = (const T *)ix.wtabf;
   const int64_t ng = ix.ng;
-  const int32_t *__restrict__ gst = ix.gst;
+  const int2 *__restrict__ gst2 = reinterpret_cast<const int2 *>(ix.gst);
+  const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)(sizeof(T) == 8 ? (const void *)ix.wtp : (const void *)ix.wtpf), (short)0,
+      (int)((ix.B + 10) * (int)sizeof(T)), 0x00020000);
   int sc[D];
-  static_for<0, D>([&](auto A) {
-    constexpr int a = decltype(A)::value;
-    sc[a] = ix.gsidx[(int64_t)o * D + a];
-  });
+  int ssum = 0;
+  {
+    const uint64_t pk = ix.gsp[o];  // suffix coordinates, 16 bits each (D <= 4)
+    static_for<0, D>([&](auto A) {
+      constexpr int a = decltype(A)::value;
+      sc[a] = (int)((pk >> (16 * a)) & 0xFFFFu);
+      ssum += sc[a];
+    });
+  }
   const uint32_t self = base + (uint32_t)o;
   const C c0 = x[self];
   // the previous Lanczos vector is needed only at the end: issue its load now so that
   // its latency overlaps the stencil work
   C pv = vz<T>();
   if (prev) pv = prev[self];
-  const double dval = (double)(rec[2] + ix.gssum[o]) + 0.5 * N + hh[5 * N];
+  const double dval = (double)(rec[2] + ssum) + 0.5 * N + hh[5 * N];
   C acc = scal<T>((T)dval, c0);
 
   // Groups run from axis N down to axis 1.  Group l loads c(j -+ e_l) and the weights
@@ -131,8 +160,8 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
       for (int s = 1; s <= 3; ++s) {
         if (s == 2 && !any2) continue;
         if (s == 3 && !need3) continue;
-        const int32_t ou = gst[(int64_t)gst_axis_slot(a, s) * ng + o];
-        const int32_t od = gst[(int64_t)gst_axis_slot(a, -s) * ng + o];
+        const int2 pr = gst2[gst_axis_pair(a, s) * ng + o];  // (-s, +s)
+        const int32_t ou = pr.y, od = pr.x;
         val[3 + s] = (uint32_t)ou < (uint32_t)len;
         val[3 - s] = od >= 0;
         id[3 + s] = val[3 + s] ? base + (uint32_t)ou : kAbsent;
@@ -143,10 +172,11 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
     if (!need3) val[0] = val[6] = false;
     // edge weights e_s (edge between s-1 and s), a3 folded in for the innermost level
     T raw[6], e[6], ea3[6];
+    if constexpr (l >= NP) WinLoad<T>::ld(wr, jl, raw);  // per-lane coordinate
 #pragma unroll
     for (int s = -2; s <= 3; ++s) {
       const int k = jl + s;
-      raw[s + 2] = wt[k > 0 ? k : 0];
+      if constexpr (l < NP) raw[s + 2] = wt[k > 0 ? k : 0];  // uniform: scalar loads
       const T w = (val[3 + s - 1] && val[3 + s]) ? raw[s + 2] : T(0);
       e[s + 2] = w;
       ea3[s + 2] = w * a3;
@@ -201,8 +231,9 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
         }
         int32_t o_lo = -1, o_hi = -1;
         if constexpr (m == NP) {  // l prefix, l+1 the first suffix axis
-          o_lo = gst[(int64_t)gst_axis_slot(0, -1) * ng + o];
-          o_hi = gst[(int64_t)gst_axis_slot(0, 1) * ng + o];
+          const int2 pr = gst2[gst_axis_pair(0, 1) * ng + o];
+          o_lo = pr.x;
+          o_hi = pr.y;
         }
 #pragma unroll
         for (int s = -2; s <= 2; ++s) {
@@ -215,6 +246,11 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
             fma_rc<T>(vs, wlo * gs, in_lo);
             fma_rc<T>(vs, whi * gs, in_hi);
           } else {
+            int2 cr = make_int2(-1, -1);  // cross displacements (r = -1, +1) on suffix axes
+            if constexpr (m > NP) {
+              constexpr int a = l - NP;
+              cr = (s == 0) ? gst2[gst_axis_pair(a + 1, 1) * ng + o] : gst2[gst_cross_pair(D, a, s) * ng + o];
+            }
 #pragma unroll
             for (int r = -1; r <= 1; r += 2) {
               uint32_t vid;
@@ -225,9 +261,7 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
                 const int32_t oq = r < 0 ? o_lo : o_hi;
                 vid = (val[3 + s] && (uint32_t)oq < (uint32_t)lnw[3 + s]) ? (uint32_t)(stw[3 + s] + oq) : kAbsent;
               } else {
-                constexpr int a = l - NP;
-                const int32_t oq = (s == 0) ? gst[(int64_t)gst_axis_slot(a + 1, r) * ng + o]
-                                            : gst[(int64_t)gst_pair_slot(D, a, s, r) * ng + o];
+                const int32_t oq = r < 0 ? cr.x : cr.y;
                 vid = (val[3 + s] && (uint32_t)oq < (uint32_t)len) ? base + (uint32_t)oq : kAbsent;
               }
               fma_rc<T>(vs, (r < 0 ? wlo : whi) * gs, BufLoad<T>::ld(xr, vid));
