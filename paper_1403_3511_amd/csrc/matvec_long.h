@@ -356,6 +356,9 @@ int launch_hh_long_impl(const IndexDev &ix, const double *hh, const void *x, voi
                         const double *out_scale, const void *prev, const double *prev_coef,
                         const double *prev_scale, hipStream_t s, bool x2) {
   if (ix.rstride != rec_stride(ix.np)) return 0;
+  // raw buffer loads take a 32-bit byte size and 32-bit byte offsets: larger sets use the
+  // generic row kernels, which index with 64 bits
+  if (ix.size > (int64_t)(INT32_MAX / (2 * sizeof(T)))) return 0;
   const bool small = ix.tile_rec != nullptr;
 #define HS_LONG_CASE(NN, PP)                                                                    \
   case NN * 32 + PP:                                                                            \

@@ -29,14 +29,22 @@ def setup():
     return hs, tt, idx, pot, k, c0
 
 
-def _vector(k):
-    """Coherent packet plus a deterministic perturbation of size 1e-3 on every row, a
-    closed-form function of the multi-index (so the oracle evaluates it by index)."""
+def _perturbation(k):
+    """A deterministic function of the multi-index, of modulus <= sqrt(2).  The phases are
+    residues of integer forms, so they are bit-identical however the rows are batched
+    (a floating-point phase like k.k * 0.11 would round differently in a vectorised
+    product and in a single-row one, and H's large weights amplify that)."""
     k = np.atleast_2d(np.asarray(k, dtype=np.int64))
-    w1 = np.arange(1, N + 1) * 0.37
-    w2 = np.arange(N, 0, -1) * 0.11
-    pert = np.cos(k @ w1) + 1j * np.sin((k * k) @ w2)
-    return coherent_state(k, 0.5) + 1e-3 * pert
+    n = k.shape[1]
+    r1 = (k @ np.arange(3, 3 + 2 * n, 2, dtype=np.int64)) % 97
+    r2 = ((k * k) @ np.arange(n, 0, -1, dtype=np.int64)) % 89
+    return np.cos(2.0 * np.pi * r1 / 97.0) + 1j * np.sin(2.0 * np.pi * r2 / 89.0)
+
+
+def _vector(k):
+    """Coherent packet plus a perturbation of size 1e-3 on every row, a closed-form
+    function of the multi-index (so the oracle evaluates it by index)."""
+    return coherent_state(np.atleast_2d(k), 0.5) + 1e-3 * _perturbation(k)
 
 
 def test_n10_float64_sampled_rows(setup):
@@ -80,4 +88,47 @@ def test_n10_float32_form_error(setup):
     err = float(torch.linalg.norm(out[hs.HS_C64] - out[hs.HS_C128]) / torch.linalg.norm(out[hs.HS_C128]))
     drift = abs(float(torch.linalg.norm(out[hs.HS_C128])) - 1.0)
     print(f"N=10 B=4096, 10 steps: FP32 form relative error vs FP64 {err:.2e}; FP64 norm drift {drift:.1e}")
+    assert err < 1e-5
+
+
+def test_above_32bit_buffer_range():
+    """N = 6, product bound 65536 (247,147,586 rows): complex128 vectors exceed the 2^31
+    bytes that 32-bit buffer offsets reach, so the float64 H application takes the 64-bit
+    row kernels; complex64 stays just below and uses the buffer kernel.  Float64 checked
+    on sampled rows against the oracle, float32 against float64."""
+    import torch
+    from paper_1403_3511_amd import hs
+    N6, B6 = 6, 65536
+    tt = hh_workload(N6, 0.111, 0.05)
+    idx = hs.Index(N6, B6)
+    assert idx.size == 247147586 and idx.size * 16 > 2 ** 31 > idx.size * 8
+    pot = hs.Pot(N6, lib_terms(tt), subtract_harmonic=True)
+    pot.set_time(0.3)
+    k = idx.multi_indices()
+
+    def vec(kk):
+        kk = np.atleast_2d(np.asarray(kk, dtype=np.int64))
+        return coherent_state(kk, 1.0) + 1e-3 * _perturbation(kk)
+
+    c = torch.empty(idx.size, dtype=torch.complex128, device="cuda")
+    step = 8_000_000
+    for i in range(0, idx.size, step):
+        c[i:i + step] = torch.from_numpy(vec(k[i:i + step]))
+    y = torch.empty_like(c)
+    hs.apply_h(idx, pot, c, y)
+    rng = np.random.default_rng(4)
+    rows = np.concatenate([np.arange(0, 20), rng.choice(idx.size, 40, replace=False),
+                           np.arange(idx.size - 10, idx.size)])
+    rsel = torch.from_numpy(rows).to("cuda")
+    y64 = y[rsel].cpu().numpy()
+    y_ref = fast_H_rows(N6, B6, oracle_W(N6, tt, 0.3), lambda m: vec(np.array(m))[0], k[rows])
+    assert rel2(y64[:20], y_ref[:20]) <= 1e-12
+    assert rel2(y64[20:], y_ref[20:]) <= 1e-12
+    # float32 form on the same input, just under its 32-bit limit
+    c32 = c.to(torch.complex64)
+    del c
+    y32 = torch.empty_like(c32)
+    hs.apply_h(idx, pot, c32, y32, hs.HS_C64)
+    err = float(torch.linalg.norm(y32.to(torch.complex128) - y) / torch.linalg.norm(y))
+    print(f"N=6 B=65536: float32 H application relative error vs float64 {err:.2e}")
     assert err < 1e-5
