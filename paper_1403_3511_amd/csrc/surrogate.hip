@@ -404,16 +404,6 @@ __global__ void __launch_bounds__(256) k_colsum(int rows, int cols, const float 
   out[j] = s;
 }
 
-// xn = 2 (x - lo) / (hi - lo) - 1, padded with zeros to ldx columns
-__global__ void k_norm_in(int batch, int in, int ldx, const double *__restrict__ x,
-                          const float *__restrict__ lo, const float *__restrict__ hi,
-                          float *__restrict__ xn) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)batch * ldx) return;
-  const int i = (int)(idx / ldx), k = (int)(idx % ldx);
-  xn[idx] = k < in ? (float)(2.0 * (x[(int64_t)i * in + k] - lo[k]) / ((double)hi[k] - lo[k]) - 1.0) : 0.f;
-}
-
 // tn = (target - mean) / std
 __global__ void k_norm_out(int64_t n, int out, const double *__restrict__ tg, const float *__restrict__ mean,
                            const float *__restrict__ sd, float *__restrict__ tn) {
@@ -421,15 +411,6 @@ __global__ void k_norm_out(int64_t n, int out, const double *__restrict__ tg, co
   if (idx >= n) return;
   const int j = (int)(idx % out);
   tn[idx] = (float)((tg[idx] - mean[j]) / sd[j]);
-}
-
-// coef = y * std + mean (float64 output)
-__global__ void k_denorm_out(int64_t n, int out, const float *__restrict__ y, const float *__restrict__ mean,
-                             const float *__restrict__ sd, double *__restrict__ coef) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  const int j = (int)(idx % out);
-  coef[idx] = (double)y[idx] * (double)sd[j] + (double)mean[j];
 }
 
 // d = y - t; dY = 2 d / n; loss = mean d^2 (one block, fixed order)
@@ -452,8 +433,8 @@ __global__ void __launch_bounds__(256) k_mse(int64_t n, const float *__restrict_
   if (threadIdx.x == 0 && loss) *loss = sh[0] / (float)n;
 }
 
-// Adam with bias correction; step counter in *tstep (incremented by the first thread
-// of block 0 after every thread has read it: the counter is read from a copy)
+// Adam with bias correction; the step counter *tstep is advanced by the next kernel on
+// the stream (k_mlp_pack), after every thread here has read it
 __global__ void __launch_bounds__(256) k_adam(int64_t n, float *__restrict__ w, const float *__restrict__ g,
                                               float *__restrict__ m, float *__restrict__ v, float lr,
                                               const int32_t *__restrict__ tstep) {
@@ -471,8 +452,110 @@ __global__ void __launch_bounds__(256) k_adam(int64_t n, float *__restrict__ w, 
   w[i] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-__global__ void k_step_inc(int32_t *tstep) {
-  if (threadIdx.x == 0) *tstep += 1;
+// ---- fused forward pass ------------------------------------------------------------------
+// One workgroup (4 waves) carries 16 samples through the three layers.  Activations stay in
+// LDS as BF16, the operand precision of the products, so the result equals that of three
+// separate products; weights come from BF16 copies laid out as the fragments need them
+// (row j holds the inputs of output j).  Each wave owns a quarter of the output columns.
+constexpr int kFwdRows = 16;
+constexpr int kFwdLd0 = 40;  // LDS row stride of the input tile (32 + 8 padding), in bf16
+
+template <class Epi>
+__device__ __forceinline__ void dense_layer(const __bf16 *A, int lda, int K, const __bf16 *__restrict__ W,
+                                            int ldw, int ncols, Epi &&epi) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int per = ncols >> 2;  // columns of this wave, a multiple of 16
+  const int c0 = wave * per;
+  const int row = lane & 15, kq = (lane >> 4) * 8;
+  for (int t = 0; t < per; t += 16) {
+    const int col = c0 + t + (lane & 15);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8 *>(A + row * lda + k0 + kq);
+      const bf16x8 b = *reinterpret_cast<const bf16x8 *>(W + (int64_t)col * ldw + k0 + kq);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) epi((lane >> 4) * 4 + r, col, acc[r]);
+  }
+}
+
+// TRAIN = false: coef = de-normalised network output (float64).
+// TRAIN = true: also writes the normalised input and the pre/post activations (float32)
+// that the backward pass reads, and the normalised output y.
+template <bool TRAIN>
+__global__ void __launch_bounds__(256)
+k_mlp_fwd(int M, int in, int hid, int out, int outp, const double *__restrict__ x, const float *__restrict__ nrm,
+          const __bf16 *__restrict__ W1b, const float *__restrict__ b1, const __bf16 *__restrict__ W2b,
+          const float *__restrict__ b2, const __bf16 *__restrict__ W3b, const float *__restrict__ b3,
+          double *__restrict__ coef, float *__restrict__ xn, float *__restrict__ z1, float *__restrict__ h1,
+          float *__restrict__ z2, float *__restrict__ h2, float *__restrict__ yo) {
+  extern __shared__ __align__(16) unsigned char fsm[];
+  const int ldh = hid + 8;
+  __bf16 *A0 = reinterpret_cast<__bf16 *>(fsm);
+  __bf16 *H1 = A0 + kFwdRows * kFwdLd0;
+  __bf16 *H2 = H1 + kFwdRows * ldh;
+  const int i0 = blockIdx.x * kFwdRows;
+  const float *lo = nrm, *hi = nrm + in, *mean = nrm + 2 * in, *sd = nrm + 2 * in + out;
+  // inputs mapped to [-1, 1], zero beyond `in` and below the last sample
+  for (int e = threadIdx.x; e < kFwdRows * 32; e += blockDim.x) {
+    const int r = e >> 5, k = e & 31, i = i0 + r;
+    float v = 0.f;
+    if (i < M && k < in) v = (float)(2.0 * (x[(int64_t)i * in + k] - lo[k]) / ((double)hi[k] - lo[k]) - 1.0);
+    A0[r * kFwdLd0 + k] = (__bf16)v;
+    if (TRAIN && i < M) xn[(int64_t)i * 32 + k] = v;
+  }
+  __syncthreads();
+  dense_layer(A0, kFwdLd0, 32, W1b, 32, hid, [&](int r, int c, float acc) {
+    const float v = acc + b1[c];
+    const float h = silu_f(v);
+    H1[r * ldh + c] = (__bf16)h;
+    const int i = i0 + r;
+    if (TRAIN && i < M) {
+      z1[(int64_t)i * hid + c] = v;
+      h1[(int64_t)i * hid + c] = h;
+    }
+  });
+  __syncthreads();
+  dense_layer(H1, ldh, hid, W2b, hid, hid, [&](int r, int c, float acc) {
+    const float v = acc + b2[c];
+    const float h = silu_f(v);
+    H2[r * ldh + c] = (__bf16)h;
+    const int i = i0 + r;
+    if (TRAIN && i < M) {
+      z2[(int64_t)i * hid + c] = v;
+      h2[(int64_t)i * hid + c] = h;
+    }
+  });
+  __syncthreads();
+  dense_layer(H2, ldh, hid, W3b, hid, outp, [&](int r, int c, float acc) {
+    const int i = i0 + r;
+    if (i >= M || c >= out) return;
+    const float v = acc + b3[c];
+    if (TRAIN) yo[(int64_t)i * out + c] = v;
+    else coef[(int64_t)i * out + c] = (double)v * (double)sd[c] + (double)mean[c];
+  });
+}
+
+// BF16 copies of the weights in the fused layout (W1 padded to 32 inputs, W3 to outp
+// outputs, zeros there); optionally advances the Adam step counter afterwards.
+__global__ void __launch_bounds__(256)
+k_mlp_pack(int in, int hid, int out, int outp, const float *__restrict__ w, int64_t oW1, int64_t oW2, int64_t oW3,
+           __bf16 *__restrict__ W1b, __bf16 *__restrict__ W2b, __bf16 *__restrict__ W3b, int32_t *tstep) {
+  const int64_t n1 = (int64_t)hid * 32, n2 = (int64_t)hid * hid, n3 = (int64_t)outp * hid;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n1 + n2 + n3;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < n1) {
+      const int64_t j = e >> 5, k = e & 31;
+      W1b[e] = (__bf16)(k < in ? w[oW1 + j * in + k] : 0.f);
+    } else if (e < n1 + n2) {
+      W2b[e - n1] = (__bf16)w[oW2 + (e - n1)];
+    } else {
+      const int64_t f = e - n1 - n2;
+      W3b[f] = (__bf16)(f / hid < out ? w[oW3 + f] : 0.f);
+    }
+  }
+  if (tstep && blockIdx.x == 0 && threadIdx.x == 0) *tstep += 1;
 }
 
 }  // namespace hs
@@ -481,7 +564,7 @@ __global__ void k_step_inc(int32_t *tstep) {
 // MLP handle and C ABI
 // ---------------------------------------------------------------------------------------
 struct hs_mlp_s {
-  int32_t in = 0, hid = 0, out = 0, kin = 32;
+  int32_t in = 0, hid = 0, out = 0, kin = 32, outp = 0;  // outp: out rounded up to 64
   int64_t nparam = 0;
   // parameter offsets (floats) inside one weights array
   int64_t oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
@@ -489,7 +572,7 @@ struct hs_mlp_s {
   int32_t max_batch = 0;
   int64_t off_w = 0, off_m = 0, off_v = 0, off_g = 0, off_norm = 0, off_t = 0, off_loss = 0,
           off_x = 0, off_z1 = 0, off_h1 = 0, off_z2 = 0, off_h2 = 0, off_y = 0, off_tn = 0,
-          off_dy = 0, off_dz2 = 0, off_dz1 = 0, dev_bytes = 0;
+          off_dy = 0, off_dz2 = 0, off_dz1 = 0, off_wb = 0, dev_bytes = 0;
   void layout(int32_t mb) {
     max_batch = mb;
     int64_t off = 0;
@@ -515,6 +598,7 @@ struct hs_mlp_s {
     off_dy = take(4 * (int64_t)mb * out);
     off_dz2 = take(4 * (int64_t)mb * hid);
     off_dz1 = take(4 * (int64_t)mb * hid);
+    off_wb = take(2 * ((int64_t)hid * 32 + (int64_t)hid * hid + (int64_t)outp * hid));
     dev_bytes = off;
   }
 };
@@ -533,19 +617,30 @@ void gemm(hipStream_t s, int M, int N, int K, const float *A, int64_t sa0, int64
                      sb1, C, ldc, bias, Z, H, Zin);
 }
 
-int32_t mlp_forward(hs_mlp_s *p, void *dev, int batch, hipStream_t s) {
-  float *w = F(dev, p->off_w);
-  const int in = p->in, hid = p->hid, out = p->out, kin = p->kin;
-  (void)in;
-  // Z1 = Xn W1^T + b1, H1 = silu(Z1)
-  gemm<hs::kEpiBiasSilu>(s, batch, hid, p->in, F(dev, p->off_x), kin, 1, w + p->oW1, 1, p->in, nullptr, hid,
-                         w + p->ob1, F(dev, p->off_z1), F(dev, p->off_h1));
-  gemm<hs::kEpiBiasSilu>(s, batch, hid, hid, F(dev, p->off_h1), hid, 1, w + p->oW2, 1, hid, nullptr, hid,
-                         w + p->ob2, F(dev, p->off_z2), F(dev, p->off_h2));
-  gemm<hs::kEpiStore>(s, batch, out, hid, F(dev, p->off_h2), hid, 1, w + p->oW3, 1, hid, F(dev, p->off_y), out,
-                      w + p->ob3);
-  HS_HIP(hipGetLastError());
-  return HS_OK;
+__bf16 *WB(void *dev, const hs_mlp_s *p, int layer) {
+  __bf16 *b = reinterpret_cast<__bf16 *>(static_cast<uint8_t *>(dev) + p->off_wb);
+  if (layer == 1) return b;
+  if (layer == 2) return b + (int64_t)p->hid * 32;
+  return b + (int64_t)p->hid * 32 + (int64_t)p->hid * p->hid;
+}
+
+void mlp_pack(hs_mlp_s *p, void *dev, int32_t *tstep, hipStream_t s) {
+  const int64_t n = (int64_t)p->hid * 32 + (int64_t)p->hid * p->hid + (int64_t)p->outp * p->hid;
+  const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(hs::k_mlp_pack, dim3(g), dim3(256), 0, s, p->in, p->hid, p->out, p->outp,
+                     (const float *)F(dev, p->off_w), p->oW1, p->oW2, p->oW3, WB(dev, p, 1), WB(dev, p, 2),
+                     WB(dev, p, 3), tstep);
+}
+
+template <bool TRAIN>
+void mlp_fwd(hs_mlp_s *p, void *dev, int batch, const double *x, double *coef, hipStream_t s) {
+  const float *w = F(dev, p->off_w);
+  const size_t lds = sizeof(__bf16) * ((size_t)hs::kFwdRows * hs::kFwdLd0 + 2 * (size_t)hs::kFwdRows * (p->hid + 8));
+  hipLaunchKernelGGL((hs::k_mlp_fwd<TRAIN>), dim3((batch + hs::kFwdRows - 1) / hs::kFwdRows), dim3(256), lds, s,
+                     batch, p->in, p->hid, p->out, p->outp, x, (const float *)F(dev, p->off_norm), WB(dev, p, 1),
+                     w + p->ob1, WB(dev, p, 2), w + p->ob2, WB(dev, p, 3), w + p->ob3, coef,
+                     F(dev, p->off_x), F(dev, p->off_z1), F(dev, p->off_h1), F(dev, p->off_z2), F(dev, p->off_h2),
+                     F(dev, p->off_y));
 }
 
 }  // namespace
@@ -636,6 +731,7 @@ int32_t hs_mlp_create(int32_t in, int32_t hidden, int32_t out, hs_mlp *mlp) {
   p->in = in;
   p->hid = hidden;
   p->out = out;
+  p->outp = (out + 63) / 64 * 64;
   int64_t o = 0;
   p->oW1 = o;
   o += (int64_t)hidden * in;
@@ -678,6 +774,8 @@ int32_t hs_mlp_upload_params(hs_mlp mlp, void *dev, const float *weights_host, c
   HS_HIP(hipMemcpyAsync(F(dev, mlp->off_m), zeros.data(), 4 * mlp->nparam, hipMemcpyHostToDevice, s));
   HS_HIP(hipMemcpyAsync(F(dev, mlp->off_v), zeros.data(), 4 * mlp->nparam, hipMemcpyHostToDevice, s));
   HS_HIP(hipMemcpyAsync(F(dev, mlp->off_t), zeros.data(), 4, hipMemcpyHostToDevice, s));
+  mlp_pack(mlp, dev, nullptr, s);
+  HS_HIP(hipGetLastError());
   HS_HIP(hipStreamSynchronize(s));  // the host staging above is pageable and short-lived
   return HS_OK;
 }
@@ -696,15 +794,7 @@ int32_t hs_mlp_predict(hs_mlp mlp, void *dev, int32_t batch, const double *x_dev
   if (!mlp || !dev || !x_dev || !coef_dev) return hs::fail(HS_E_INVALID, "hs_mlp_predict: NULL argument");
   if (batch < 1 || batch > mlp->max_batch) return hs::fail(HS_E_WORKSPACE, "hs_mlp_predict: batch above max_batch");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const float *nrm = F(dev, mlp->off_norm);
-  const int64_t nx = (int64_t)batch * mlp->kin;
-  hipLaunchKernelGGL(hs::k_norm_in, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, batch, mlp->in, mlp->kin,
-                     x_dev, nrm, nrm + mlp->in, F(dev, mlp->off_x));
-  int32_t st = mlp_forward(mlp, dev, batch, s);
-  if (st != HS_OK) return st;
-  const int64_t ny = (int64_t)batch * mlp->out;
-  hipLaunchKernelGGL(hs::k_denorm_out, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s, ny, mlp->out,
-                     F(dev, mlp->off_y), nrm + 2 * mlp->in, nrm + 2 * mlp->in + mlp->out, coef_dev);
+  mlp_fwd<false>(mlp, dev, batch, x_dev, coef_dev, s);  // one launch: normalise, 3 layers, de-normalise
   HS_HIP(hipGetLastError());
   return HS_OK;
 }
@@ -732,13 +822,11 @@ int32_t hs_mlp_train_step(hs_mlp mlp, void *dev, int32_t batch, const double *x_
   const int in = mlp->in, hid = mlp->hid, out = mlp->out, kin = mlp->kin;
   float *w = F(dev, mlp->off_w), *g = grads_dev ? grads_dev : F(dev, mlp->off_g);
   const float *nrm = F(dev, mlp->off_norm);
-  const int64_t nx = (int64_t)batch * kin, ny = (int64_t)batch * out;
-  hipLaunchKernelGGL(hs::k_norm_in, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, batch, in, kin, x_dev, nrm,
-                     nrm + in, F(dev, mlp->off_x));
+  const int64_t ny = (int64_t)batch * out;
   hipLaunchKernelGGL(hs::k_norm_out, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s, ny, out, target_dev,
                      nrm + 2 * in, nrm + 2 * in + out, F(dev, mlp->off_tn));
-  int32_t st = mlp_forward(mlp, dev, batch, s);
-  if (st != HS_OK) return st;
+  // forward in one launch, keeping the normalised input and the activations
+  mlp_fwd<true>(mlp, dev, batch, x_dev, nullptr, s);
   hipLaunchKernelGGL(hs::k_mse, dim3(1), dim3(256), 0, s, ny, F(dev, mlp->off_y), F(dev, mlp->off_tn),
                      F(dev, mlp->off_dy), loss_dev ? loss_dev : F(dev, mlp->off_loss));
   float *dy = F(dev, mlp->off_dy), *h2 = F(dev, mlp->off_h2), *h1 = F(dev, mlp->off_h1);
@@ -760,7 +848,8 @@ int32_t hs_mlp_train_step(hs_mlp mlp, void *dev, int32_t batch, const double *x_
   const unsigned ab = (unsigned)((mlp->nparam + 255) / 256);
   hipLaunchKernelGGL(hs::k_adam, dim3(ab), dim3(256), 0, s, mlp->nparam, w, (const float *)g, F(dev, mlp->off_m),
                      F(dev, mlp->off_v), lr, (const int32_t *)F(dev, mlp->off_t));
-  hipLaunchKernelGGL(hs::k_step_inc, dim3(1), dim3(64), 0, s, (int32_t *)F(dev, mlp->off_t));
+  // refresh the BF16 copies used by the forward pass, then advance the step counter
+  mlp_pack(mlp, dev, (int32_t *)F(dev, mlp->off_t), s);
   HS_HIP(hipGetLastError());
   return HS_OK;
 }
