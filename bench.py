@@ -118,6 +118,7 @@ def main():
     ap.add_argument("--forms", type=int, default=1, help="also measure the FP32 and batched forms")
     ap.add_argument("--batch-log2-bmax", type=float, default=10.0)
     ap.add_argument("--n10-steps", type=int, default=20, help="steps of the N=10 FP32/FP64 comparison")
+    ap.add_argument("--train-steps", type=int, default=3000, help="Adam steps of the learned form")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -193,6 +194,7 @@ def main():
         forms["fp32"] = fp32_form(hs, idx, pot, c0, stream, args)
         forms["batched"] = batched_form(hs, stream, args)
         forms["fp32_n10"] = fp32_n10_form(hs, stream, args)
+        forms["learned"] = learned_form(hs, stream, args)
 
     cpu = None
     if not args.no_cpu:
@@ -299,6 +301,113 @@ def fp32_n10_form(hs, stream, args):
             "fp32_us_per_matvec": round(mv_us["fp32"], 1), "fp64_us_per_matvec": round(mv_us["fp64"], 1),
             "fp32_alg_gbs": round(2 * S["fp32"] * idx.size / mv_us["fp32"] / 1e3, 1),
             "fp64_alg_gbs": round(2 * S["fp64"] * idx.size / mv_us["fp64"] / 1e3, 1)}
+
+
+def learned_form(hs, stream, args):
+    """Learned coefficients, N = 4: Gaussian wells on circles expanded in Hermite
+    polynomials of total degree <= 6 (210 coefficients).  Targets from the Gauss-Hermite
+    projection (Q = 16) of 4096 parameter draws; the 7-256-256-210 network trained with
+    Adam (batch 256); accuracy against a Q = 24 judge on 256 held-out draws; coefficient
+    latency of network and quadrature; one propagation step at product bound 8192 with
+    either coefficient source."""
+    import math
+    import numpy as np
+    import torch
+    from synth import (coherent_state, draw_surrogate_params, mlp_initial_weights, surrogate_geometry,
+                       surrogate_param_box)
+
+    N, D, Q, G = 4, 6, 16, 3
+    geom = surrogate_geometry(N, G, seed=7)
+    lo, hi = surrogate_param_box()
+    dev = "cuda"
+    P = torch.from_numpy(draw_surrogate_params(4096, seed=11)).to(dev)
+    T = hs.gh_project(geom, P, D, Q)
+    Tn = T.cpu().numpy()
+    mean, sd = Tn.mean(axis=0), Tn.std(axis=0) + 1e-3 * np.abs(Tn).max()
+    nout = Tn.shape[1]
+    net = hs.MLP(7, 256, nout, max_batch=4096)
+    net.upload(mlp_initial_weights([7, 256, 256, nout], 21), lo, hi, mean, sd)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev).manual_seed(0)
+    bs = 256
+    sels = torch.randint(0, 4096, (args.train_steps, bs), generator=gen, device=dev)
+    Xb = P[sels]  # all batches gathered before timing
+    Yb = T[sels]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(args.train_steps):
+        lr = 2e-3 * 0.5 * (1 + math.cos(math.pi * it / args.train_steps)) + 1e-5
+        net.train_step(Xb[it], Yb[it], lr, loss=loss)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    fwd_flops = 2 * bs * (7 * 256 + 256 * 256 + 256 * nout)
+    step_flops = 3 * fwd_flops  # forward, and two products per layer backward
+    # accuracy on held-out draws against a finer quadrature
+    Pv = torch.from_numpy(draw_surrogate_params(256, seed=12)).to(dev)
+    J = hs.gh_project(geom, Pv, D, 24).cpu().numpy()
+    scale = np.linalg.norm(J, axis=1)
+    err_net = float(np.median(np.linalg.norm(net.predict(Pv).cpu().numpy() - J, axis=1) / scale))
+    err_q = {q: float(np.median(np.linalg.norm(hs.gh_project(geom, Pv, D, q).cpu().numpy() - J, axis=1) / scale))
+             for q in (4, 5, 6, 8, 16)}
+    q_match = min([q for q in err_q if err_q[q] <= err_net] or [16])
+
+    def lat_us(fn, reps=50):
+        fn()
+        torch.cuda.synchronize()
+        return event_time_ms(fn, reps, stream) * 1e3 / reps
+
+    out1 = torch.empty((1, nout), dtype=torch.float64, device=dev)
+    out256 = torch.empty((256, nout), dtype=torch.float64, device=dev)
+    lat = {"network_b1": lat_us(lambda: net.predict(Pv[:1], out=out1)),
+           "network_b256": lat_us(lambda: net.predict(Pv, out=out256)),
+           "quad_q16_b1": lat_us(lambda: hs.gh_project(geom, Pv[:1], D, Q, out=out1)),
+           "quad_q16_b256": lat_us(lambda: hs.gh_project(geom, Pv, D, Q, out=out256)),
+           "quad_matched_b1": lat_us(lambda: hs.gh_project(geom, Pv[:1], D, q_match, out=out1)),
+           "quad_matched_b256": lat_us(lambda: hs.gh_project(geom, Pv, D, q_match, out=out256))}
+    # one step at product bound 8192 with each coefficient source
+    degs = hs.total_degree_multi_indices(N, D)
+    idx = hs.Index(N, 8192)
+    pot = hs.Pot(N, [(0.0, a) for a in degs], basis="herm")
+    c0 = coherent_state(idx.multi_indices(), np.array([0.5, 0.0, -0.3, 0.2]))
+    c0 /= np.linalg.norm(c0)
+    ws = hs.workspace(idx, pot, hs.HS_C128, M_KRYLOV)
+    prow = Pv[:1].clone()
+    coef = torch.empty((1, nout), dtype=torch.float64, device=dev)
+    res = {}
+    for src in ("network", "quadrature"):
+        c = torch.from_numpy(c0).to(dev)
+
+        def one():
+            if src == "network":
+                net.coeffs(geom, prow, D, Q, out=coef)
+            else:
+                hs.gh_project(geom, prow, D, Q, out=coef)
+            pot.set_coeffs_device(coef[0])
+            hs.step(idx, pot, c, 0.0, 0.002, M_KRYLOV, ws=ws)
+        one()
+        c.copy_(torch.from_numpy(c0))
+        res[src] = (event_time_ms(one, 3, stream) / 3, c)
+    x = torch.from_numpy(c0).to(dev)
+    yq, yn = torch.empty_like(x), torch.empty_like(x)
+    aws = hs.workspace(idx, pot, hs.HS_C128, 0)
+    hs.gh_project(geom, prow, D, Q, out=coef)
+    pot.set_coeffs_device(coef[0])
+    mv_ms = event_time_ms(lambda: hs.apply_h(idx, pot, x, yq, hs.HS_C128, aws), 3, stream) / 3
+    net.predict(prow, out=coef)
+    pot.set_coeffs_device(coef[0])
+    hs.apply_h(idx, pot, x, yn, hs.HS_C128, aws)
+    hc_diff = float(torch.linalg.norm(yn - yq) / torch.linalg.norm(yq))
+    return {"workload": "N=4, 3 Gaussian wells on circles, total degree 6 (210 Hermite coefficients); targets "
+                        "Gauss-Hermite Q=16 on 4096 draws; network 7-256-256-210 BF16 MFMA; step at product "
+                        "bound 8192 (%d rows), h=0.002, m=10" % idx.size,
+            "train_steps": args.train_steps, "train_samples_per_s": round(args.train_steps * bs / train_s, 1),
+            "train_tflops": round(args.train_steps * step_flops / train_s / 1e12, 3),
+            "final_loss": float(loss.item()),
+            "median_rel_err_network": err_net, "median_rel_err_quadrature": err_q, "quad_q_matched": q_match,
+            "latency_us": {k: round(v, 2) for k, v in lat.items()},
+            "step_ms_with_network": round(res["network"][0], 3),
+            "step_ms_with_quadrature": round(res["quadrature"][0], 3),
+            "h_apply_ms": round(mv_ms, 3), "hc_rel_diff_network_vs_quadrature": hc_diff}
 
 
 def batched_form(hs, stream, args, nsteps=3):

@@ -312,6 +312,13 @@ class Batch:
 # ---- learned coefficients -----------------------------------------------------------
 
 
+def total_degree_multi_indices(N: int, D: int):
+    """The multi-indices a with |a| <= D in lexicographic order: the coefficient order of
+    hs_gh_project, hs_mlp_predict and hs_sur_coeffs (terms of the learned potential)."""
+    import itertools
+    return [a for a in itertools.product(range(D + 1), repeat=N) if sum(a) <= D]
+
+
 def gh_ncoef(N: int, D: int) -> int:
     n = C.c_int32()
     hs_gh_ncoef(N, D, C.byref(n))

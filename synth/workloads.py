@@ -18,7 +18,7 @@ __all__ = [
     "TimeTerm", "henon_heiles_chain", "lex_order",
     "complex_normal_by_index", "coherent_state", "decay_vector",
     "batch_instances", "surrogate_geometry", "surrogate_param_box",
-    "draw_surrogate_params",
+    "draw_surrogate_params", "mlp_initial_weights",
 ]
 
 
@@ -153,3 +153,15 @@ def draw_surrogate_params(n: int, seed: int) -> np.ndarray:
     lo, hi = surrogate_param_box()
     rng = np.random.default_rng(seed)
     return lo + (hi - lo) * rng.uniform(size=(n, 7))
+
+
+def mlp_initial_weights(sizes, seed: int):
+    """Seeded initial weights of a dense network: W_i (fan_out x fan_in) uniform in
+    +-1/sqrt(fan_in), biases zero (keys W1, b1, W2, ...)."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for i in range(len(sizes) - 1):
+        bound = 1.0 / math.sqrt(sizes[i])
+        out[f"W{i + 1}"] = rng.uniform(-bound, bound, size=(sizes[i + 1], sizes[i]))
+        out[f"b{i + 1}"] = np.zeros(sizes[i + 1])
+    return out
