@@ -61,6 +61,12 @@ extern "C" int32_t hs_pot_upload(hs_pot pot, void *dev, int64_t bytes, void *str
   put(pot->off_freq, pot->freq.data(), pot->nterms);
   put(pot->off_phase, pot->phase.data(), pot->nterms);
   if (pot->fused) put(pot->off_M, pot->M.data(), (int64_t)pot->nslots * pot->nterms);
+  if (!pot->cptr.empty()) {  // combination table of a split program: cptr | cidx | cterm
+    int32_t *ct = reinterpret_cast<int32_t *>(img.data() + pot->off_comb);
+    std::memcpy(ct, pot->cptr.data(), 4 * pot->cptr.size());
+    std::memcpy(ct + pot->cptr.size(), pot->cidx.data(), 4 * pot->cidx.size());
+    std::memcpy(ct + pot->cptr.size() + pot->cidx.size(), pot->cterm.data(), 4 * pot->cterm.size());
+  }
   void *pinned = nullptr;
   HS_HIP(hipHostMalloc(&pinned, pot->dev_bytes, hipHostMallocDefault));
   std::memcpy(pinned, img.data(), pot->dev_bytes);

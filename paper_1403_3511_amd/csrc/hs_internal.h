@@ -130,13 +130,22 @@ struct HHCoef {
 };
 
 // Generic program of recurrence passes over whole vectors.
+// Program step over whole vectors (slot 0: input, slot 1: output y, others workspace).
+//  kind 0: dst = A X_axis(src) + Bc src - C prev + plus   (prev, plus optional)
+//  kind 1: y += coef * src
+//  kind 2: the combination W_o = sum_e beta[term_e] V_{in_e} (tables in the potential)
+// For kinds 0 and 1, term >= 0 accumulates beta[term] * (result) into y; term == -2
+// accumulates it with coefficient 1; term == -1 does not accumulate.
+constexpr int kTermOne = -2;
 struct PassOp {
-  int32_t kind;      // 0: dst = A X_axis(src) + Bc src - C prev ; 1: acc += coef[term] * src
+  int32_t kind;
   int32_t axis;      // axis for kind 0
   int32_t src, prev, dst;  // vector slots (-1 none)
   double A, Bc, C;   // recurrence coefficients
-  int32_t term;      // kind 1: term index into the coefficient array
+  int32_t term;
+  int32_t plus;      // kind 0: slot added to the result (-1 none)
 };
+constexpr int kMaxComb = 64;  // inputs / outputs of the combination step
 
 }  // namespace hs
 
@@ -154,10 +163,14 @@ struct hs_pot_s {
   // generic program
   std::vector<hs::PassOp> prog;
   int32_t nslots_vec = 0;             // vector slots used by the program
+  int32_t split = 0;                  // outer axes evaluated by Clenshaw sums (0: trie only)
+  // combination step (split > 0): output o = sum over entries e in [cptr[o], cptr[o+1])
+  // of beta[cterm[e]] * slot cin_slot[cidx[e]]
+  std::vector<int32_t> cin_slot, cout_slot, cptr, cidx, cterm;
   // device block: beta[kMaxTerms] | base | amp | freq | phase | M | hh coefficients
   int64_t dev_bytes = 0;
   int64_t off_beta = 0, off_base = 0, off_amp = 0, off_freq = 0, off_phase = 0, off_M = 0,
-          off_hh = 0;
+          off_hh = 0, off_comb = 0;
 };
 
 namespace hs {

@@ -374,13 +374,14 @@ k_diag(IndexDev ix, const typename V2<T>::t *__restrict__ x, typename V2<T>::t *
   y[r] = scal<T>((T)dval, x[r]);
 }
 
-// dst = A X_axis src + Bc src - C prev ; optionally y += beta[term] dst
+// dst = A X_axis src + Bc src - C prev + plus ; optionally y += beta[term] dst (term >= 0)
+// or y += dst (term == kTermOne)
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_pass(IndexDev ix, int axis, double A, double Bc, double Cc,
        const typename V2<T>::t *__restrict__ src, const typename V2<T>::t *__restrict__ prev,
-       typename V2<T>::t *__restrict__ dst, typename V2<T>::t *__restrict__ y,
-       const double *__restrict__ beta, int term) {
+       const typename V2<T>::t *__restrict__ plus, typename V2<T>::t *__restrict__ dst,
+       typename V2<T>::t *__restrict__ y, const double *__restrict__ beta, int term) {
   using C = typename V2<T>::t;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= ix.size) return;
@@ -396,10 +397,15 @@ k_pass(IndexDev ix, int axis, double A, double Bc, double Cc,
   C out = scal<T>((T)A, xs);
   fma_rc<T>(out, (T)Bc, s0);
   if (prev) fma_rc<T>(out, (T)(-Cc), prev[r]);
+  if (plus) {
+    const C pl = plus[r];
+    out.x += pl.x;
+    out.y += pl.y;
+  }
   dst[r] = out;
-  if (term >= 0) {
+  if (term != -1) {
     C yy = y[r];
-    fma_rc<T>(yy, (T)beta[term], out);
+    fma_rc<T>(yy, term >= 0 ? (T)beta[term] : T(1), out);
     y[r] = yy;
   }
 }
@@ -411,8 +417,39 @@ k_accum(int64_t n, const typename V2<T>::t *__restrict__ src, typename V2<T>::t 
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   typename V2<T>::t yy = y[r];
-  fma_rc<T>(yy, (T)beta[term], src[r]);
+  fma_rc<T>(yy, term >= 0 ? (T)beta[term] : T(1), src[r]);
   y[r] = yy;
+}
+
+// Combination of a split program: out_o = sum_{e in [cptr[o], cptr[o+1])} beta[cterm[e]] *
+// in_{cidx[e]}, row by row.  Each thread keeps its row's inputs in LDS (64 rows per block).
+struct CombSlots {
+  int32_t nin, nout;
+  int32_t in[kMaxComb], out[kMaxComb];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_combine(int64_t n, CombSlots cs, const typename V2<T>::t *__restrict__ x, typename V2<T>::t *__restrict__ y,
+          typename V2<T>::t *__restrict__ ws, int64_t stride, const int32_t *__restrict__ ctab,
+          const double *__restrict__ beta) {
+  using C = typename V2<T>::t;
+  extern __shared__ __align__(16) unsigned char csm[];
+  C *V = reinterpret_cast<C *>(csm);
+  const int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (r >= n) return;  // rows are independent: no barrier below
+  auto slot = [&](int k) -> C * {
+    if (k == 0) return const_cast<C *>(x);
+    if (k == 1) return y;
+    return ws + (int64_t)(k - 2) * stride;
+  };
+  for (int i = 0; i < cs.nin; ++i) V[i * 64 + threadIdx.x] = slot(cs.in[i])[r];
+  const int32_t *cptr = ctab, *cidx = ctab + cs.nout + 1, *cterm = cidx + ctab[cs.nout];
+  for (int o = 0; o < cs.nout; ++o) {
+    C acc = vz<T>();
+    for (int e = cptr[o]; e < cptr[o + 1]; ++e) fma_rc<T>(acc, (T)beta[cterm[e]], V[cidx[e] * 64 + threadIdx.x]);
+    slot(cs.out[o])[r] = acc;
+  }
 }
 
 // y = out_scale * y - prev_coef * prev_scale * prev (epilogue of the generic program)
@@ -496,10 +533,19 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
     if (op.kind == 0) {
       hipLaunchKernelGGL(k_pass<T>, dim3(g), dim3(256), 0, s, ix, op.axis, op.A, op.Bc, op.C,
                          (const C *)slot(op.src), op.prev >= 0 ? (const C *)slot(op.prev) : nullptr,
-                         slot(op.dst), (C *)y, beta, op.term);
-    } else {
+                         op.plus >= 0 ? (const C *)slot(op.plus) : nullptr, slot(op.dst), (C *)y, beta, op.term);
+    } else if (op.kind == 1) {
       hipLaunchKernelGGL(k_accum<T>, dim3(g), dim3(256), 0, s, idx->size, (const C *)slot(op.src),
                          (C *)y, beta, op.term);
+    } else {
+      CombSlots cs{};
+      cs.nin = (int32_t)p->cin_slot.size();
+      cs.nout = (int32_t)p->cout_slot.size();
+      for (int i = 0; i < cs.nin; ++i) cs.in[i] = p->cin_slot[i];
+      for (int i = 0; i < cs.nout; ++i) cs.out[i] = p->cout_slot[i];
+      const size_t lds = sizeof(C) * 64 * (size_t)std::max(cs.nin, 1);
+      hipLaunchKernelGGL(k_combine<T>, dim3(nblk(idx->size, 64)), dim3(64), lds, s, idx->size, cs, (const C *)x,
+                         (C *)y, (C *)ws, stride / (int64_t)sizeof(C), (const int32_t *)(pb + p->off_comb), beta);
     }
   }
   if (out_scale || prev)

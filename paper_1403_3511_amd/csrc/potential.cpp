@@ -133,6 +133,7 @@ struct TrieBuilder {
         op.prev = -1;
         op.dst = 1;
         op.term = order[i];
+        op.plus = -1;
         P->prog.push_back(op);
       }
       return;
@@ -167,6 +168,7 @@ struct TrieBuilder {
         op.Bc = Bc;
         op.C = (k == 0 ? 0.0 : C);
         op.term = -1;
+        op.plus = -1;
         last_op = (int)P->prog.size();
         P->prog.push_back(op);
         prev = cur;
@@ -185,6 +187,206 @@ struct TrieBuilder {
   }
 };
 
+// ---- split program: trie over the inner axes, Clenshaw sums over the outer axes ----
+// With outer axes 0..s-1 and inner axes s..N-1 (axis N-1 is applied first),
+//   W^pol c = sum_o p_{o_0}(X_0) ... p_{o_{s-1}}(X_{s-1}) W_o,
+//   W_o = sum_{terms t with outer part o} beta_t V_{inner(t)},
+//   V_i = p_{i_s}(X_s) ... p_{i_{N-1}}(X_{N-1}) c.
+// The V_i come from a trie of recurrence passes (shared from c outwards), the nested
+// sums over the outer axes from Clenshaw's recurrence with vector coefficients
+//   b_k = u_k + (A_k X + B_k) b_{k+1} - C_{k+1} b_{k+2},  sum_k p_k(X) u_k = b_0,
+// (shared from the outside inwards), and a per-row combination links the two.  Same
+// operator as the trie, in exact arithmetic.
+struct SplitBuilder {
+  hs_pot_s *P;
+  int N, s;
+  std::vector<hs::PassOp> prog;
+  int next = 2, max_slot = 2;
+  std::vector<int> freel;
+  // inner: vector slot of each inner multi-degree prefix (axes N-1 .. l), keyed by the
+  // degree string of axes l..N-1
+  std::map<std::vector<int>, int> inner_slot;
+  std::vector<int> cin_slot, cout_slot, cptr, cidx, cterm;
+  bool ok = true;
+
+  int alloc() {
+    if (!freel.empty()) {
+      const int x = freel.back();
+      freel.pop_back();
+      return x;
+    }
+    const int x = next++;
+    max_slot = std::max(max_slot, next);
+    return x;
+  }
+  void release(int x) {
+    if (x >= 2) freel.push_back(x);
+  }
+  int deg(int t, int l) const { return P->deg[t * N + l]; }
+  std::vector<int> inner_key(int t, int l) const {  // degrees of axes l..N-1
+    std::vector<int> k;
+    for (int a = l; a < N; ++a) k.push_back(deg(t, a));
+    return k;
+  }
+  hs::PassOp pass(int axis, int src, int prev, int dst, double A, double Bc, double C, int plus) const {
+    hs::PassOp op{};
+    op.kind = 0;
+    op.axis = axis;
+    op.src = src;
+    op.prev = prev;
+    op.dst = dst;
+    op.A = A;
+    op.Bc = Bc;
+    op.C = C;
+    op.term = -1;
+    op.plus = plus;
+    return op;
+  }
+
+  // V vectors of every inner node, level by level from axis N-1 down to axis s
+  void build_inner() {
+    inner_slot[std::vector<int>()] = 0;  // the input vector
+    for (int l = N - 1; l >= s; --l) {
+      // chains: parent key (axes l+1..N-1) -> largest degree on axis l among terms
+      std::map<std::vector<int>, int> kmax;
+      for (int t = 0; t < P->nterms; ++t) {
+        const std::vector<int> par = inner_key(t, l + 1);
+        int &m = kmax[par];
+        m = std::max(m, deg(t, l));
+      }
+      for (const auto &kv : kmax) {
+        const int u = inner_slot.at(kv.first);
+        int pm = -1, pc = u;
+        std::vector<int> key = kv.first;
+        key.insert(key.begin(), 0);
+        inner_slot[key] = u;  // p_0(X) u = u
+        for (int k = 0; k < kv.second; ++k) {
+          double A, Bc, C;
+          rec_coeffs(P->basis, P->scale, k, &A, &Bc, &C);
+          const int d = alloc();
+          prog.push_back(pass(l, pc, k == 0 ? -1 : pm, d, A, Bc, k == 0 ? 0.0 : C, -1));
+          key[0] = k + 1;
+          inner_slot[key] = d;
+          pm = pc;
+          pc = d;
+        }
+      }
+    }
+  }
+
+  // W_o for every outer multi-degree, one combination step
+  std::map<std::vector<int>, int> outer_slot;
+  void build_combination() {
+    std::map<std::vector<int>, std::vector<std::pair<int, int>>> rows;  // outer -> (V slot, term)
+    for (int t = 0; t < P->nterms; ++t) {
+      std::vector<int> o;
+      for (int a = 0; a < s; ++a) o.push_back(deg(t, a));
+      rows[o].push_back({inner_slot.at(inner_key(t, s)), t});
+    }
+    std::map<int, int> in_index;
+    for (auto &kv : rows)
+      for (auto &e : kv.second)
+        if (!in_index.count(e.first)) {
+          in_index[e.first] = (int)cin_slot.size();
+          cin_slot.push_back(e.first);
+        }
+    if ((int)cin_slot.size() > hs::kMaxComb || (int)rows.size() > hs::kMaxComb) {
+      ok = false;
+      return;
+    }
+    cptr.push_back(0);
+    for (auto &kv : rows) {
+      const int d = alloc();
+      outer_slot[kv.first] = d;
+      cout_slot.push_back(d);
+      for (auto &e : kv.second) {
+        cidx.push_back(in_index[e.first]);
+        cterm.push_back(e.second);
+      }
+      cptr.push_back((int)cidx.size());
+    }
+    hs::PassOp op{};
+    op.kind = 2;
+    op.src = op.prev = op.dst = op.plus = -1;
+    op.term = -1;
+    prog.push_back(op);
+    // inner vectors are dead after the combination (the input vector is slot 0)
+    std::vector<int> dead;
+    for (auto &kv : inner_slot) dead.push_back(kv.second);
+    std::sort(dead.begin(), dead.end());
+    dead.erase(std::unique(dead.begin(), dead.end()), dead.end());
+    for (int x : dead) release(x);
+  }
+
+  // slot of sum_{o_l..o_{s-1}} p(X_l) .. p(X_{s-1}) W_{prefix, o_l..}; at l = 0 the result
+  // is accumulated into y
+  int build_outer(int l, const std::vector<int> &prefix) {
+    if (l == s) return outer_slot.at(prefix);
+    std::map<int, int> child;  // degree on axis l -> slot
+    for (const auto &kv : outer_slot) {
+      if (!std::equal(prefix.begin(), prefix.end(), kv.first.begin())) continue;
+      const int k = kv.first[l];
+      if (child.count(k)) continue;
+      std::vector<int> pre = prefix;
+      pre.push_back(k);
+      child[k] = build_outer(l + 1, pre);
+    }
+    const int K = child.rbegin()->first;
+    auto u = [&](int k) { return child.count(k) ? child[k] : -1; };
+    if (K == 0) {
+      const int r = child[0];
+      if (l == 0) {
+        hs::PassOp op{};
+        op.kind = 1;
+        op.src = r;
+        op.prev = op.dst = op.plus = -1;
+        op.term = hs::kTermOne;
+        prog.push_back(op);
+      }
+      return r;
+    }
+    int b2 = -1, b1 = child[K];  // b_{k+2}, b_{k+1}
+    bool b2_temp = false, b1_temp = false;
+    for (int k = K - 1; k >= 0; --k) {
+      double A, Bc, C, A1, B1, C1;
+      rec_coeffs(P->basis, P->scale, k, &A, &Bc, &C);
+      rec_coeffs(P->basis, P->scale, k + 1, &A1, &B1, &C1);
+      const int d = alloc();
+      hs::PassOp op = pass(l, b1, b2, d, A, Bc, b2 >= 0 ? C1 : 0.0, u(k));
+      if (l == 0 && k == 0) op.term = hs::kTermOne;
+      prog.push_back(op);
+      if (b2 >= 0 && b2_temp) release(b2);
+      b2 = b1;
+      b2_temp = b1_temp;
+      b1 = d;
+      b1_temp = true;
+    }
+    if (b2 >= 0 && b2_temp) release(b2);
+    for (auto &kv : child) release(kv.second);  // coefficient vectors consumed
+    return b1;
+  }
+
+  bool build() {
+    build_inner();
+    build_combination();
+    if (!ok) return false;
+    build_outer(0, {});
+    return true;
+  }
+};
+
+// memory traffic of a program in vector passes (a recurrence pass reads src and its
+// neighbours, prev, plus and writes dst; an accumulation reads and writes y)
+double program_cost(const std::vector<hs::PassOp> &prog, int ncomb_in, int ncomb_out) {
+  double c = 0.0;
+  for (const auto &op : prog) {
+    if (op.kind == 0) c += 2.0 + (op.prev >= 0) + (op.plus >= 0) + (op.term != -1 ? 2.0 : 0.0);
+    else if (op.kind == 1) c += 3.0;
+    else c += ncomb_in + ncomb_out;
+  }
+  return c;
+}
+
 }  // namespace
 
 namespace hs {
@@ -193,6 +395,12 @@ int32_t compile_potential(hs_pot_s *P) {
   const int N = P->N;
   P->fused = try_fused(P);
   P->prog.clear();
+  P->split = 0;
+  P->cin_slot.clear();
+  P->cout_slot.clear();
+  P->cptr.clear();
+  P->cidx.clear();
+  P->cterm.clear();
   if (!P->fused) {
     // generic program: sort terms by (a_N, a_{N-1}, ..., a_1) and build the trie
     TrieBuilder tb{P, N, {}};
@@ -205,6 +413,25 @@ int32_t compile_potential(hs_pot_s *P) {
     });
     tb.rec(0, P->nterms, N - 1, 0);
     P->nslots_vec = tb.max_slot;
+    // a split between Clenshaw sums (outer axes) and the trie (inner axes) when it moves
+    // fewer vectors; slot count bounded so the workspace stays moderate
+    double best = program_cost(P->prog, 0, 0);
+    for (int s = 1; s <= N && P->nterms > 0; ++s) {
+      SplitBuilder sb{P, N, s};
+      if (!sb.build() || sb.max_slot > 160) continue;
+      const double c = program_cost(sb.prog, (int)sb.cin_slot.size(), (int)sb.cout_slot.size());
+      if (c < 0.8 * best) {
+        best = c;
+        P->split = s;
+        P->prog = sb.prog;
+        P->nslots_vec = sb.max_slot;
+        P->cin_slot = sb.cin_slot;
+        P->cout_slot = sb.cout_slot;
+        P->cptr = sb.cptr;
+        P->cidx = sb.cidx;
+        P->cterm = sb.cterm;
+      }
+    }
   }
   // device block layout
   int64_t off = 0;
@@ -220,6 +447,7 @@ int32_t compile_potential(hs_pot_s *P) {
   P->off_phase = take(8 * P->nterms);
   P->off_M = take(8 * (int64_t)std::max(1, P->nslots) * P->nterms);
   P->off_hh = take(8 * (int64_t)std::max(1, P->nslots));
+  P->off_comb = take(4 * (int64_t)(P->cptr.size() + 2 * P->cidx.size()));  // cptr | cidx | cterm
   P->dev_bytes = off;
   return HS_OK;
 }
