@@ -410,7 +410,12 @@ int32_t run_step(const StepJob &J, int m, int reorth, double h, void *cvoid, voi
                      (const double *)sc);
   for (int k = 0; k < m; ++k) {
     C *Vk = V + (int64_t)k * sv_el;
-    st = J.matvec(Vk, W, k > 0 ? (const void *)(V + (int64_t)(k - 1) * sv_el) : nullptr, k, sc, aws, s);
+    // With the Gram-Schmidt pass against all previous vectors, the projection removes
+    // <v_{k-1}, H v_k> v_{k-1} whether or not beta_{k-1} v_{k-1} was subtracted first
+    // (and alpha_k = Re <v_k, H v_k> either way), so the H application then skips the
+    // previous vector; the plain recurrence subtracts it.
+    const bool sub_prev = (k > 0) && !reorth;
+    st = J.matvec(Vk, W, sub_prev ? (const void *)(V + (int64_t)(k - 1) * sv_el) : nullptr, k, sc, aws, s);
     if (st != HS_OK) return st;
     // the last step needs alpha_{m-1} only: no orthogonalisation against older vectors
     const bool last = (k == m - 1);
