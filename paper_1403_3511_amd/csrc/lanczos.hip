@@ -44,6 +44,26 @@ template <typename T> struct CT;
 template <> struct CT<double> { using t = double2; };
 template <> struct CT<float> { using t = float2; };
 
+// Streaming accesses of the Krylov vectors, marked non-temporal so that they do not
+// push the index metadata and the current vector out of the caches between H
+// applications.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 nt_ld(const double2 *p) {
+  const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
+  return make_double2(v[0], v[1]);
+}
+__device__ __forceinline__ float2 nt_ld(const float2 *p) {
+  const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(p));
+  return make_float2(v[0], v[1]);
+}
+__device__ __forceinline__ void nt_st(double2 *p, double2 v) {
+  d2v t;
+  t[0] = v.x;
+  t[1] = v.y;
+  __builtin_nontemporal_store(t, reinterpret_cast<d2v *>(p));
+}
+
 // Krylov vectors are stored unnormalised: v_q = s_q V_q with s_0 = 1 (the start vector
 // is normalised when written) and s_q = 1 / beta_{q-1}.
 __device__ __forceinline__ double vscale(const double *sc, int q) {
@@ -59,7 +79,7 @@ k_snorm2_part(SegView sv, const double2 *__restrict__ c, double *__restrict__ pa
   sv.get(blockIdx.x, inst, r0, len);
   double acc = 0.0;
   for (int i = threadIdx.x; i < len; i += blockDim.x) {
-    const double2 v = c[r0 + i];
+    const double2 v = nt_ld(c + r0 + i);
     acc = fma(v.x, v.x, fma(v.y, v.y, acc));
   }
   const double s = block_sum(acc, sh);
@@ -95,7 +115,7 @@ k_sstart(SegView sv, const double2 *__restrict__ c, typename CT<T>::t *__restric
   sv.get(blockIdx.x, inst, r0, len);
   const double s = scall[(int64_t)inst * Scal::size + Scal::inv0];
   for (int i = threadIdx.x; i < len; i += blockDim.x) {
-    const double2 a = c[r0 + i];
+    const double2 a = nt_ld(c + r0 + i);
     typename CT<T>::t o;
     o.x = (T)(a.x * s);
     o.y = (T)(a.y * s);
@@ -119,11 +139,12 @@ k_sdots_part(SegView sv, const typename CT<T>::t *__restrict__ V, int64_t stride
   for (int q = 0; q < kDotChunk; ++q) ar[q] = ai[q] = 0.0;
   for (int i = threadIdx.x; i < len; i += blockDim.x) {
     const int64_t r = r0 + i;
-    const double wr = W[r].x, wi = W[r].y;
+    const typename CT<T>::t wv = nt_ld(W + r);
+    const double wr = wv.x, wi = wv.y;
 #pragma unroll
     for (int q = 0; q < kDotChunk; ++q) {
       if (q < cnt) {
-        const typename CT<T>::t v = V[(int64_t)(lo + q) * stride + r];
+        const typename CT<T>::t v = nt_ld(V + (int64_t)(lo + q) * stride + r);
         const double vr = v.x, vi = v.y;
         ar[q] = fma(vr, wr, fma(vi, wi, ar[q]));
         ai[q] = fma(vr, wi, fma(-vi, wr, ai[q]));
@@ -176,19 +197,20 @@ k_supdate(SegView sv, const typename CT<T>::t *__restrict__ V, int64_t stride, i
   double acc = 0.0;
   for (int i = threadIdx.x; i < len; i += blockDim.x) {
     const int64_t r = r0 + i;
-    double wr = W[r].x, wi = W[r].y;
+    const typename CT<T>::t wv = nt_ld(W + r);
+    double wr = wv.x, wi = wv.y;
     if (reorth) {
       for (int q = lo; q <= k; ++q) {
         const double vs = vscale(sc, q);
         const double dr = sc[Scal::dre + q] * vs, di = sc[Scal::dim + q] * vs;
-        const typename CT<T>::t v = V[(int64_t)q * stride + r];
+        const typename CT<T>::t v = nt_ld(V + (int64_t)q * stride + r);
         const double vr = v.x, vi = v.y;
         wr -= dr * vr - di * vi;
         wi -= dr * vi + di * vr;
       }
     } else {
       const double a = sc[Scal::alpha + k] * vscale(sc, k);
-      const typename CT<T>::t v = V[(int64_t)k * stride + r];
+      const typename CT<T>::t v = nt_ld(V + (int64_t)k * stride + r);
       wr -= a * (double)v.x;
       wi -= a * (double)v.y;
     }
@@ -343,11 +365,11 @@ k_scombine(SegView sv, const typename CT<T>::t *__restrict__ V, int64_t stride, 
     for (int k = 0; k < me && k < m; ++k) {
       const double vs = vscale(sc, k);
       const double yr = sc[Scal::yre + k] * vs, yi = sc[Scal::yim + k] * vs;
-      const typename CT<T>::t v = V[(int64_t)k * stride + r];
+      const typename CT<T>::t v = nt_ld(V + (int64_t)k * stride + r);
       cr += yr * v.x - yi * v.y;
       ci += yr * v.y + yi * v.x;
     }
-    c[r] = make_double2(cr, ci);
+    nt_st(c + r, make_double2(cr, ci));
   }
 }
 
