@@ -288,7 +288,20 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
   });
   acc = scal<T>(oscale, acc);
   if (prev) fma_rc<T>(acc, -pcoef, pv);
-  y[self] = acc;
+  // the result is streamed to its consumers (inner products, update): non-temporal store
+  if constexpr (sizeof(T) == 8) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    v2 t;
+    t[0] = acc.x;
+    t[1] = acc.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<v2 *>(y + self));
+  } else {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    v2 t;
+    t[0] = acc.x;
+    t[1] = acc.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<v2 *>(y + self));
+  }
 }
 
 // One launch covers both kinds of work.  The grid is kXcd equal ranges; block b runs on
