@@ -1,5 +1,7 @@
-"""Oracle: exponential-midpoint Magnus step with an m-step Lanczos approximation of the
-matrix exponential (Sec. 2.1 eq. expMPR, Sec. 2.2, Fig. 4 time_propagation).
+"""Oracle: Magnus steps with an m-step Lanczos approximation of the matrix exponential:
+the exponential midpoint rule (Sec. 2.1 eq. expMPR) and the fourth-order two-stage
+Gauss-Legendre Magnus scheme (Sec. 2.1 eq. 2stageMagnus); Sec. 2.2; Fig. 4
+time_propagation.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
@@ -68,13 +70,46 @@ def magnus_midpoint_step(idx, pot_at, applyH_factory, c, t, h, m, reorth=True):
     return lanczos_expm(A, c, h, m, reorth)
 
 
-def propagate(idx, pot_at, applyH_factory, c0, t0, h, nsteps, m, reorth=True):
-    """time_propagation of Fig. 4: nsteps exponential-midpoint Lanczos steps."""
+# Gauss-Legendre nodes of the two-stage scheme (Sec. 2.1 eq. 2stageMagnus)
+GL2_NODES = (0.5 - np.sqrt(3.0) / 6.0, 0.5 + np.sqrt(3.0) / 6.0)
+
+
+def magnus4_operator(applyA1, applyA2, h):
+    """The Hermitian M with Omega^n = -i h M for the two-stage scheme (Sec. 2.1, eq.
+    2stageMagnus).  Omega^n = -(i/2) h (A_1 + A_2) - (sqrt(3)/12) h^2 [A_2, A_1]; dividing
+    by -i h gives M = (A_1 + A_2)/2 - i (sqrt(3) h / 12) (A_2 A_1 - A_1 A_2), applied to a
+    vector with four operator products (A_1 v, A_2 v, A_2 A_1 v, A_1 A_2 v)."""
+    g = np.sqrt(3.0) * h / 12.0
+
+    def M(v):
+        u1 = applyA1(v)
+        u2 = applyA2(v)
+        comm = applyA2(u1) - applyA1(u2)
+        return 0.5 * (u1 + u2) - 1j * g * comm
+
+    return M
+
+
+def magnus4_step(idx, pot_at, applyH_factory, c, t, h, m, reorth=True):
+    """One step of the two-stage Gauss-Legendre Magnus scheme (Sec. 2.1, eq.
+    2stageMagnus): A_j = A(t_n + c_j h) with c_{1,2} = 1/2 -+ sqrt(3)/6, and
+    exp(-i h M) c by the Lanczos method of Sec. 2.2."""
+    A1 = applyH_factory(pot_at(t + GL2_NODES[0] * h))
+    A2 = applyH_factory(pot_at(t + GL2_NODES[1] * h))
+    return lanczos_expm(magnus4_operator(A1, A2, h), c, h, m, reorth)
+
+
+def propagate(idx, pot_at, applyH_factory, c0, t0, h, nsteps, m, reorth=True, scheme=2):
+    """time_propagation of Fig. 4: nsteps Magnus-Lanczos steps of the exponential
+    midpoint rule (scheme 2) or of the two-stage Gauss-Legendre scheme (scheme 4)."""
+    if scheme not in (2, 4):
+        raise ValueError("scheme must be 2 or 4")
+    one = magnus_midpoint_step if scheme == 2 else magnus4_step
     c = np.asarray(c0, dtype=np.complex128).copy()
     t = t0
     m_effs = []
     for _ in range(nsteps):
-        c, me, _, _ = magnus_midpoint_step(idx, pot_at, applyH_factory, c, t, h, m, reorth)
+        c, me, _, _ = one(idx, pot_at, applyH_factory, c, t, h, m, reorth)
         m_effs.append(me)
         t += h
     return c, m_effs

@@ -15,7 +15,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "TimeTerm", "henon_heiles_chain", "lex_order",
+    "TimeTerm", "henon_heiles_chain", "stretched_hh_cw_laser", "lex_order",
     "complex_normal_by_index", "coherent_state", "decay_vector",
     "batch_instances", "surrogate_geometry", "surrogate_param_box",
     "draw_surrogate_params", "mlp_initial_weights",
@@ -61,6 +61,20 @@ def henon_heiles_chain(N: int, lam: float = 0.111, laser: float = 0.0,
     if laser != 0.0:
         for d in range(N):
             terms.append(TimeTerm(0.0, _deg(N, [(d, 1)]), amp=laser, freq=laser_freq))
+    return terms
+
+
+def stretched_hh_cw_laser(N: int, L: float = 16.0):
+    """The potential of the paper's time-integration study (Sec. 6, eq.
+    HenonHeilesExperiments), in the reading that reproduces its error table:
+        W(x, t) = sum_{l<N} [(x_l/L)^2 (x_{l+1}/L) - (x_{l+1}/L)^3 / 3] - sin^2(t) x_1 / L,
+    with no harmonic term (W is the potential beyond the oscillator).  The laser factor
+    -sin^2(t) / L is written as -1/(2L) + 1/(2L) sin(2t + pi/2)."""
+    terms = []
+    for l in range(N - 1):
+        terms.append(TimeTerm(1.0 / L ** 3, _deg(N, [(l, 2), (l + 1, 1)])))
+        terms.append(TimeTerm(-1.0 / (3.0 * L ** 3), _deg(N, [(l + 1, 3)])))
+    terms.append(TimeTerm(-0.5 / L, _deg(N, [(0, 1)]), amp=0.5 / L, freq=2.0, phase=0.5 * math.pi))
     return terms
 
 
