@@ -135,6 +135,27 @@ int32_t hs_step(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev, in
                 double t, double *t_dev, double h, int32_t m, int32_t reorth, void *c, void *ws,
                 double *diag_dev, void *stream);
 
+/* ---- fourth-order step (paper Sec. 2.1, eq. 2stageMagnus) ------------------------
+ * Two-stage Gauss-Legendre Magnus scheme: Omega = -i h M with
+ *   M = (A_1 + A_2)/2 - i (sqrt(3) h / 12) (A_2 A_1 - A_1 A_2),  A_j = H(t + c_j h),
+ *   c_{1,2} = 1/2 -+ sqrt(3)/6.
+ * The two coefficient sets live in two device parameter blocks of the same potential
+ * (pot_dev1, pot_dev2: distinct buffers of hs_pot_device_bytes bytes, both uploaded
+ * with hs_pot_upload; the step overwrites their coefficients).  One application of M
+ * costs four H applications and one combination pass.
+ * hs_magnus4_workspace_bytes(m = 0) sizes the workspace of hs_apply_magnus4, m >= 1
+ * that of hs_step_magnus4 (three vectors more than hs_workspace_bytes).
+ * hs_apply_magnus4: y = M c with the coefficients currently in the two blocks (c != y).
+ * hs_step_magnus4: c <- V_m exp(-i h T_m) e_1 ||c|| with T_m from m Lanczos steps on M;
+ * arguments, dtype, reorth, t_dev and diag_dev as for hs_step.                       */
+int32_t hs_magnus4_workspace_bytes(hs_index idx, hs_pot pot, int32_t dtype, int32_t m, int64_t *bytes);
+int32_t hs_apply_magnus4(hs_index idx, const void *idx_dev, hs_pot pot, const void *pot_dev1,
+                         const void *pot_dev2, int32_t dtype, double h, const void *c, void *y,
+                         void *ws, void *stream);
+int32_t hs_step_magnus4(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev1, void *pot_dev2,
+                        int32_t dtype, double t, double *t_dev, double h, int32_t m, int32_t reorth,
+                        void *c, void *ws, double *diag_dev, void *stream);
+
 /* ---- batched form: many (index, potential) instances in one persistent launch ----
  * Instances are described by handles plus their uploaded device blocks (which must stay
  * alive); vectors of all instances are packed back to back in one device buffer with

@@ -28,6 +28,14 @@ int32_t launch_step(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *
                     int32_t dtype, double t, double *t_dev, double h, int m, int reorth, void *c,
                     void *ws, double *diag, hipStream_t s);
 int64_t step_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32_t dtype, int m);
+int64_t m4_apply_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32_t dtype);
+int64_t step4_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32_t dtype, int m);
+int32_t launch_apply_m4(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p, const void *pot1,
+                        const void *pot2, int32_t dtype, double h, const void *x, void *y, void *ws,
+                        hipStream_t s);
+int32_t launch_step_m4(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p, void *pot1,
+                       void *pot2, int32_t dtype, double t, double *t_dev, double h, int m, int reorth,
+                       void *c, void *ws, double *diag, hipStream_t s);
 
 static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
@@ -137,4 +145,50 @@ extern "C" int32_t hs_step(hs_index idx, const void *idx_dev, hs_pot pot, void *
     return hs::fail(HS_E_INVALID, "hs_step: device pointer not 16-byte aligned");
   return hs::launch_step(idx, idx_dev, pot, pot_dev, dtype, t, t_dev, h, m, reorth, c, ws, diag_dev,
                          static_cast<hipStream_t>(stream));
+}
+
+extern "C" int32_t hs_magnus4_workspace_bytes(hs_index idx, hs_pot pot, int32_t dtype, int32_t m,
+                                              int64_t *bytes) {
+  if (!idx || !pot || !bytes) return hs::fail(HS_E_INVALID, "hs_magnus4_workspace_bytes: NULL argument");
+  if (dtype != HS_C128 && dtype != HS_C64) return hs::fail(HS_E_INVALID, "hs_magnus4_workspace_bytes: bad dtype");
+  if (m < 0 || m > 32) return hs::fail(HS_E_INVALID, "hs_magnus4_workspace_bytes: m out of range 0..32");
+  if (pot->N != idx->N) return hs::fail(HS_E_INVALID, "hs_magnus4_workspace_bytes: potential and index differ in N");
+  *bytes = m == 0 ? hs::m4_apply_workspace_bytes(idx, pot, dtype) : hs::step4_workspace_bytes(idx, pot, dtype, m);
+  return HS_OK;
+}
+
+extern "C" int32_t hs_apply_magnus4(hs_index idx, const void *idx_dev, hs_pot pot, const void *pot_dev1,
+                                    const void *pot_dev2, int32_t dtype, double h, const void *c, void *y,
+                                    void *ws, void *stream) {
+  if (!idx || !pot || !idx_dev || !pot_dev1 || !pot_dev2 || !c || !y || !ws)
+    return hs::fail(HS_E_INVALID, "hs_apply_magnus4: NULL argument");
+  if (pot->N != idx->N) return hs::fail(HS_E_INVALID, "hs_apply_magnus4: potential and index differ in N");
+  if (dtype != HS_C128 && dtype != HS_C64) return hs::fail(HS_E_INVALID, "hs_apply_magnus4: bad dtype");
+  if (c == y) return hs::fail(HS_E_INVALID, "hs_apply_magnus4: input and output must differ");
+  if (pot_dev1 == pot_dev2) return hs::fail(HS_E_INVALID, "hs_apply_magnus4: the two parameter blocks must differ");
+  if (!std::isfinite(h)) return hs::fail(HS_E_NONFINITE, "hs_apply_magnus4: h not finite");
+  if (!hs::aligned16(c) || !hs::aligned16(y) || !hs::aligned16(ws) || !hs::aligned16(idx_dev) ||
+      !hs::aligned16(pot_dev1) || !hs::aligned16(pot_dev2))
+    return hs::fail(HS_E_INVALID, "hs_apply_magnus4: device pointer not 16-byte aligned");
+  return hs::launch_apply_m4(idx, idx_dev, pot, pot_dev1, pot_dev2, dtype, h, c, y, ws,
+                             static_cast<hipStream_t>(stream));
+}
+
+extern "C" int32_t hs_step_magnus4(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev1,
+                                   void *pot_dev2, int32_t dtype, double t, double *t_dev, double h,
+                                   int32_t m, int32_t reorth, void *c, void *ws, double *diag_dev,
+                                   void *stream) {
+  if (!idx || !pot || !idx_dev || !pot_dev1 || !pot_dev2 || !c || !ws)
+    return hs::fail(HS_E_INVALID, "hs_step_magnus4: NULL argument");
+  if (pot->N != idx->N) return hs::fail(HS_E_INVALID, "hs_step_magnus4: potential and index differ in N");
+  if (dtype != HS_C128 && dtype != HS_C64) return hs::fail(HS_E_INVALID, "hs_step_magnus4: bad dtype");
+  if (m < 1 || m > 32) return hs::fail(HS_E_INVALID, "hs_step_magnus4: m out of range 1..32");
+  if (pot_dev1 == pot_dev2) return hs::fail(HS_E_INVALID, "hs_step_magnus4: the two parameter blocks must differ");
+  if (!std::isfinite(h) || (!t_dev && !std::isfinite(t)))
+    return hs::fail(HS_E_NONFINITE, "hs_step_magnus4: t or h not finite");
+  if (!hs::aligned16(c) || !hs::aligned16(ws) || !hs::aligned16(idx_dev) || !hs::aligned16(pot_dev1) ||
+      !hs::aligned16(pot_dev2))
+    return hs::fail(HS_E_INVALID, "hs_step_magnus4: device pointer not 16-byte aligned");
+  return hs::launch_step_m4(idx, idx_dev, pot, pot_dev1, pot_dev2, dtype, t, t_dev, h, m, reorth, c, ws,
+                            diag_dev, static_cast<hipStream_t>(stream));
 }

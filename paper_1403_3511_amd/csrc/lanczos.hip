@@ -63,6 +63,12 @@ __device__ __forceinline__ void nt_st(double2 *p, double2 v) {
   t[1] = v.y;
   __builtin_nontemporal_store(t, reinterpret_cast<d2v *>(p));
 }
+__device__ __forceinline__ void nt_st(float2 *p, float2 v) {
+  f2v t;
+  t[0] = v.x;
+  t[1] = v.y;
+  __builtin_nontemporal_store(t, reinterpret_cast<f2v *>(p));
+}
 
 // Krylov vectors are stored unnormalised: v_q = s_q V_q with s_0 = 1 (the start vector
 // is normalised when written) and s_q = 1 / beta_{q-1}.
@@ -386,6 +392,35 @@ __global__ void k_advance_time(double *t_dev, double h, const double *__restrict
   }
 }
 
+// ---- two-stage Gauss-Legendre Magnus operator (paper Sec. 2.1, eq. 2stageMagnus) -------
+// With Omega = -i h M, M = (A_1 + A_2)/2 - i g (A_2 A_1 - A_1 A_2), g = sqrt(3) h / 12.
+// Given u1 = A_1 v, u2 = A_2 v, z = A_2 u1 and w = A_1 u2 (w is overwritten):
+//   w <- (u1 + u2)/2 - i g (z - w) - prev_coef * prev_scale * prev.
+// -i g (a + i b) = g b - i g a.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_m4_combine(int64_t n, const typename CT<T>::t *__restrict__ u1, const typename CT<T>::t *__restrict__ u2,
+             const typename CT<T>::t *__restrict__ z, typename CT<T>::t *__restrict__ w, double g,
+             const typename CT<T>::t *__restrict__ prev, const double *__restrict__ prev_coef,
+             const double *__restrict__ prev_scale) {
+  using C = typename CT<T>::t;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const C a = nt_ld(u1 + r), b = nt_ld(u2 + r), zz = nt_ld(z + r), ww = nt_ld(w + r);
+  const T gg = (T)g;
+  const T dre = zz.x - ww.x, dim = zz.y - ww.y;
+  C o;
+  o.x = (T)0.5 * (a.x + b.x) + gg * dim;
+  o.y = (T)0.5 * (a.y + b.y) - gg * dre;
+  if (prev) {
+    const T pc = (T)(*prev_coef * (prev_scale ? *prev_scale : 1.0));
+    const C pv = nt_ld(prev + r);
+    o.x -= pc * pv.x;
+    o.y -= pc * pv.y;
+  }
+  nt_st(w + r, o);
+}
+
 // ---- host side --------------------------------------------------------------------------
 StepLayout step_layout(int64_t rows, int64_t nseg, int n, int64_t elem_bytes, int m,
                        int64_t apply_ws) {
@@ -509,6 +544,85 @@ int32_t launch_step(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *
                         k > 0 ? sc + Scal::inv + (k - 1) : nullptr, vprev,
                         vprev ? sc + Scal::beta + (k - 1) : nullptr,
                         k > 1 ? sc + Scal::inv + (k - 2) : nullptr);
+  };
+  if (dtype == HS_C128) return run_step<double>(J, m, reorth, h, c, ws, t_dev, t_dev, diag, s);
+  return run_step<float>(J, m, reorth, h, c, ws, t_dev, t_dev, diag, s);
+}
+
+// ---- two-stage Gauss-Legendre Magnus scheme (paper Sec. 2.1, eq. 2stageMagnus) ----------
+// Nodes c_{1,2} = 1/2 -+ sqrt(3)/6; the operator M of k_m4_combine is applied with four H
+// applications (A_1 v, A_2 v, A_2 A_1 v, A_1 A_2 v) and one combination pass.  Scratch:
+// three vectors (A_1 v, A_2 v, A_2 A_1 v) in front of the H application's own workspace.
+static const double kGl2c1 = 0.5 - 0.28867513459481288225;  // sqrt(3) / 6
+static const double kGl2c2 = 0.5 + 0.28867513459481288225;
+
+int64_t m4_apply_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32_t dtype) {
+  const int64_t vec = align_up(idx->size * (dtype == HS_C64 ? 8 : 16), 256);
+  return 3 * vec + apply_workspace_bytes(idx, p, dtype);
+}
+
+template <typename T>
+static int32_t m4_apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p,
+                             const void *pot1, const void *pot2, const void *x, void *y, void *ws,
+                             double h, hipStream_t s, const double *in_scale, const void *prev,
+                             const double *prev_coef, const double *prev_scale) {
+  using C = typename CT<T>::t;
+  const int32_t dt = sizeof(T) == 8 ? HS_C128 : HS_C64;
+  const int64_t vec = align_up(idx->size * (int64_t)sizeof(C), 256);
+  uint8_t *w8 = static_cast<uint8_t *>(ws);
+  void *u1 = w8, *u2 = w8 + vec, *z = w8 + 2 * vec, *aws = w8 + 3 * vec;
+  if (idx->size == 0) return HS_OK;
+  int32_t st;
+  if ((st = launch_apply(idx, idx_dev, p, pot1, dt, x, u1, aws, s, in_scale, nullptr, nullptr, nullptr)) != HS_OK)
+    return st;
+  if ((st = launch_apply(idx, idx_dev, p, pot2, dt, x, u2, aws, s, in_scale, nullptr, nullptr, nullptr)) != HS_OK)
+    return st;
+  if ((st = launch_apply(idx, idx_dev, p, pot2, dt, u1, z, aws, s, nullptr, nullptr, nullptr, nullptr)) != HS_OK)
+    return st;
+  if ((st = launch_apply(idx, idx_dev, p, pot1, dt, u2, y, aws, s, nullptr, nullptr, nullptr, nullptr)) != HS_OK)
+    return st;
+  const double g = 1.7320508075688772935 * h / 12.0;
+  hipLaunchKernelGGL(k_m4_combine<T>, dim3((unsigned)((idx->size + 255) / 256)), dim3(256), 0, s, idx->size,
+                     (const C *)u1, (const C *)u2, (const C *)z, (C *)y, g, (const C *)prev, prev_coef,
+                     prev_scale);
+  HS_HIP(hipGetLastError());
+  return HS_OK;
+}
+
+int32_t launch_apply_m4(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p, const void *pot1,
+                        const void *pot2, int32_t dtype, double h, const void *x, void *y, void *ws,
+                        hipStream_t s) {
+  if (dtype == HS_C128)
+    return m4_apply_impl<double>(idx, idx_dev, p, pot1, pot2, x, y, ws, h, s, nullptr, nullptr, nullptr, nullptr);
+  return m4_apply_impl<float>(idx, idx_dev, p, pot1, pot2, x, y, ws, h, s, nullptr, nullptr, nullptr, nullptr);
+}
+
+int64_t step4_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32_t dtype, int m) {
+  const SegView sv = single_segments(idx->size);
+  return step_layout(idx->size, sv.nseg, 1, dtype == HS_C64 ? 8 : 16, m,
+                     m4_apply_workspace_bytes(idx, p, dtype)).total;
+}
+
+int32_t launch_step_m4(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p, void *pot1,
+                       void *pot2, int32_t dtype, double t, double *t_dev, double h, int m, int reorth,
+                       void *c, void *ws, double *diag, hipStream_t s) {
+  StepJob J;
+  J.rows = idx->size;
+  J.sv = single_segments(idx->size);
+  J.apply_ws = m4_apply_workspace_bytes(idx, p, dtype);
+  // both blocks read t before the step advances it
+  J.set_time = [&](hipStream_t st) {
+    const int32_t r = launch_set_time(p, pot1, t, t_dev, kGl2c1 * h, st);
+    return r != HS_OK ? r : launch_set_time(p, pot2, t, t_dev, kGl2c2 * h, st);
+  };
+  J.matvec = [&](const void *vk, void *w, const void *vprev, int k, double *sc, void *aws,
+                 hipStream_t st) {
+    const double *in_scale = k > 0 ? sc + Scal::inv + (k - 1) : nullptr;
+    const double *pc = vprev ? sc + Scal::beta + (k - 1) : nullptr;
+    const double *ps = k > 1 ? sc + Scal::inv + (k - 2) : nullptr;
+    if (dtype == HS_C128)
+      return m4_apply_impl<double>(idx, idx_dev, p, pot1, pot2, vk, w, aws, h, st, in_scale, vprev, pc, ps);
+    return m4_apply_impl<float>(idx, idx_dev, p, pot1, pot2, vk, w, aws, h, st, in_scale, vprev, pc, ps);
   };
   if (dtype == HS_C128) return run_step<double>(J, m, reorth, h, c, ws, t_dev, t_dev, diag, s);
   return run_step<float>(J, m, reorth, h, c, ws, t_dev, t_dev, diag, s);

@@ -50,6 +50,9 @@ _SIGS = {
     "hs_workspace_bytes": [_vp, _vp, _i32, _i32, _pi64],
     "hs_apply_h": [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "hs_step": [_vp, _vp, _vp, _vp, _i32, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
+    "hs_magnus4_workspace_bytes": [_vp, _vp, _i32, _i32, _pi64],
+    "hs_apply_magnus4": [_vp, _vp, _vp, _vp, _vp, _i32, _f64, _vp, _vp, _vp, _vp],
+    "hs_step_magnus4": [_vp, _vp, _vp, _vp, _vp, _i32, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
     "hs_batch_create": [_i32, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp)],
     "hs_batch_destroy": [_vp],
     "hs_batch_offsets": [_vp, _pi64],
@@ -205,18 +208,34 @@ class Pot:
         hs_pot_is_fused(h, C.byref(f))
         self.fused = bool(f.value)
         self.dev = None
+        self.dev2 = None      # second parameter block of the fourth-order step
+        self.device = device
         if upload:
-            nb = C.c_int64()
-            hs_pot_device_bytes(h, C.byref(nb))
-            self.dev = dev_buffer(nb.value, device)
-            hs_pot_upload(h, ptr(self.dev), nb.value, stream_ptr())
+            self.dev = self._new_block()
+
+    def _new_block(self):
+        nb = C.c_int64()
+        hs_pot_device_bytes(self.h, C.byref(nb))
+        dev = dev_buffer(nb.value, self.device)
+        hs_pot_upload(self.h, ptr(dev), nb.value, stream_ptr())
+        return dev
+
+    def blocks2(self):
+        """The two parameter blocks of the two-stage Magnus scheme (the second one is
+        made on first use, a copy of the first)."""
+        if self.dev2 is None:
+            self.dev2 = self.dev.clone()
+        return self.dev, self.dev2
 
     def set_time(self, t: float):
         hs_pot_set_time(self.h, ptr(self.dev), float(t), None, stream_ptr())
 
     def set_coeffs_device(self, coef):
-        """Base coefficients from a device float64 tensor (nterms values, term order)."""
+        """Base coefficients from a device float64 tensor (nterms values, term order);
+        applied to both parameter blocks when the second one exists."""
         hs_pot_set_coeffs_device(self.h, ptr(self.dev), ptr(coef), stream_ptr())
+        if self.dev2 is not None:
+            hs_pot_set_coeffs_device(self.h, ptr(self.dev2), ptr(coef), stream_ptr())
 
     def __del__(self):
         try:
@@ -248,6 +267,35 @@ def step(idx: Index, pot: Pot, c, t: float, h: float, m: int, dtype: int = HS_C1
         ws = workspace(idx, pot, dtype, m, c.device)
     hs_step(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, float(t), ptr(t_dev), float(h), int(m),
             1 if reorth else 0, ptr(c), ptr(ws), ptr(diag), stream_ptr())
+    return c
+
+
+def workspace_magnus4(idx: Index, pot: Pot, dtype: int, m: int, device="cuda"):
+    """Workspace of apply_magnus4 (m = 0) or step_magnus4 (m >= 1)."""
+    nb = C.c_int64()
+    hs_magnus4_workspace_bytes(idx.h, pot.h, dtype, m, C.byref(nb))
+    return dev_buffer(nb.value, device)
+
+
+def apply_magnus4(idx: Index, pot: Pot, h: float, c, y, dtype: int = HS_C128, ws=None):
+    """y = M c, the operator of the two-stage Gauss-Legendre Magnus scheme, with the
+    coefficients currently held in the potential's two parameter blocks."""
+    if ws is None:
+        ws = workspace_magnus4(idx, pot, dtype, 0, c.device)
+    d1, d2 = pot.blocks2()
+    hs_apply_magnus4(idx.h, ptr(idx.dev), pot.h, ptr(d1), ptr(d2), dtype, float(h), ptr(c), ptr(y),
+                     ptr(ws), stream_ptr())
+    return y
+
+
+def step_magnus4(idx: Index, pot: Pot, c, t: float, h: float, m: int, dtype: int = HS_C128,
+                 reorth: bool = True, ws=None, t_dev=None, diag=None):
+    """One fourth-order two-stage Gauss-Legendre Magnus step in place on c."""
+    if ws is None:
+        ws = workspace_magnus4(idx, pot, dtype, m, c.device)
+    d1, d2 = pot.blocks2()
+    hs_step_magnus4(idx.h, ptr(idx.dev), pot.h, ptr(d1), ptr(d2), dtype, float(t), ptr(t_dev),
+                    float(h), int(m), 1 if reorth else 0, ptr(c), ptr(ws), ptr(diag), stream_ptr())
     return c
 
 

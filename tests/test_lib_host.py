@@ -123,6 +123,16 @@ def test_error_paths(hs):
     expect(-1, hs.hs_workspace_bytes, idx.h, pot2.h, 0, 33, C.byref(nb))      # m > 32
     expect(-1, hs.hs_workspace_bytes, idx.h, pot2.h, 5, 10, C.byref(nb))      # dtype
     expect(-1, hs.hs_apply_h, idx.h, None, pot2.h, None, 0, None, None, None, None)  # NULL buffers
+    expect(-1, hs.hs_magnus4_workspace_bytes, idx.h, pot3.h, 0, 4, C.byref(nb))   # N mismatch
+    expect(-1, hs.hs_magnus4_workspace_bytes, idx.h, pot2.h, 0, -1, C.byref(nb))  # m < 0
+    # the two parameter blocks must differ (checked before any device access)
+    fake = (C.c_double * 64)()
+    fp = C.cast(fake, C.c_void_p)
+    expect(-1, hs.hs_step_magnus4, idx.h, fp, pot2.h, fp, fp, 0, 0.0, None, 0.1, 4, 1, fp, fp,
+           None, None)
+    expect(-1, hs.hs_apply_magnus4, idx.h, fp, pot2.h, fp, fp, 0, 0.1, fp, fp, fp, None)
+    expect(-1, hs.hs_step_magnus4, idx.h, fp, pot2.h, None, fp, 0, 0.0, None, 0.1, 4, 1, fp, fp,
+           None, None)                                                           # NULL block
     expect(-1, hs.hs_mlp_create, 7, 100, 210, C.byref(h))                    # hidden not a multiple of 64
     expect(-1, hs.hs_mlp_create, 40, 256, 210, C.byref(h))                   # in > 32
     n = C.c_int32()
@@ -130,6 +140,24 @@ def test_error_paths(hs):
     g = np.zeros(4 * 3 * 5)
     expect(-1, hs.hs_gh_project, 5, 3, 6, 16, g.ctypes.data_as(C.POINTER(C.c_double)), 1, None, None, None)
     assert set(codes) == {-1, -5, -7}
+
+
+def test_magnus4_workspace_sizes(hs):
+    """The fourth-order step needs three vectors beyond the midpoint step's workspace;
+    its operator application alone needs three vectors plus the H workspace."""
+    for N, B, terms in [(3, 300, [(0.1, (2, 1, 0)), (0.2, (0, 0, 3))]),
+                        (2, 100, [(0.1, (4, 0)), (0.2, (1, 1))])]:
+        idx = hs.Index(N, B, upload=False)
+        pot = hs.Pot(N, terms, upload=False)
+        for dt, es in ((hs.HS_C128, 16), (hs.HS_C64, 8)):
+            vec = -(-idx.size * es // 256) * 256
+            a, b, c0, c4 = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+            hs.hs_workspace_bytes(idx.h, pot.h, dt, 7, C.byref(a))
+            hs.hs_magnus4_workspace_bytes(idx.h, pot.h, dt, 7, C.byref(b))
+            hs.hs_workspace_bytes(idx.h, pot.h, dt, 0, C.byref(c0))
+            hs.hs_magnus4_workspace_bytes(idx.h, pot.h, dt, 0, C.byref(c4))
+            assert b.value == a.value + 3 * vec
+            assert c4.value == c0.value + 3 * vec
 
 
 def test_sizes_and_counts(hs):
