@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--tile-dim", type=int, default=0)
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--forms", type=int, default=1, help="also measure the FP32 and batched forms")
+    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4",
+                    help="comma-separated forms measured when --forms is set")
     ap.add_argument("--batch-log2-bmax", type=float, default=10.0)
     ap.add_argument("--n10-steps", type=int, default=20, help="steps of the N=10 FP32/FP64 comparison")
     ap.add_argument("--train-steps", type=int, default=3000, help="Adam steps of the learned form")
@@ -191,10 +193,17 @@ def main():
     forms = None
     if args.forms:
         forms = {"fp64": {"matvec_per_s": round(value, 1), "us_per_matvec": round(us_matvec, 2)}}
-        forms["fp32"] = fp32_form(hs, idx, pot, c0, stream, args)
-        forms["batched"] = batched_form(hs, stream, args)
-        forms["fp32_n10"] = fp32_n10_form(hs, stream, args)
-        forms["learned"] = learned_form(hs, stream, args)
+        want = set(args.form_names.split(","))
+        if "fp32" in want:
+            forms["fp32"] = fp32_form(hs, idx, pot, c0, stream, args)
+        if "batched" in want:
+            forms["batched"] = batched_form(hs, stream, args)
+        if "fp32_n10" in want:
+            forms["fp32_n10"] = fp32_n10_form(hs, stream, args)
+        if "learned" in want:
+            forms["learned"] = learned_form(hs, stream, args)
+        if "magnus4" in want:
+            forms["magnus4"] = magnus4_form(hs, idx, pot, c0, stream, args, value)
 
     cpu = None
     if not args.no_cpu:
@@ -252,6 +261,61 @@ def fp32_form(hs, idx, pot, c0, stream, args, nsteps=20):
     return {"workload": "as the main line, %d steps from the same start" % nsteps,
             "matvec_per_s": round(out["fp32"], 1), "fp64_matvec_per_s_same_run": round(out["fp64"], 1),
             "speedup_vs_fp64": round(out["fp32"] / out["fp64"], 3), "rel_err_vs_fp64": err}
+
+
+def magnus4_form(hs, idx, pot, c0, stream, args, midpoint_matvec_per_s, nsteps=10):
+    """The fourth-order two-stage Gauss-Legendre Magnus step on the main workload: step
+    time (graph replays), one application of its operator M against one H application,
+    and the accuracy of both schemes at h = 0.005 over 8 steps against the fourth-order
+    scheme at h / 4, with m = 10 and m = 16 Lanczos vectors."""
+    import torch
+    dev = "cuda"
+    c = torch.from_numpy(c0).to(dev)
+    ws = hs.workspace_magnus4(idx, pot, hs.HS_C128, M_KRYLOV)
+    t_dev = torch.zeros(1, dtype=torch.float64, device=dev)
+    pot.blocks2()
+
+    def one():
+        hs.step_magnus4(idx, pot, c, 0.0, H_STEP, M_KRYLOV, reorth=True, ws=ws, t_dev=t_dev)
+    one()
+    torch.cuda.synchronize()
+    g = capture(one, stream)
+    g.replay()
+    ms = event_time_ms(g.replay, nsteps, stream) / nsteps
+    del g
+    # M application alone (4 H applications + combination), and the H application
+    x = torch.from_numpy(c0).to(dev)
+    y = torch.empty_like(x)
+    aws = hs.workspace_magnus4(idx, pot, hs.HS_C128, 0)
+    for _ in range(2):
+        hs.apply_magnus4(idx, pot, H_STEP, x, y, hs.HS_C128, aws)
+    us_m = event_time_ms(lambda: hs.apply_magnus4(idx, pot, H_STEP, x, y, hs.HS_C128, aws), 20,
+                         stream) * 1e3 / 20
+    hws = hs.workspace(idx, pot, hs.HS_C128, 0)
+    us_h = event_time_ms(lambda: hs.apply_h(idx, pot, x, y, hs.HS_C128, hws), 20, stream) * 1e3 / 20
+    del x, y, aws, hws, ws
+
+    def run(scheme, h, n, m):
+        cc = torch.from_numpy(c0).to(dev)
+        w = (hs.workspace_magnus4 if scheme == 4 else hs.workspace)(idx, pot, hs.HS_C128, m)
+        t = 0.0
+        for _ in range(n):
+            (hs.step_magnus4 if scheme == 4 else hs.step)(idx, pot, cc, t, h, m, reorth=True, ws=w)
+            t += h
+        torch.cuda.synchronize()
+        return cc
+    err = {}
+    for m in (M_KRYLOV, 16):
+        ref = run(4, H_STEP / 4, 32, m)
+        for sch in (2, 4):
+            d = run(sch, H_STEP, 8, m) - ref
+            err[f"{'midpoint' if sch == 2 else 'magnus4'}_m{m}"] = float(torch.linalg.norm(d) / torch.linalg.norm(ref))
+    return {"workload": "as the main line, fourth-order two-stage Gauss-Legendre Magnus step",
+            "ms_per_step": round(ms, 4), "h_applications_per_s": round(4 * M_KRYLOV / (ms / 1e3), 1),
+            "step_time_vs_midpoint": round(ms / (1e3 * M_KRYLOV / midpoint_matvec_per_s), 3),
+            "us_per_m_application": round(us_m, 2), "us_per_h_application": round(us_h, 2),
+            "m_application_in_h_applications": round(us_m / us_h, 3),
+            "rel_err_8_steps_vs_h_over_4": err}
 
 
 def fp32_n10_form(hs, stream, args):

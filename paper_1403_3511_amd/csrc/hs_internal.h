@@ -157,6 +157,7 @@ struct hs_pot_s {
   bool fused = false;
   bool x2 = false;                    // fused form uses x_l^2 or x_l x_{l+1} monomials
   bool x2_struct = false;             // ... for some choice of the coefficients
+  bool dyn_linear = false;            // time-dependent terms reach only x_l^1 and constant slots
   // fused: compiled monomial coefficient of each HH slot = sum_t M[slot][t] beta_t
   int32_t nslots = 0;
   std::vector<double> M;              // nslots x nterms

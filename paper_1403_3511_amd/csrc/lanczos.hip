@@ -550,9 +550,10 @@ int32_t launch_step(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *
 }
 
 // ---- two-stage Gauss-Legendre Magnus scheme (paper Sec. 2.1, eq. 2stageMagnus) ----------
-// Nodes c_{1,2} = 1/2 -+ sqrt(3)/6; the operator M of k_m4_combine is applied with four H
-// applications (A_1 v, A_2 v, A_2 A_1 v, A_1 A_2 v) and one combination pass.  Scratch:
-// three vectors (A_1 v, A_2 v, A_2 A_1 v) in front of the H application's own workspace.
+// Nodes c_{1,2} = 1/2 -+ sqrt(3)/6.  Potentials of the fused class take the two fused
+// passes of matvec_m4.h; the others (and sets without a specialised kernel) apply M with
+// four H applications (A_1 v, A_2 v, A_2 A_1 v, A_1 A_2 v) and one combination pass.
+// Scratch: three vectors in front of the H application's own workspace.
 static const double kGl2c1 = 0.5 - 0.28867513459481288225;  // sqrt(3) / 6
 static const double kGl2c2 = 0.5 + 0.28867513459481288225;
 
@@ -560,6 +561,15 @@ int64_t m4_apply_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32
   const int64_t vec = align_up(idx->size * (dtype == HS_C64 ? 8 : 16), 256);
   return 3 * vec + apply_workspace_bytes(idx, p, dtype);
 }
+
+bool launch_m4_f64(const IndexDev &ix, const double *hh1, const double *hh2, const void *v, void *a,
+                   void *d, void *w, const double *in_scale, double g2, const void *prev,
+                   const double *prev_coef, const double *prev_scale, hipStream_t s, bool x2,
+                   bool dl);
+bool launch_m4_f32(const IndexDev &ix, const double *hh1, const double *hh2, const void *v, void *a,
+                   void *d, void *w, const double *in_scale, double g2, const void *prev,
+                   const double *prev_coef, const double *prev_scale, hipStream_t s, bool x2,
+                   bool dl);
 
 template <typename T>
 static int32_t m4_apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p,
@@ -572,6 +582,22 @@ static int32_t m4_apply_impl(const hs_index_s *idx, const void *idx_dev, const h
   uint8_t *w8 = static_cast<uint8_t *>(ws);
   void *u1 = w8, *u2 = w8 + vec, *z = w8 + 2 * vec, *aws = w8 + 3 * vec;
   if (idx->size == 0) return HS_OK;
+  if (p->fused) {
+    // two fused passes: (Abar v, Delta v), then the commutator and combination
+    const IndexDev ix = idx->view(idx_dev);
+    const double *hh1 = (const double *)((const uint8_t *)pot1 + p->off_hh);
+    const double *hh2 = (const double *)((const uint8_t *)pot2 + p->off_hh);
+    const double g2 = 2.0 * 1.7320508075688772935 * h / 12.0;
+    const bool done = sizeof(T) == 8
+        ? launch_m4_f64(ix, hh1, hh2, x, u1, u2, y, in_scale, g2, prev, prev_coef, prev_scale, s, p->x2, p->dyn_linear)
+        : launch_m4_f32(ix, hh1, hh2, x, u1, u2, y, in_scale, g2, prev, prev_coef, prev_scale, s, p->x2,
+                        p->dyn_linear);
+    if (done) {
+      HS_HIP(hipGetLastError());
+      return HS_OK;
+    }
+  }
+  // four H applications and one combination pass
   int32_t st;
   if ((st = launch_apply(idx, idx_dev, p, pot1, dt, x, u1, aws, s, in_scale, nullptr, nullptr, nullptr)) != HS_OK)
     return st;

@@ -109,6 +109,14 @@ bool try_fused(hs_pot_s *P) {
       if (any) P->x2_struct = true;
       if (dyn || val != 0.0) P->x2 = true;
     }
+  // the time-dependent terms reach only the linear and constant slots (a laser-type
+  // drive): the difference of two coefficient sets is then linear in the coordinates
+  P->dyn_linear = true;
+  for (int slot = 0; slot < P->nslots; ++slot) {
+    if (slot == slot_c(N) || slot % 5 == 0) continue;  // x_l^1 and the constant
+    for (int t = 0; t < P->nterms; ++t)
+      if (P->amp[t] != 0.0 && P->M[(size_t)slot * P->nterms + t] != 0.0) P->dyn_linear = false;
+  }
   return true;
 }
 

@@ -46,19 +46,37 @@ def _from_lib(t, lexpos):
     return out
 
 
-@pytest.mark.parametrize("N,B", [(2, 700), (3, 300), (5, 64)])
-def test_apply_m_fused(hs, N, B):
-    """y = M c for the chained Henon-Heiles potential with the laser term: several
-    tiles and a ragged tail; h = 0.5 so the commutator carries weight."""
-    import torch
+def _drive_terms(N, kind):
+    """Fused-class potentials: 'laser' (time-dependent linear terms only, harmonic part
+    subtracted), 'cubic' (the cubic coupling itself oscillates), 'x2' (laser, harmonic
+    part kept, so x_l^2 coefficients are present)."""
     tt = hh_workload(N, 0.111, 0.05)
+    if kind == "cubic":
+        from synth import TimeTerm
+        tt = [TimeTerm(x[0], x.degrees, amp=0.04, freq=1.3, phase=0.2) if sum(x.degrees) == 3 else x
+              for x in tt]
+    return tt, kind != "x2"
+
+
+def _oracle_pot(N, tt, t, harmonic):
+    V = Potential(N, "mono", 1.0, [(x.coef(t), x.degrees) for x in tt])
+    return oracle_W(N, tt, t) if harmonic else V
+
+
+@pytest.mark.parametrize("N,B,kind", [(2, 700, "laser"), (3, 300, "laser"), (5, 64, "laser"),
+                                      (3, 300, "cubic"), (4, 150, "x2"), (6, 300, "cubic")])
+def test_apply_m_fused(hs, N, B, kind):
+    """y = M c for fused-class potentials (the two fused passes): several tiles and a
+    ragged tail; h = 0.5 so the commutator carries weight."""
+    import torch
+    tt, harmonic = _drive_terms(N, kind)
     t, h = 0.4, 0.5
     ix = IndexSet(N, B)
     c = complex_normal_by_index(ix.k, 20 + N)
-    W1, W2 = oracle_W(N, tt, t + C1 * h), oracle_W(N, tt, t + C2 * h)
+    W1, W2 = _oracle_pot(N, tt, t + C1 * h, harmonic), _oracle_pot(N, tt, t + C2 * h, harmonic)
     y_ref = magnus4_operator(lambda v: fast_apply_H(ix, W1, v), lambda v: fast_apply_H(ix, W2, v), h)(c)
     idx = hs.Index(N, B)
-    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=harmonic)
     assert pot.fused
     _set_blocks(hs, pot, t + C1 * h, t + C2 * h)
     cl, lexpos = _to_lib(idx, N, B, c)
