@@ -133,7 +133,7 @@ def fast_apply_W(idx, pot: Potential, v: np.ndarray, axis_order: str = "eq") -> 
 
     Each term restarts from the input vector.  axis_order 'eq' applies axis N first and
     axis 1 last, as the nested product of eq. Horner is written; 'rev' applies axis 1
-    first (only used to check the adjoint identity)."""
+    first (the adjoint identity, and the symmetrised operator sym_apply_H)."""
     v = np.asarray(v, dtype=np.complex128)
     res = np.zeros_like(v)
     axes = range(pot.N - 1, -1, -1) if axis_order == "eq" else range(pot.N)
@@ -156,6 +156,19 @@ def fast_apply_H(idx, pot: Potential, v: np.ndarray, axis_order: str = "eq") -> 
     """(D + W^pol(X_K)) v, the action used in each Lanczos step (Fig. 4, step (2))."""
     v = np.asarray(v, dtype=np.complex128)
     return diag_D(idx) * v + fast_apply_W(idx, pot, v, axis_order)
+
+
+def sym_apply_H(idx, pot: Potential, v: np.ndarray) -> np.ndarray:
+    """(D + (F + F_rev)/2) v: the Hermitian part of the fast operator.
+
+    On a reduced set the truncated coordinate matrices do not commute, so the order of
+    the factors in eq. Horner matters there (Sec. 4.2, discussion after Lemma 1; on the
+    full set it does not).  Each X^(l)_K is real symmetric, so the transpose of a term
+    p(X^(1))...p(X^(N)) (axis N applied first) is the same product applied in the reverse
+    order: F^T = F_rev, and (F + F_rev)/2 is the symmetric part of F.  It agrees with F
+    on every term that touches a single axis, and on a full box."""
+    v = np.asarray(v, dtype=np.complex128)
+    return diag_D(idx) * v + 0.5 * (fast_apply_W(idx, pot, v, "eq") + fast_apply_W(idx, pot, v, "rev"))
 
 
 # ----------------------------------------------------------------------------------
