@@ -184,7 +184,7 @@ def main():
     alg_bytes = 32.0 * idx.size
     achieved = alg_bytes / (us_matvec * 1e-6) / 1e9
     np_axes = N_DIM - idx.tile_dim
-    kernel = f"hs::k_hh_long<double, {N_DIM}, {np_axes}, false>" if pot.fused else "hs::k_pass<double>"
+    kernel = f"hs::k_hh_long<double, {N_DIM}, {np_axes}, false, false>" if pot.fused else "hs::k_pass<double>"
     traffic = recorded_traffic(kernel)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -55,6 +55,9 @@ extern "C" {
 
 #define HS_NMAX 16
 
+#define HS_FORM_PAPER 0 /* the fast operator F: factors applied axis N first (eq. Horner)   */
+#define HS_FORM_SYM 1   /* its symmetric part D + (F + F_rev)/2 (see hs_pot_set_form)     */
+
 typedef struct hs_index_s *hs_index;
 typedef struct hs_pot_s *hs_pot;
 typedef struct hs_batch_s *hs_batch;
@@ -107,6 +110,17 @@ int32_t hs_pot_upload(hs_pot pot, void *dev, int64_t bytes, void *stream);
  * writing them into the device parameter block; graph-capturable (t is read from the
  * device scalar t_dev when t_dev != NULL, else the host value t is used).           */
 int32_t hs_pot_set_time(hs_pot pot, void *pot_dev, double t, const double *t_dev, void *stream);
+/* Operator form used by every later call with this potential.  HS_FORM_PAPER (the
+ * default) is the fast operator F of the paper, factors applied axis N first.  On a
+ * reduced set the truncated coordinate matrices do not commute (paper Sec. 4.2, after
+ * Lemma 1), so F is not symmetric there; each X_K is symmetric, so F^T = F_rev (the
+ * reversed factor order) and HS_FORM_SYM = D + (F + F_rev)/2 is the symmetric part of
+ * the same discretisation.  HS_FORM_SYM is served for potentials of the fused class on
+ * index sets with a specialised kernel that lists every row (else the H application
+ * returns HS_E_UNSUPPORTED); batches accept HS_FORM_PAPER only.  A host-side setting:
+ * no device block changes.  Returns HS_E_UNSUPPORTED for a potential outside the fused
+ * class, HS_E_INVALID for an unknown form.                                            */
+int32_t hs_pot_set_form(hs_pot pot, int32_t form);
 /* Replace the time-dependent base coefficients by values already on the device
  * (nterms doubles, e.g. written by the surrogate or the quadrature kernels).          */
 int32_t hs_pot_set_coeffs_device(hs_pot pot, void *pot_dev, const double *coef_dev, void *stream);

@@ -97,6 +97,15 @@ extern "C" int32_t hs_pot_set_time(hs_pot pot, void *pot_dev, double t, const do
   return hs::launch_set_time(pot, pot_dev, t, t_dev, 0.0, static_cast<hipStream_t>(stream));
 }
 
+extern "C" int32_t hs_pot_set_form(hs_pot pot, int32_t form) {
+  if (!pot) return hs::fail(HS_E_INVALID, "hs_pot_set_form: NULL handle");
+  if (form != HS_FORM_PAPER && form != HS_FORM_SYM) return hs::fail(HS_E_INVALID, "hs_pot_set_form: unknown form");
+  if (form == HS_FORM_SYM && !pot->fused)
+    return hs::fail(HS_E_UNSUPPORTED, "hs_pot_set_form: the symmetrised form needs a potential of the fused class");
+  pot->form = form;
+  return HS_OK;
+}
+
 extern "C" int32_t hs_pot_set_coeffs_device(hs_pot pot, void *pot_dev, const double *coef_dev,
                                             void *stream) {
   if (!pot || !pot_dev || !coef_dev) return hs::fail(HS_E_INVALID, "hs_pot_set_coeffs_device: NULL argument");

@@ -34,9 +34,9 @@ __device__ __forceinline__ void batch_row(const BatchInst &B, const typename V2<
                                           typename V2<T>::t *y, const int32_t *rec, int32_t o,
                                           const typename V2<T>::t *prev, T oscale, T pcoef) {
   if (B.x2)
-    hh_row<T, N, NP, true>(B.ix, B.hh, x + B.off, y + B.off, rec, o, oscale, prev ? prev + B.off : nullptr, pcoef);
+    hh_row<T, N, NP, true, false>(B.ix, B.hh, x + B.off, y + B.off, rec, o, oscale, prev ? prev + B.off : nullptr, pcoef);
   else
-    hh_row<T, N, NP, false>(B.ix, B.hh, x + B.off, y + B.off, rec, o, oscale, prev ? prev + B.off : nullptr, pcoef);
+    hh_row<T, N, NP, false, false>(B.ix, B.hh, x + B.off, y + B.off, rec, o, oscale, prev ? prev + B.off : nullptr, pcoef);
 }
 
 // y = H x, or inside a Lanczos step (scall != nullptr, km1 = k - 1 >= 0) with the stored
@@ -196,6 +196,10 @@ extern "C" int32_t hs_batch_create(int32_t n, const hs_index *idx, const void *c
       if (idx[i]->size > (int64_t)(INT32_MAX / 16)) {  // 32-bit buffer offsets of the row kernel
         delete b;
         return hs::fail(HS_E_UNSUPPORTED, "hs_batch_create: an instance has 2^27 or more rows");
+      }
+      if (pot[i]->form != HS_FORM_PAPER) {
+        delete b;
+        return hs::fail(HS_E_UNSUPPORTED, "hs_batch_create: batches serve the paper's operator form only");
       }
       if (!pot[i]->fused || !idx[i]->recs_all || !batch_supported(idx[i]->N, idx[i]->np)) {
         delete b;

@@ -158,6 +158,7 @@ struct hs_pot_s {
   bool x2 = false;                    // fused form uses x_l^2 or x_l x_{l+1} monomials
   bool x2_struct = false;             // ... for some choice of the coefficients
   bool dyn_linear = false;            // time-dependent terms reach only x_l^1 and constant slots
+  int32_t form = HS_FORM_PAPER;       // operator form (hs_pot_set_form)
   // fused: compiled monomial coefficient of each HH slot = sum_t M[slot][t] beta_t
   int32_t nslots = 0;
   std::vector<double> M;              // nslots x nterms

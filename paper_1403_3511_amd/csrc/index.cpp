@@ -335,8 +335,15 @@ static int32_t build_index(hs_index_s *ix) {
       for (int l = 0; l + 1 < np; ++l)
         for (int s = -2; s <= 2; ++s)
           for (int r : {-1, 1}) {
+            // p + s e_l + r e_{l+1} may exist when p + s e_l does not (r = -1): then walk
+            // along l + 1 first (the symmetrised operator reads such tiles)
             int64_t tt = walk(t, l, s);
-            put(hs::rec_pair(np, l, s, r), tt >= 0 ? walk(tt, l + 1, r) : -1);
+            int64_t u = tt >= 0 ? walk(tt, l + 1, r) : -1;
+            if (u < 0) {
+              const int64_t t2 = walk(t, l + 1, r);
+              u = t2 >= 0 ? walk(t2, l, s) : -1;
+            }
+            put(hs::rec_pair(np, l, s, r), u);
           }
       if (len >= hs::kLongTile)
         for (int32_t o = 0; o < len; o += hs::kChunk) {

@@ -582,7 +582,7 @@ static int32_t m4_apply_impl(const hs_index_s *idx, const void *idx_dev, const h
   uint8_t *w8 = static_cast<uint8_t *>(ws);
   void *u1 = w8, *u2 = w8 + vec, *z = w8 + 2 * vec, *aws = w8 + 3 * vec;
   if (idx->size == 0) return HS_OK;
-  if (p->fused) {
+  if (p->fused && p->form == HS_FORM_PAPER) {
     // two fused passes: (Abar v, Delta v), then the commutator and combination
     const IndexDev ix = idx->view(idx_dev);
     const double *hh1 = (const double *)((const uint8_t *)pot1 + p->off_hh);

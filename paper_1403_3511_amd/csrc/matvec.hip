@@ -25,6 +25,13 @@ int launch_hh_long_f64(const IndexDev &ix, const double *hh, const void *x, void
 int launch_hh_long_f32(const IndexDev &ix, const double *hh, const void *x, void *y,
                        const double *out_scale, const void *prev, const double *prev_coef,
                        const double *prev_scale, hipStream_t s, bool x2);
+// the same for the symmetrised operator D + (F + F_rev)/2
+int launch_hh_long_sym_f64(const IndexDev &ix, const double *hh, const void *x, void *y,
+                           const double *out_scale, const void *prev, const double *prev_coef,
+                           const double *prev_scale, hipStream_t s, bool x2);
+int launch_hh_long_sym_f32(const IndexDev &ix, const double *hh, const void *x, void *y,
+                           const double *out_scale, const void *prev, const double *prev_coef,
+                           const double *prev_scale, hipStream_t s, bool x2);
 
 struct Pos {
   int32_t t, o;
@@ -508,6 +515,16 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
   const double *beta = (const double *)(pb + p->off_beta);
   const unsigned g = nblk(idx->size, 256);
   if (idx->size == 0) return HS_OK;
+  if (p->fused && p->form == HS_FORM_SYM) {
+    // the symmetrised operator exists only as the specialised kernel serving every row
+    const int done = sizeof(T) == 8
+        ? launch_hh_long_sym_f64(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, p->x2)
+        : launch_hh_long_sym_f32(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, p->x2);
+    if (done != 1)
+      return fail(HS_E_UNSUPPORTED, "symmetrised form: no specialised kernel for this index set");
+    HS_HIP(hipGetLastError());
+    return HS_OK;
+  }
   if (p->fused) {
     const int done = sizeof(T) == 8
         ? launch_hh_long_f64(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, p->x2)

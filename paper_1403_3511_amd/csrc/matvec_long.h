@@ -11,6 +11,12 @@
 //
 // X2 = false drops the x_l^2 and x_l x_{l+1} monomials (absent in the Henon-Heiles
 // class) at compile time.
+//
+// SYM = true evaluates the symmetrised operator D + (F + F_rev)/2: the coupling terms
+// x_l^a x_{l+1} (a = 1, 2) are averaged over both factor orders.  The reversed order,
+// X_{l+1} (X_l^a c), needs c at the same cross positions j + s e_l + r e_{l+1} as the
+// paper's order; only which of them count differs (the intermediate j + r e_{l+1} must
+// lie in K instead of j + s e_l), and that is decided from the product prod(1 + j_i).
 #pragma once
 
 #include "dev_common.h"
@@ -68,7 +74,7 @@ template <> struct WinLoad<float> {
 //   h1_s = e_s h2_{s-1} + e_{s+1} h2_{s+1} + a1 u_s + g1 v_s          (s = -1, 1)
 //   G_l  = e_0 h1_{-1} + e_1 h1_1.
 // One row (offset o of the tile whose record is rec) of y = oscale (D + W) x - pcoef prev.
-template <typename T, int N, int NP, bool X2>
+template <typename T, int N, int NP, bool X2, bool SYM>
 __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restrict__ hh,
                                        const typename V2<T>::t *__restrict__ x,
                                        typename V2<T>::t *__restrict__ y,
@@ -99,6 +105,12 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
   }
   const uint32_t self = base + (uint32_t)o;
   const C c0 = x[self];
+  // prod(1 + j_i), exact in double (membership tests of the reversed factor order)
+  double pj = 1.0;
+  if constexpr (SYM) {
+    static_for<0, NP>([&](auto I) { pj *= (double)(1 + rec[4 + decltype(I)::value]); });
+    static_for<0, D>([&](auto A) { pj *= (double)(1 + sc[decltype(A)::value]); });
+  }
   // the previous Lanczos vector is needed only at the end: issue its load now so that
   // its latency overlaps the stencil work
   C pv = vz<T>();
@@ -118,8 +130,9 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
     constexpr bool inner = (l + 1 < N);
     const T a1 = (T)hh[5 * l + 0], a3 = (T)hh[5 * l + 2];
     const T a2 = X2 ? (T)hh[5 * l + 1] : T(0);
-    const T g1 = (X2 && inner) ? (T)hh[5 * l + 3] : T(0);
-    const T g2 = inner ? (T)hh[5 * l + 4] : T(0);
+    // symmetrised: each factor order carries half of the coupling coefficient
+    const T g1 = (X2 && inner) ? (T)(SYM ? 0.5 * hh[5 * l + 3] : hh[5 * l + 3]) : T(0);
+    const T g2 = inner ? (T)(SYM ? 0.5 * hh[5 * l + 4] : hh[5 * l + 4]) : T(0);
     const bool any2 = (a3 != T(0)) || (a2 != T(0)) || (g2 != T(0));
     const bool need3 = (a3 != T(0));
     const bool in_car = have_car;
@@ -235,6 +248,12 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
           o_lo = pr.x;
           o_hi = pr.y;
         }
+        // symmetrised form: c at j + s e_l -+ e_{l+1}, whether or not j + s e_l is in K
+        C xs_lo[5], xs_hi[5];
+        if constexpr (SYM) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) xs_lo[q] = xs_hi[q] = vz<T>();
+        }
 #pragma unroll
         for (int s = -2; s <= 2; ++s) {
           if (!X2 && (s & 1)) continue;
@@ -245,26 +264,39 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
             // (X_{l+1} c)(j) from the carried neighbours
             fma_rc<T>(vs, wlo * gs, in_lo);
             fma_rc<T>(vs, whi * gs, in_hi);
+            if constexpr (SYM) {
+              xs_lo[2] = in_lo;
+              xs_hi[2] = in_hi;
+            }
           } else {
             int2 cr = make_int2(-1, -1);  // cross displacements (r = -1, +1) on suffix axes
             if constexpr (m > NP) {
               constexpr int a = l - NP;
               cr = (s == 0) ? gst2[gst_axis_pair(a + 1, 1) * ng + o] : gst2[gst_cross_pair(D, a, s) * ng + o];
             }
+            const bool vs_ok = SYM ? true : val[3 + s];
 #pragma unroll
             for (int r = -1; r <= 1; r += 2) {
               uint32_t vid;
               if constexpr (m < NP) {
                 const int p = rec_pair(NP, l, s, r);
-                vid = (val[3 + s] && o < rec[p + 1]) ? (uint32_t)(rec[p] + o) : kAbsent;
+                vid = (vs_ok && o < rec[p + 1]) ? (uint32_t)(rec[p] + o) : kAbsent;
               } else if constexpr (m == NP) {
                 const int32_t oq = r < 0 ? o_lo : o_hi;
-                vid = (val[3 + s] && (uint32_t)oq < (uint32_t)lnw[3 + s]) ? (uint32_t)(stw[3 + s] + oq) : kAbsent;
+                vid = (vs_ok && (uint32_t)oq < (uint32_t)lnw[3 + s]) ? (uint32_t)(stw[3 + s] + oq) : kAbsent;
               } else {
                 const int32_t oq = r < 0 ? cr.x : cr.y;
-                vid = (val[3 + s] && (uint32_t)oq < (uint32_t)len) ? base + (uint32_t)oq : kAbsent;
+                vid = (vs_ok && (uint32_t)oq < (uint32_t)len) ? base + (uint32_t)oq : kAbsent;
               }
-              fma_rc<T>(vs, (r < 0 ? wlo : whi) * gs, BufLoad<T>::ld(xr, vid));
+              const C xv = BufLoad<T>::ld(xr, vid);
+              if constexpr (SYM) {
+                if (r < 0) xs_lo[s + 2] = xv; else xs_hi[s + 2] = xv;
+              }
+              fma_rc<T>(vs, (r < 0 ? wlo : whi) * gs, xv);
+            }
+            // the paper's order counts (X_{l+1} c)(j + s e_l) only for j + s e_l in K
+            if constexpr (SYM) {
+              if (!val[3 + s]) vs = vz<T>();
             }
           }
           if (s & 1) v1[(s + 1) / 2] = vs;
@@ -272,6 +304,45 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
             h2[(s + 2) / 2].x += vs.x;
             h2[(s + 2) / 2].y += vs.y;
           }
+        }
+        // reversed order: X_{l+1} applied last, to (X_l^a c) at j -+ e_{l+1}.  The lower
+        // intermediate lies in K when j_{l+1} >= 1 (its weight wlo is 0 otherwise), the
+        // upper one when prod(1 + j_i) (2 + j_{l+1}) / (1 + j_{l+1}) <= B.  The
+        // diagonal of X_l^2 at j' counts j' + e_l only when that lies in K.
+        if constexpr (SYM) {
+          int jm;
+          if constexpr (m < NP) jm = rec[4 + m]; else jm = sc[m - NP];
+          const double bm = (double)ix.B * (double)(1 + jm), bl = (double)(1 + jl);
+          const bool up_in = pj * (double)(2 + jm) <= bm;
+          const T wup = up_in ? whi : T(0);
+          C rev = vz<T>();
+          if (g2 != T(0)) {
+            const bool lo_l = jm >= 1 && pj * (double)jm * (double)(2 + jl) <= bm * bl;
+            const bool hi_l = up_in && pj * (double)(2 + jm) * (double)(2 + jl) <= bm * bl;
+            const T dm = raw[2] * raw[1], dp = raw[3] * raw[4], d0 = raw[2] * raw[2], d1 = raw[3] * raw[3];
+            C rl = vz<T>(), rh = vz<T>();
+            fma_rc<T>(rl, dm, xs_lo[0]);
+            fma_rc<T>(rl, lo_l ? d0 + d1 : d0, xs_lo[2]);
+            fma_rc<T>(rl, dp, xs_lo[4]);
+            fma_rc<T>(rh, dm, xs_hi[0]);
+            fma_rc<T>(rh, hi_l ? d0 + d1 : d0, xs_hi[2]);
+            fma_rc<T>(rh, dp, xs_hi[4]);
+            fma_rc<T>(rev, wlo * g2, rl);
+            fma_rc<T>(rev, wup * g2, rh);
+          }
+          if constexpr (X2) {
+            if (g1 != T(0)) {
+              C rl = vz<T>(), rh = vz<T>();
+              fma_rc<T>(rl, raw[2], xs_lo[1]);
+              fma_rc<T>(rl, raw[3], xs_lo[3]);
+              fma_rc<T>(rh, raw[2], xs_hi[1]);
+              fma_rc<T>(rh, raw[3], xs_hi[3]);
+              fma_rc<T>(rev, wlo * g1, rl);
+              fma_rc<T>(rev, wup * g1, rh);
+            }
+          }
+          acc.x += rev.x;
+          acc.y += rev.y;
         }
       }
     }
@@ -309,7 +380,7 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
 // contiguous share of the long-tile chunks (tiles and their neighbours then share one
 // L2), followed by a contiguous share of the packed short-tile rows, so every XCD gets
 // the same mix of the two.
-template <typename T, int N, int NP, bool X2>
+template <typename T, int N, int NP, bool X2, bool SYM = false>
 __global__ void __launch_bounds__(256)
 k_hh_long(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *__restrict__ x,
           typename V2<T>::t *__restrict__ y, const double *__restrict__ out_scale,
@@ -328,14 +399,14 @@ k_hh_long(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *_
     const int32_t *__restrict__ rec = ix.recs + (int64_t)ri * RS;
     const int32_t o = o0 + (int32_t)(threadIdx.x & 63);
     if (o >= rec[1]) return;
-    hh_row<T, N, NP, X2>(ix, hh, x, y, rec, o, oscale, prev, pcoef);
+    hh_row<T, N, NP, X2, SYM>(ix, hh, x, y, rec, o, oscale, prev, pcoef);
   } else {
     const int64_t blk = (int64_t)xcd * small_per_xcd + (j - long_per_xcd);
     const int64_t i = blk * blockDim.x + threadIdx.x;
     if (i >= ix.nsmall) return;
     const int32_t r = ix.small_rows[i];
     const int32_t *__restrict__ rec = ix.recs + (int64_t)ix.tile_rec[ix.rowtile[r]] * RS;
-    hh_row<T, N, NP, X2>(ix, hh, x, y, rec, r - rec[0], oscale, prev, pcoef);
+    hh_row<T, N, NP, X2, SYM>(ix, hh, x, y, rec, r - rec[0], oscale, prev, pcoef);
   }
 }
 
@@ -349,7 +420,7 @@ inline void long_grid(const IndexDev &ix, bool with_small, int32_t &long_per, in
   blocks = (unsigned)((int64_t)(long_per + small_per) * kXcd);
 }
 
-template <typename T, int N, int NP, bool X2>
+template <typename T, int N, int NP, bool X2, bool SYM>
 static void launch_long_pair(const IndexDev &ix, const double *hh, const void *x, void *y,
                              const double *out_scale, const void *prev, const double *prev_coef,
                              const double *prev_scale, hipStream_t s, bool with_small) {
@@ -358,13 +429,13 @@ static void launch_long_pair(const IndexDev &ix, const double *hh, const void *x
   unsigned blocks;
   long_grid(ix, with_small, lp, sp, blocks);
   if (blocks == 0) return;
-  hipLaunchKernelGGL((k_hh_long<T, N, NP, X2>), dim3(blocks), dim3(256), 0, s, ix, hh, (const C *)x,
+  hipLaunchKernelGGL((k_hh_long<T, N, NP, X2, SYM>), dim3(blocks), dim3(256), 0, s, ix, hh, (const C *)x,
                      (C *)y, out_scale, (const C *)prev, prev_coef, prev_scale, lp, sp);
 }
 
 // Returns 1 if long and short tiles were both launched, 2 if only the long tiles (the
 // caller handles the short ones), 0 if (N, NP) has no specialisation.
-template <typename T>
+template <typename T, bool SYM = false>
 int launch_hh_long_impl(const IndexDev &ix, const double *hh, const void *x, void *y,
                         const double *out_scale, const void *prev, const double *prev_coef,
                         const double *prev_scale, hipStream_t s, bool x2) {
@@ -376,9 +447,9 @@ int launch_hh_long_impl(const IndexDev &ix, const double *hh, const void *x, voi
 #define HS_LONG_CASE(NN, PP)                                                                    \
   case NN * 32 + PP:                                                                            \
     if (x2)                                                                                     \
-      launch_long_pair<T, NN, PP, true>(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, small);  \
+      launch_long_pair<T, NN, PP, true, SYM>(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, small);  \
     else                                                                                        \
-      launch_long_pair<T, NN, PP, false>(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, small); \
+      launch_long_pair<T, NN, PP, false, SYM>(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, small); \
     return small ? 1 : 2;
   switch (ix.N * 32 + ix.np) {
     HS_LONG_CASE(1, 0)

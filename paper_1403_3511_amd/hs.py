@@ -24,6 +24,7 @@ _lib = C.CDLL(LIB_PATH)
 HS_OK, HS_INFO_BREAKDOWN = 0, 1
 HS_C128, HS_C64 = 0, 1
 HS_BASIS_MONO, HS_BASIS_CHEB, HS_BASIS_HERM = 0, 1, 2
+HS_FORM_PAPER, HS_FORM_SYM = 0, 1
 BASIS = {"mono": HS_BASIS_MONO, "cheb": HS_BASIS_CHEB, "herm": HS_BASIS_HERM}
 
 _vp, _i32, _i64, _f64, _f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_float
@@ -47,6 +48,7 @@ _SIGS = {
     "hs_pot_upload": [_vp, _vp, _i64, _vp],
     "hs_pot_set_time": [_vp, _vp, _f64, _vp, _vp],
     "hs_pot_set_coeffs_device": [_vp, _vp, _vp, _vp],
+    "hs_pot_set_form": [_vp, _i32],
     "hs_workspace_bytes": [_vp, _vp, _i32, _i32, _pi64],
     "hs_apply_h": [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "hs_step": [_vp, _vp, _vp, _vp, _i32, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
@@ -229,6 +231,10 @@ class Pot:
 
     def set_time(self, t: float):
         hs_pot_set_time(self.h, ptr(self.dev), float(t), None, stream_ptr())
+
+    def set_form(self, form: int):
+        """HS_FORM_PAPER (the fast operator) or HS_FORM_SYM (its symmetric part)."""
+        hs_pot_set_form(self.h, int(form))
 
     def set_coeffs_device(self, coef):
         """Base coefficients from a device float64 tensor (nterms values, term order);

@@ -123,6 +123,11 @@ def test_error_paths(hs):
     expect(-1, hs.hs_workspace_bytes, idx.h, pot2.h, 0, 33, C.byref(nb))      # m > 32
     expect(-1, hs.hs_workspace_bytes, idx.h, pot2.h, 5, 10, C.byref(nb))      # dtype
     expect(-1, hs.hs_apply_h, idx.h, None, pot2.h, None, 0, None, None, None, None)  # NULL buffers
+    expect(-1, hs.hs_pot_set_form, pot2.h, 7)                                 # unknown form
+    gen = hs.Pot(2, [(1.0, (4, 0))], upload=False)                            # outside the fused class
+    assert not gen.fused
+    expect(-5, hs.hs_pot_set_form, gen.h, hs.HS_FORM_SYM)
+    hs.hs_pot_set_form(gen.h, hs.HS_FORM_PAPER)
     expect(-1, hs.hs_magnus4_workspace_bytes, idx.h, pot3.h, 0, 4, C.byref(nb))   # N mismatch
     expect(-1, hs.hs_magnus4_workspace_bytes, idx.h, pot2.h, 0, -1, C.byref(nb))  # m < 0
     # the two parameter blocks must differ (checked before any device access)
