@@ -20,7 +20,8 @@ Also measured inside this run:
                    workload with its error against the float64 run, the batched form
                    (256 instances, one persistent launch per H application) against the
                    same instances stepped one by one, the N = 10 FP32 form, the learned
-                   coefficient path, and the fourth-order two-stage Magnus step.
+                   coefficient path, the fourth-order two-stage Magnus step, and the
+                   symmetrised operator.
   cpu_baseline  -- the CPU oracle's fast algorithm on the same workload (rank 0 only).
 
 --calibrate-copy MIB runs only a device-to-device copy of that size (the reference
@@ -117,7 +118,7 @@ def main():
     ap.add_argument("--tile-dim", type=int, default=0)
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--forms", type=int, default=1, help="also measure the FP32 and batched forms")
-    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4",
+    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4,sym",
                     help="comma-separated forms measured when --forms is set")
     ap.add_argument("--batch-log2-bmax", type=float, default=10.0)
     ap.add_argument("--n10-steps", type=int, default=20, help="steps of the N=10 FP32/FP64 comparison")
@@ -205,6 +206,8 @@ def main():
             forms["learned"] = learned_form(hs, stream, args)
         if "magnus4" in want:
             forms["magnus4"] = magnus4_form(hs, idx, pot, c0, stream, args, value)
+        if "sym" in want:
+            forms["sym"] = sym_form(hs, idx, pot, c0, stream, args, value)
 
     cpu = None
     if not args.no_cpu:
@@ -318,6 +321,58 @@ def magnus4_form(hs, idx, pot, c0, stream, args, midpoint_matvec_per_s, nsteps=1
             # two fused passes: read v, write a and d; read a and d, write w (6 S per row)
             "m_alg_gbs": round(6 * 16.0 * idx.size / (us_m * 1e-6) / 1e9, 1),
             "rel_err_8_steps_vs_h_over_4": err}
+
+
+def sym_form(hs, idx, pot, c0, stream, args, paper_matvec_per_s, nsteps=10):
+    """The symmetrised operator D + (F + F_rev)/2 on the main workload: step rate (graph
+    replays), one H application, the symmetry defect |<u, A v> - <A u, v>| / |<u, A v>| of
+    both forms on random vectors, and the distance between the two forms' states after
+    the timed steps."""
+    import torch
+    dev = "cuda"
+    out = {}
+    state = {}
+    try:
+        for form in (hs.HS_FORM_SYM, hs.HS_FORM_PAPER):
+            pot.set_form(form)
+            c = torch.from_numpy(c0).to(dev)
+            ws = hs.workspace(idx, pot, hs.HS_C128, M_KRYLOV)
+            t_dev = torch.zeros(1, dtype=torch.float64, device=dev)
+
+            def one():
+                hs.step(idx, pot, c, 0.0, H_STEP, M_KRYLOV, reorth=True, ws=ws, t_dev=t_dev)
+            one()
+            torch.cuda.synchronize()
+            g = capture(one, stream)
+            c.copy_(torch.from_numpy(c0))
+            t_dev.zero_()
+            ms = event_time_ms(g.replay, nsteps, stream) / nsteps
+            del g
+            state[form] = c
+            x = torch.from_numpy(c0).to(dev)
+            y = torch.empty_like(x)
+            hws = hs.workspace(idx, pot, hs.HS_C128, 0)
+            pot.set_time(0.1)
+            hs.apply_h(idx, pot, x, y, hs.HS_C128, hws)
+            us_h = event_time_ms(lambda: hs.apply_h(idx, pot, x, y, hs.HS_C128, hws), 20, stream) * 1e3 / 20
+            gen = torch.Generator(device=dev).manual_seed(3)
+            u = torch.randn(idx.size, dtype=torch.complex128, device=dev, generator=gen)
+            v = torch.randn(idx.size, dtype=torch.complex128, device=dev, generator=gen)
+            au, av = torch.empty_like(u), torch.empty_like(v)
+            hs.apply_h(idx, pot, u, au, hs.HS_C128, hws)
+            hs.apply_h(idx, pot, v, av, hs.HS_C128, hws)
+            lhs, rhs = torch.vdot(u, av).item(), torch.vdot(au, v).item()
+            name = "sym" if form == hs.HS_FORM_SYM else "paper"
+            out[name] = {"ms_per_step": round(ms, 4), "matvec_per_s": round(M_KRYLOV / (ms / 1e3), 1),
+                         "us_per_h_application": round(us_h, 2), "symmetry_defect": abs(lhs - rhs) / abs(lhs)}
+            del x, y, u, v, au, av, ws
+    finally:
+        pot.set_form(hs.HS_FORM_PAPER)
+    d = float(torch.linalg.norm(state[hs.HS_FORM_SYM] - state[hs.HS_FORM_PAPER]))
+    return {"workload": "as the main line, symmetrised operator D + (F + F_rev)/2, %d steps" % nsteps,
+            "sym": out["sym"], "paper_same_run": out["paper"],
+            "step_time_vs_paper": round(out["sym"]["ms_per_step"] / out["paper"]["ms_per_step"], 3),
+            "state_distance_after_steps": d}
 
 
 def fp32_n10_form(hs, stream, args):
