@@ -1,5 +1,6 @@
 """Oracle: Gauss-Hermite projection of a smooth potential onto Hermite polynomials of
-bounded total degree, and a float64 multilayer perceptron with manual backward and Adam.
+bounded total degree, Chebyshev interpolation of it on a cube, and a float64 multilayer
+perceptron with manual backward and Adam.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
@@ -62,6 +63,25 @@ def gh_project(Wvals_fn, N: int, D: int, Q: int) -> np.ndarray:
         # contract the leading grid axis, append the degree axis at the end
         T = np.tensordot(T, P, axes=([0], [1]))
     return np.array([T[a] for a in total_degree_list(N, D)])
+
+
+def cheb_interpolate(Wvals_fn, N: int, R: int, L: float, rset) -> np.ndarray:
+    """Chebyshev interpolation of W on [-L, L]^N (Sec. 1.3): the tensor interpolant on the
+    full grid of (R + 1)^N first-kind Chebyshev points x = L cos(theta_k),
+    theta_k = (2k + 1) pi / (2 (R + 1)), in the basis T_r(x / L):
+        alpha_r = prod_l (2 - [r_l = 0]) / (R + 1) * sum_k W(x_k) prod_l cos(r_l theta_{k_l}),
+    returned for the multi-indices r in rset (r_l <= R).  Wvals_fn(points) evaluates W at
+    an array of points (M, N).  The transform is taken axis by axis with a library
+    contraction (tensordot)."""
+    theta = (2 * np.arange(R + 1) + 1) * np.pi / (2 * (R + 1))
+    x = L * np.cos(theta)
+    grid = np.stack(np.meshgrid(*([x] * N), indexing="ij"), axis=-1).reshape(-1, N)
+    F = Wvals_fn(grid).reshape((R + 1,) * N)
+    C = np.stack([np.cos(r * theta) * ((1.0 if r == 0 else 2.0) / (R + 1)) for r in range(R + 1)])
+    T = F
+    for _ in range(N):
+        T = np.tensordot(T, C, axes=([0], [1]))
+    return np.array([T[tuple(r)] for r in rset])
 
 
 def gaussian_hermite_moment_1d(n: int, c: float, s: float) -> float:
