@@ -216,6 +216,20 @@ int32_t hs_batch_autotune_sync(hs_batch b, const void *batch_dev, const void *c,
  * eigenvalues of the Hermite Jacobi matrix); one workgroup per sample; asynchronous on
  * the stream.  HS_E_INVALID for sizes out of range.                                  */
 int32_t hs_gh_ncoef(int32_t N, int32_t D, int32_t *ncoef);
+/* hs_cheb_interp: Chebyshev interpolation of the same Gaussian-well W on the cube
+ * [-L, L]^N (paper Sec. 1.3, step (1) of Fig. 4): the tensor interpolant on the
+ * (R + 1)^N first-kind Chebyshev points L cos((2k + 1) pi / (2 (R + 1))),
+ *   alpha_r = prod_l (2 - [r_l = 0]) / (R + 1) sum_k W(x_k) prod_l cos(r_l theta_{k_l}),
+ * returned for the multi-indices r with every r_l <= R and |r| <= D, in lexicographic
+ * order (hs_cheb_ncoef counts them; for D <= R this is C(N + D, N)), as coefficients of
+ * T_r(x / L) = prod_l T_{r_l}(x_l / L): a potential created with HS_BASIS_CHEB, scale L
+ * and these degrees takes them through hs_pot_set_coeffs_device.  N <= 4, G <= 4,
+ * R <= 15, (R + 1)^N + (R + 1)^2 <= 8192 (HS_E_UNSUPPORTED above), at most 512
+ * coefficients; params, coef and geometry as for hs_gh_project; one workgroup per
+ * sample; asynchronous on the stream.                                                */
+int32_t hs_cheb_ncoef(int32_t N, int32_t D, int32_t R, int32_t *ncoef);
+int32_t hs_cheb_interp(int32_t N, int32_t G, int32_t D, int32_t R, double L, const double *geometry_host,
+                       int32_t nsamp, const double *params_dev, double *coef_dev, void *stream);
 int32_t hs_gh_project(int32_t N, int32_t G, int32_t D, int32_t Q, const double *geometry_host,
                       int32_t nsamp, const double *params_dev, double *coef_dev, void *stream);
 

@@ -342,6 +342,107 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 enum GemmEpi { kEpiStore = 0, kEpiBiasSilu = 1, kEpiSiluGrad = 2 };
 
+// ---------------------------------------------------------------------------------------
+// Chebyshev interpolation (paper Sec. 1.3)
+// ---------------------------------------------------------------------------------------
+constexpr int kChMaxP = 16;                  // R + 1 points per axis
+constexpr int kChMaxCoef = 512;
+constexpr int kChThreads = 512;
+constexpr size_t kChLdsBytes = 64 * 1024;   // grid values and the cosine table
+
+struct ChArgs {
+  int N, G, P, grid, ncoef;
+  double xk[kChMaxP];              // L cos(theta_k), theta_k = (2k + 1) pi / (2P)
+  int16_t digits[kChMaxCoef];      // requested r, 4 bits per axis (axis 0 highest)
+  double base[kGhMaxG][kGhMaxN], u[kGhMaxG][kGhMaxN], w[kGhMaxG][kGhMaxN], phase[kGhMaxG];
+};
+
+// One block per sample; params row: (t, a_1..a_G, sigma, rho, omega).  W is evaluated at
+// the P^N points of the first-kind Chebyshev grid (grid index with the last axis
+// fastest) into LDS; the discrete Chebyshev transform is then taken one axis at a time,
+// in place, one fibre per thread (the P inputs of a fibre are held in registers while its
+// P outputs are written); the requested coefficients are gathered at the end.
+__global__ void __launch_bounds__(kChThreads)
+k_cheb_interp(ChArgs A, const double *__restrict__ params, double *__restrict__ coef) {
+  extern __shared__ double lds[];
+  double *F = lds, *cth = lds + A.grid;
+  const int tid = threadIdx.x, s = blockIdx.x, N = A.N, P = A.P;
+  for (int e = tid; e < P * P; e += kChThreads) {
+    const int r = e / P, k = e - r * P;
+    cth[e] = (r == 0 ? 1.0 : 2.0) / P * cos(r * (2.0 * k + 1.0) * M_PI / (2.0 * P));
+  }
+  const double *p = params + (int64_t)s * (A.G + 4);
+  const double t = p[0], sigma = p[A.G + 1], rho = p[A.G + 2], omega = p[A.G + 3];
+  const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+  double cen[kGhMaxG][kGhMaxN], amp[kGhMaxG];
+#pragma unroll
+  for (int i = 0; i < kGhMaxG; ++i) {
+    amp[i] = i < A.G ? p[1 + i] : 0.0;
+    const double ang = omega * t + A.phase[i];
+    const double ca = cos(ang), sa = sin(ang);
+#pragma unroll
+    for (int l = 0; l < kGhMaxN; ++l) cen[i][l] = A.base[i][l] + rho * (ca * A.u[i][l] + sa * A.w[i][l]);
+  }
+  for (int m = tid; m < A.grid; m += kChThreads) {
+    double xv[kGhMaxN];
+    int r = m;
+#pragma unroll
+    for (int l = kGhMaxN - 1; l >= 0; --l) {
+      xv[l] = 0.0;
+      if (l < N) {
+        const int q = r / P;
+        xv[l] = A.xk[r - q * P];
+        r = q;
+      }
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < kGhMaxG; ++i) {
+      if (i < A.G) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int l = 0; l < kGhMaxN; ++l) {
+          if (l < N) {
+            const double d = xv[l] - cen[i][l];
+            d2 = fma(d, d, d2);
+          }
+        }
+        v -= amp[i] * exp(-d2 * inv2s2);
+      }
+    }
+    F[m] = v;
+  }
+  __syncthreads();
+  // axis l has stride P^(N-1-l) in the grid index; grid / P fibres per axis
+  int stride = A.grid / P;
+  const int nf = A.grid / P;
+  for (int l = 0; l < N; ++l) {
+    for (int f = tid; f < nf; f += kChThreads) {
+      const int hi = f / stride, lo = f - hi * stride;
+      double *fb = F + (int64_t)hi * stride * P + lo;
+      double v[kChMaxP];
+#pragma unroll
+      for (int k = 0; k < kChMaxP; ++k) v[k] = k < P ? fb[(int64_t)k * stride] : 0.0;
+      for (int r = 0; r < P; ++r) {
+        const double *c = cth + r * P;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kChMaxP; ++k)
+          if (k < P) acc = fma(c[k], v[k], acc);
+        fb[(int64_t)r * stride] = acc;
+      }
+    }
+    __syncthreads();
+    stride /= P;
+  }
+  for (int c = tid; c < A.ncoef; c += kChThreads) {
+    const int dg = A.digits[c];
+    int m = 0;
+    for (int l = 0; l < N; ++l) m = m * P + ((dg >> (4 * (N - 1 - l))) & 15);
+    coef[(int64_t)s * A.ncoef + c] = F[m];
+  }
+}
+
 __device__ __forceinline__ float silu_f(float z) { return z / (1.0f + expf(-z)); }
 __device__ __forceinline__ float silu_grad_f(float z) {
   const float s = 1.0f / (1.0f + expf(-z));
@@ -705,9 +806,81 @@ int32_t gh_launch(int32_t N, int32_t G, int32_t D, int32_t Q, const double *geom
   return HS_OK;
 }
 
+int32_t cheb_launch(int32_t N, int32_t G, int32_t D, int32_t R, double L, const double *geometry_host,
+                    int32_t nsamp, const double *params_dev, double *coef_dev, hipStream_t stream) {
+  using hs::ChArgs;
+  if (N < 1 || N > hs::kGhMaxN || G < 1 || G > hs::kGhMaxG || D < 0 || R < 0 || R + 1 > hs::kChMaxP ||
+      !(L > 0.0) || !std::isfinite(L) || nsamp < 0 || !geometry_host || (nsamp > 0 && (!params_dev || !coef_dev)))
+    return hs::fail(HS_E_INVALID, "Chebyshev interpolation: arguments out of range (N<=4, G<=4, R<=15, L>0)");
+  ChArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.N = N;
+  A.G = G;
+  A.P = R + 1;
+  int64_t grid = 1;
+  for (int l = 0; l < N; ++l) grid *= A.P;
+  const size_t lds = sizeof(double) * (size_t)(grid + (int64_t)A.P * A.P);
+  if (lds > hs::kChLdsBytes) return hs::fail(HS_E_UNSUPPORTED, "Chebyshev interpolation: (R + 1)^N grid exceeds LDS");
+  A.grid = (int)grid;
+  // requested coefficients: |r| <= D with every r_l <= R, lexicographic order
+  int nc = 0;
+  std::vector<int> r(N, 0);
+  for (int64_t m = 0; m < grid; ++m) {
+    int64_t q = m;
+    int sum = 0, code = 0;
+    for (int l = N - 1; l >= 0; --l) {
+      r[l] = (int)(q % A.P);
+      q /= A.P;
+      sum += r[l];
+    }
+    if (sum > D) continue;
+    for (int l = 0; l < N; ++l) code |= r[l] << (4 * (N - 1 - l));
+    if (nc >= hs::kChMaxCoef) return hs::fail(HS_E_UNSUPPORTED, "Chebyshev interpolation: more than 512 coefficients");
+    A.digits[nc++] = (int16_t)code;
+  }
+  A.ncoef = nc;
+  for (int k = 0; k < A.P; ++k) A.xk[k] = L * std::cos((2.0 * k + 1.0) * M_PI / (2.0 * A.P));
+  const double *g = geometry_host;
+  for (int i = 0; i < G; ++i)
+    for (int l = 0; l < N; ++l) {
+      A.base[i][l] = g[i * N + l];
+      A.u[i][l] = g[G * N + i * N + l];
+      A.w[i][l] = g[2 * G * N + i * N + l];
+    }
+  for (int i = 0; i < G; ++i) A.phase[i] = g[3 * G * N + i];
+  if (nsamp == 0) return HS_OK;
+  hipLaunchKernelGGL(hs::k_cheb_interp, dim3(nsamp), dim3(hs::kChThreads), lds, stream, A, params_dev, coef_dev);
+  HS_HIP(hipGetLastError());
+  return HS_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int32_t hs_cheb_ncoef(int32_t N, int32_t D, int32_t R, int32_t *ncoef) {
+  if (!ncoef || N < 1 || N > hs::kGhMaxN || D < 0 || R < 0 || R + 1 > hs::kChMaxP)
+    return hs::fail(HS_E_INVALID, "hs_cheb_ncoef: bad arguments");
+  int64_t grid = 1, nc = 0;
+  for (int l = 0; l < N; ++l) grid *= (R + 1);
+  for (int64_t m = 0; m < grid; ++m) {
+    int64_t q = m;
+    int sum = 0;
+    for (int l = 0; l < N; ++l) {
+      sum += (int)(q % (R + 1));
+      q /= (R + 1);
+    }
+    if (sum <= D) ++nc;
+  }
+  *ncoef = (int32_t)nc;
+  return HS_OK;
+}
+
+int32_t hs_cheb_interp(int32_t N, int32_t G, int32_t D, int32_t R, double L, const double *geometry_host,
+                       int32_t nsamp, const double *params_dev, double *coef_dev, void *stream) {
+  return cheb_launch(N, G, D, R, L, geometry_host, nsamp, params_dev, coef_dev,
+                     static_cast<hipStream_t>(stream));
+}
 
 int32_t hs_gh_ncoef(int32_t N, int32_t D, int32_t *ncoef) {
   if (!ncoef || N < 1 || D < 0) return hs::fail(HS_E_INVALID, "hs_gh_ncoef: bad arguments");

@@ -9,6 +9,7 @@ import fails.
 from __future__ import annotations
 
 import ctypes as C
+import itertools
 import os
 
 import numpy as np
@@ -68,6 +69,8 @@ _SIGS = {
     "hs_batch_autotune_sync": [_vp, _vp, _vp, _vp, _vp, _vp],
     "hs_gh_ncoef": [_i32, _i32, _pi32],
     "hs_gh_project": [_i32, _i32, _i32, _i32, _pf64, _i32, _vp, _vp, _vp],
+    "hs_cheb_ncoef": [_i32, _i32, _i32, _pi32],
+    "hs_cheb_interp": [_i32, _i32, _i32, _i32, _f64, _pf64, _i32, _vp, _vp, _vp],
     "hs_mlp_create": [_i32, _i32, _i32, C.POINTER(_vp)],
     "hs_mlp_destroy": [_vp],
     "hs_mlp_device_bytes": [_vp, _i32, _pi64],
@@ -396,6 +399,35 @@ def gh_project(geom, params, D: int, Q: int, out=None):
         out = torch.empty((ns, nc), dtype=torch.float64, device=params.device)
     g = geometry_array(geom)
     hs_gh_project(N, G, D, Q, g.ctypes.data_as(_pf64), ns, ptr(params), ptr(out), stream_ptr())
+    return out
+
+
+def cheb_ncoef(N: int, D: int, R: int) -> int:
+    n = C.c_int32()
+    hs_cheb_ncoef(N, D, R, C.byref(n))
+    return n.value
+
+
+def cheb_interp(geom, params, D: int, R: int, L: float, out=None):
+    """Chebyshev coefficients (basis T_r(x/L), |r| <= D, r_l <= R) of the Gaussian-well
+    potential for each parameter row (device float64 tensor, rows of 4 + G)."""
+    torch = _torch()
+    N = geom["base"].shape[1]
+    G = geom["base"].shape[0]
+    n = params.shape[0]
+    if out is None:
+        out = torch.empty((n, cheb_ncoef(N, D, R)), dtype=torch.float64, device=params.device)
+    g = geometry_array(geom)
+    hs_cheb_interp(N, G, D, R, float(L), g.ctypes.data_as(_pf64), n, ptr(params), ptr(out), stream_ptr())
+    return out
+
+
+def cheb_degrees(N: int, D: int, R: int):
+    """The multi-indices of cheb_interp's output, in its order."""
+    out = []
+    for m in itertools.product(range(R + 1), repeat=N):
+        if sum(m) <= D:
+            out.append(tuple(m))
     return out
 
 

@@ -1,0 +1,97 @@
+"""Chebyshev interpolation of the Gaussian-well potential on the GPU (paper Sec. 1.3,
+step (1) of Fig. 4) against the oracle, and time steps whose coefficients are
+re-interpolated on the device at every midpoint, against the oracle's propagation in
+the Chebyshev basis."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.index import IndexSet
+from oracle.operators import Potential, fast_apply_H
+from oracle.propagate import lanczos_expm
+from oracle.surrogate import cheb_interpolate, circle_centres, gaussian_sum_W
+from synth import coherent_state, draw_surrogate_params, surrogate_geometry
+from tests.hsutil import lib_to_lex, rel2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hs():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1403_3511_amd import hs as _hs
+    return _hs
+
+
+def _geom(N):
+    if N == 1:  # circles degenerate to segments on the line
+        return {"base": np.array([[0.3], [-0.2], [0.0]]), "u": np.ones((3, 1)), "w": np.zeros((3, 1)),
+                "phase": np.array([0.1, 2.0, 4.0])}
+    return surrogate_geometry(N, 3, seed=7)
+
+
+def _W(geom, p):
+    G = geom["base"].shape[0]
+    cen = circle_centres(p[0], p[G + 2], p[G + 3], geom["base"], geom["u"], geom["w"], geom["phase"])
+    return lambda x: gaussian_sum_W(x, p[1:1 + G], p[G + 1], cen)
+
+
+@pytest.mark.parametrize("N,R,D,L", [(1, 15, 10, 3.0), (2, 15, 15, 4.0), (3, 12, 8, 4.0),
+                                     (4, 6, 6, 4.0), (4, 8, 5, 2.5)])
+def test_interp_vs_oracle(hs, N, R, D, L):
+    import torch
+    geom = _geom(N)
+    P = draw_surrogate_params(6, seed=300 + N + R)
+    out = hs.cheb_interp(geom, torch.from_numpy(P).to("cuda"), D, R, L)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    rset = hs.cheb_degrees(N, D, R)
+    assert got.shape == (6, len(rset)) == (6, hs.cheb_ncoef(N, D, R))
+    for s in range(6):
+        ref = cheb_interpolate(_W(geom, P[s]), N, R, L, rset)
+        assert np.max(np.abs(got[s] - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_steps_with_device_interpolation(hs):
+    """Each step re-interpolates W at t + h/2 on the device (coefficients written into
+    the potential's device block), N = 3, product bound 64, Chebyshev basis on
+    [-4, 4]^3, degree 6."""
+    import torch
+    N, B, R, D, L, h, m, n = 3, 64, 6, 6, 4.0, 0.002, 10, 4
+    geom = _geom(N)
+    p0 = draw_surrogate_params(1, seed=17)[0]
+    rset = hs.cheb_degrees(N, D, R)
+    # oracle
+    ix = IndexSet(N, B)
+    c0 = coherent_state(ix.k, [0.5, -0.3, 0.2])
+    c0 /= np.linalg.norm(c0)
+    ref = c0.copy()
+    t = 0.0
+    for _ in range(n):
+        p = p0.copy()
+        p[0] = t + 0.5 * h
+        a = cheb_interpolate(_W(geom, p), N, R, L, rset)
+        W = Potential(N, "cheb", L, list(zip(a, rset)))
+        ref = lanczos_expm(lambda v: fast_apply_H(ix, W, v), ref, h, m)[0]
+        t += h
+    # GPU
+    idx = hs.Index(N, B)
+    pot = hs.Pot(N, [(0.0, r) for r in rset], basis="cheb", scale=L)
+    lexpos = lib_to_lex(idx, N, B)
+    c = torch.from_numpy(np.ascontiguousarray(c0[lexpos])).to("cuda")
+    params = torch.from_numpy(p0[None, :].copy()).to("cuda")
+    coef = torch.empty((1, len(rset)), dtype=torch.float64, device="cuda")
+    ws = hs.workspace(idx, pot, hs.HS_C128, m)
+    t = 0.0
+    for _ in range(n):
+        params[0, 0] = t + 0.5 * h
+        hs.cheb_interp(geom, params, D, R, L, out=coef)
+        pot.set_coeffs_device(coef[0])
+        hs.step(idx, pot, c, t, h, m, ws=ws)
+        t += h
+    torch.cuda.synchronize()
+    got = np.empty_like(c0)
+    got[lexpos] = c.cpu().numpy()
+    assert rel2(got, ref) <= 1e-11

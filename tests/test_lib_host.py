@@ -124,6 +124,12 @@ def test_error_paths(hs):
     expect(-1, hs.hs_workspace_bytes, idx.h, pot2.h, 5, 10, C.byref(nb))      # dtype
     expect(-1, hs.hs_apply_h, idx.h, None, pot2.h, None, 0, None, None, None, None)  # NULL buffers
     expect(-1, hs.hs_pot_set_form, pot2.h, 7)                                 # unknown form
+    gz = np.zeros(5 * 3 * 5)
+    gp = gz.ctypes.data_as(C.POINTER(C.c_double))
+    expect(-1, hs.hs_cheb_interp, 5, 3, 4, 4, 2.0, gp, 0, None, None, None)   # N > 4
+    expect(-1, hs.hs_cheb_interp, 2, 3, 4, 16, 2.0, gp, 0, None, None, None)  # R + 1 > 16
+    expect(-1, hs.hs_cheb_interp, 2, 3, 4, 4, 0.0, gp, 0, None, None, None)   # L <= 0
+    expect(-5, hs.hs_cheb_interp, 4, 3, 4, 15, 2.0, gp, 0, None, None, None)  # 16^4 grid > LDS
     gen = hs.Pot(2, [(1.0, (4, 0))], upload=False)                            # outside the fused class
     assert not gen.fused
     expect(-5, hs.hs_pot_set_form, gen.h, hs.HS_FORM_SYM)
@@ -163,6 +169,14 @@ def test_magnus4_workspace_sizes(hs):
             hs.hs_magnus4_workspace_bytes(idx.h, pot.h, dt, 0, C.byref(c4))
             assert b.value == a.value + 3 * vec
             assert c4.value == c0.value + 3 * vec
+
+
+def test_cheb_coefficient_counts(hs):
+    import itertools
+    for N, D, R in [(1, 10, 15), (2, 15, 15), (3, 8, 12), (4, 6, 6), (4, 5, 8), (3, 20, 6)]:
+        want = sum(1 for r in itertools.product(range(R + 1), repeat=N) if sum(r) <= D)
+        assert hs.cheb_ncoef(N, D, R) == want == len(hs.cheb_degrees(N, D, R))
+    assert hs.cheb_ncoef(4, 6, 6) == math.comb(10, 4)
 
 
 def test_sizes_and_counts(hs):

@@ -103,3 +103,37 @@ def test_total_degree_truncation_order():
     a_td = cheb_interpolate(f, N, R, L, td)
     assert np.array_equal(a_td, np.array([a_full[tuple(r)] for r in td]))
     assert math.isfinite(float(np.sum(a_td)))
+
+
+def test_compare_with_gauss_hermite_projection():
+    """For the Gaussian wells and a packet near the origin, the Hermite projection
+    (weight exp(-|x|^2)) gives a more accurate Galerkin action than the Chebyshev
+    interpolant on a cube at the same total degree: the interpolant spends its accuracy
+    uniformly over [-L, L]^N.  Reference: the exact Galerkin action by a 220-point product
+    Gauss-Hermite rule on the Hermite functions."""
+    from numpy.polynomial.hermite import hermgauss
+
+    from oracle.operators import fast_apply_W, hermite_functions_scaled
+    from oracle.surrogate import gh_project
+    from synth import coherent_state
+    N, B, D = 2, 32, 6
+    f = _wells(N)
+    ix = IndexSet(N, B)
+    c = coherent_state(ix.k, [0.5, -0.3])
+    c /= np.linalg.norm(c)
+    x, w = hermgauss(220)
+    psi = hermite_functions_scaled(int(ix.k.max()), x)
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    Gw = f(np.stack([X.ravel(), Y.ravel()], -1)).reshape(x.size, x.size) * w[:, None] * w[None, :]
+    A, Bm = psi[ix.k[:, 0]], psi[ix.k[:, 1]]
+    y_ex = np.einsum("im,in,mn->i", A, Bm, Gw * np.einsum("jm,jn,j->mn", A, Bm, c))
+    td = total_degree_list(N, D)
+    herm = Potential(N, "herm", 1.0, list(zip(gh_project(f, N, D, 24), td)))
+    e_gh = np.linalg.norm(fast_apply_W(ix, herm, c) - y_ex) / np.linalg.norm(y_ex)
+    errs = {}
+    for L in (3.0, 5.0):
+        cheb = Potential(N, "cheb", L, list(zip(cheb_interpolate(f, N, D, L, td), td)))
+        errs[L] = np.linalg.norm(fast_apply_W(ix, cheb, c) - y_ex) / np.linalg.norm(y_ex)
+    print(f"relative error of W c: GH projection {e_gh:.2e}, Chebyshev L=3 {errs[3.0]:.2e}, L=5 {errs[5.0]:.2e}")
+    assert e_gh < 0.05
+    assert e_gh < errs[3.0] < errs[5.0] < 0.5
