@@ -429,8 +429,9 @@ def learned_form(hs, stream, args):
     polynomials of total degree <= 6 (210 coefficients).  Targets from the Gauss-Hermite
     projection (Q = 16) of 4096 parameter draws; the 7-256-256-210 network trained with
     Adam (batch 256); accuracy against a Q = 24 judge on 256 held-out draws; coefficient
-    latency of network and quadrature; one propagation step at product bound 8192 with
-    either coefficient source."""
+    latency of network, quadrature and Chebyshev interpolation (degree 6 on [-4, 4]^4,
+    the Chebyshev-basis potential of the same degrees); one propagation step at product
+    bound 8192 with each coefficient source."""
     import math
     import numpy as np
     import torch
@@ -485,6 +486,12 @@ def learned_form(hs, stream, args):
            "quad_q16_b256": lat_us(lambda: hs.gh_project(geom, Pv, D, Q, out=out256)),
            "quad_matched_b1": lat_us(lambda: hs.gh_project(geom, Pv[:1], D, q_match, out=out1)),
            "quad_matched_b256": lat_us(lambda: hs.gh_project(geom, Pv, D, q_match, out=out256))}
+    # Chebyshev interpolation on [-4, 4]^4 at degree 6 per axis, truncated to total degree 6
+    ncheb = hs.cheb_ncoef(N, D, D)
+    ch1 = torch.empty((1, ncheb), dtype=torch.float64, device=dev)
+    ch256 = torch.empty((256, ncheb), dtype=torch.float64, device=dev)
+    lat["cheb_r6_l4_b1"] = lat_us(lambda: hs.cheb_interp(geom, Pv[:1], D, D, 4.0, out=ch1))
+    lat["cheb_r6_l4_b256"] = lat_us(lambda: hs.cheb_interp(geom, Pv, D, D, 4.0, out=ch256))
     # one step at product bound 8192 with each coefficient source
     degs = hs.total_degree_multi_indices(N, D)
     idx = hs.Index(N, 8192)
@@ -495,14 +502,20 @@ def learned_form(hs, stream, args):
     prow = Pv[:1].clone()
     coef = torch.empty((1, nout), dtype=torch.float64, device=dev)
     res = {}
-    for src in ("network", "quadrature"):
+    cpot = hs.Pot(N, [(0.0, a) for a in hs.cheb_degrees(N, D, D)], basis="cheb", scale=4.0)
+    for src in ("network", "quadrature", "chebyshev"):
         c = torch.from_numpy(c0).to(dev)
 
         def one():
             if src == "network":
                 net.coeffs(geom, prow, D, Q, out=coef)
-            else:
+            elif src == "quadrature":
                 hs.gh_project(geom, prow, D, Q, out=coef)
+            else:
+                hs.cheb_interp(geom, prow, D, D, 4.0, out=ch1)
+                cpot.set_coeffs_device(ch1[0])
+                hs.step(idx, cpot, c, 0.0, 0.002, M_KRYLOV, ws=ws)
+                return
             pot.set_coeffs_device(coef[0])
             hs.step(idx, pot, c, 0.0, 0.002, M_KRYLOV, ws=ws)
         one()
@@ -528,6 +541,7 @@ def learned_form(hs, stream, args):
             "latency_us": {k: round(v, 2) for k, v in lat.items()},
             "step_ms_with_network": round(res["network"][0], 3),
             "step_ms_with_quadrature": round(res["quadrature"][0], 3),
+            "step_ms_with_chebyshev": round(res["chebyshev"][0], 3),
             "h_apply_ms": round(mv_ms, 3), "hc_rel_diff_network_vs_quadrature": hc_diff}
 
 
