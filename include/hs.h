@@ -88,6 +88,15 @@ int32_t hs_index_multi_indices(hs_index idx, uint16_t *host_out);
 int32_t hs_index_device_bytes(hs_index idx, int64_t *bytes);
 int32_t hs_index_upload(hs_index idx, void *dev, int64_t bytes, void *stream);
 
+/* Box sets {0..Kmax}^N (the full index set K_full of paper Sec. 4.1-4.2), in the same
+ * tiled layout (every tile holds the whole suffix list, in lexicographic order), for
+ * the error diagnostics below; every H application and step accepts them in the
+ * paper's operator form.  Kmax <= 65535, fewer than 2^31 rows.                       */
+int32_t hs_index_create_box(int32_t N, int64_t Kmax, int32_t tile_dim, hs_index *out);
+/* map_host[r] = the row of box that holds row r's multi-index of sub (sub->size int32),
+ * -1 when it lies outside the box.  HS_E_UNSUPPORTED when box is not a box set.      */
+int32_t hs_index_embed(hs_index sub, hs_index box, int32_t *map_host);
+
 /* ---- potential (paper Sec. 1.3; W = V - |x|^2/2, Sec. 1.2) ---------------------
  * Terms t = 0..nterms-1 with per-axis degrees degrees[t*N + l] in the given basis and
  * time-dependent coefficients  beta_t(t) = base_t + amp_t * sin(freq_t * t + phase_t).
@@ -169,6 +178,24 @@ int32_t hs_apply_magnus4(hs_index idx, const void *idx_dev, hs_pot pot, const vo
 int32_t hs_step_magnus4(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev1, void *pot_dev2,
                         int32_t dtype, double t, double *t_dev, double h, int32_t m, int32_t reorth,
                         void *c, void *ws, double *diag_dev, void *stream);
+
+/* ---- local error diagnostics (paper Sec. 5.1, eqs. ErrorQuadratureDef and
+ * ErrorGridReductionDef; Sec. 6.1) ---------------------------------------------------
+ * For a vector v on the set sub (complex128, library order):
+ *   e_red  = W^pol(X_K) v - Omega(W^pol(X_full) Omega_+(v))   (index set reduction)
+ *   e_quad = W_{K,pol} v - W^{GH(K)}_{K,pol} v                  (quadrature)
+ * where box is K_full = {0..K}^N containing sub (by Lemma 1 the fast algorithm on it,
+ * restricted to sub, is the Gauss-Hermite matrix W^{GH(K)}), and pad is a box padded by
+ * at least half the potential's largest per-axis degree, on which the fast algorithm
+ * restricted to sub is the exact Galerkin product W_{K,pol} v.  pad may be NULL (then
+ * e_quad is not written).  box_map / pad_map: hs_index_embed(sub, box / pad), uploaded
+ * (device int32, sub->size).  The paper's operator form only.  ws holds
+ * hs_error_split_workspace_bytes bytes.                                              */
+int32_t hs_error_split_workspace_bytes(hs_index sub, hs_index box, hs_index pad, hs_pot pot, int64_t *bytes);
+int32_t hs_error_split(hs_index sub, const void *sub_dev, hs_index box, const void *box_dev,
+                       const int32_t *box_map_dev, hs_index pad, const void *pad_dev,
+                       const int32_t *pad_map_dev, hs_pot pot, const void *pot_dev, const void *v,
+                       void *e_quad, void *e_red, void *ws, void *stream);
 
 /* ---- batched form: many (index, potential) instances in one persistent launch ----
  * Instances are described by handles plus their uploaded device blocks (which must stay

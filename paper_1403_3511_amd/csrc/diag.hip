@@ -1,0 +1,118 @@
+// Local error diagnostics of the fast algorithm (paper Sec. 5.1, eqs. ErrorQuadratureDef and
+// ErrorGridReductionDef), at the sizes the GPU holds.
+//
+//   E^red(v)  = W^pol(X_K) v - Omega(W^pol(X_full) Omega_+(v))
+//   E^quad v  = W_{K,pol} v  - W^{GH(K)}_{K,pol} v
+// with K_full the box {0..K}^N around the set.  By Lemma 1, W^{GH(K)} on the set is the
+// restriction of the fast algorithm on the box; the exact Galerkin product W_{K,pol} v is
+// the restriction of the fast algorithm on a box padded by half the polynomial's
+// per-axis degree (a polynomial of degree r moves an index by at most r/2 and back, so
+// the padded truncation is not seen by rows of the box).  The diagonal D is applied on
+// every set and cancels in both differences.
+#include "hs_internal.h"
+
+namespace hs {
+
+int32_t launch_apply(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p,
+                     const void *pot_dev, int32_t dtype, const void *x, void *y, void *ws,
+                     hipStream_t s, const double *out_scale, const void *prev,
+                     const double *prev_coef, const double *prev_scale);
+
+// y_box = Omega_+(x): zero, then the set's entries at their box rows
+__global__ void __launch_bounds__(256) k_zero(int64_t n, double2 *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = make_double2(0.0, 0.0);
+}
+__global__ void __launch_bounds__(256)
+k_scatter(int64_t n, const int32_t *__restrict__ map, const double2 *__restrict__ x, double2 *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[map[i]] = x[i];
+}
+// e = a - b (e may alias a)
+__global__ void __launch_bounds__(256)
+k_diff(int64_t n, const double2 *a, const double2 *__restrict__ b, double2 *e) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 u = a[i], w = b[i];
+  e[i] = make_double2(u.x - w.x, u.y - w.y);
+}
+__global__ void __launch_bounds__(256)
+k_gather(int64_t n, const int32_t *__restrict__ map, const double2 *__restrict__ ybox, double2 *__restrict__ g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) g[i] = ybox[map[i]];
+}
+
+static unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+struct DiagLayout {
+  int64_t big, off_x, off_y, off_g, off_apply, total;
+};
+static DiagLayout diag_layout(const hs_index_s *sub, const hs_index_s *box, const hs_index_s *pad,
+                              const hs_pot_s *p) {
+  DiagLayout L;
+  L.big = std::max<int64_t>(box->size, pad ? pad->size : 0);
+  const int64_t vb = align_up(L.big * 16, 256), vs = align_up(std::max<int64_t>(sub->size, 1) * 16, 256);
+  int64_t aws = std::max(apply_workspace_bytes(sub, p, HS_C128), apply_workspace_bytes(box, p, HS_C128));
+  if (pad) aws = std::max(aws, apply_workspace_bytes(pad, p, HS_C128));
+  L.off_x = 0;
+  L.off_y = vb;
+  L.off_g = 2 * vb;
+  L.off_apply = 2 * vb + vs;
+  L.total = L.off_apply + align_up(aws, 256);
+  return L;
+}
+
+}  // namespace hs
+
+extern "C" int32_t hs_error_split_workspace_bytes(hs_index sub, hs_index box, hs_index pad, hs_pot pot,
+                                                  int64_t *bytes) {
+  if (!sub || !box || !pot || !bytes) return hs::fail(HS_E_INVALID, "hs_error_split_workspace_bytes: NULL argument");
+  *bytes = hs::diag_layout(sub, box, pad, pot).total;
+  return HS_OK;
+}
+
+extern "C" int32_t hs_error_split(hs_index sub, const void *sub_dev, hs_index box, const void *box_dev,
+                                  const int32_t *box_map_dev, hs_index pad, const void *pad_dev,
+                                  const int32_t *pad_map_dev, hs_pot pot, const void *pot_dev, const void *v,
+                                  void *e_quad, void *e_red, void *ws, void *stream) {
+  if (!sub || !box || !pot || !sub_dev || !box_dev || !box_map_dev || !pot_dev || !v || !e_red || !ws)
+    return hs::fail(HS_E_INVALID, "hs_error_split: NULL argument");
+  if (pad && (!pad_dev || !pad_map_dev || !e_quad))
+    return hs::fail(HS_E_INVALID, "hs_error_split: padded box given without its buffers");
+  if (!box->box || (pad && !pad->box)) return hs::fail(HS_E_INVALID, "hs_error_split: box and pad must be box sets");
+  if (sub->N != pot->N || box->N != pot->N || (pad && pad->N != pot->N))
+    return hs::fail(HS_E_INVALID, "hs_error_split: sets and potential differ in N");
+  if (pad && pad->kmax < box->kmax) return hs::fail(HS_E_INVALID, "hs_error_split: the padded box is smaller than the box");
+  if (pot->form != HS_FORM_PAPER) return hs::fail(HS_E_UNSUPPORTED, "hs_error_split: the paper's operator form only");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const hs::DiagLayout L = hs::diag_layout(sub, box, pad, pot);
+  uint8_t *w8 = static_cast<uint8_t *>(ws);
+  double2 *x = (double2 *)(w8 + L.off_x), *y = (double2 *)(w8 + L.off_y), *g = (double2 *)(w8 + L.off_g);
+  void *aws = w8 + L.off_apply;
+  const int64_t n = sub->size;
+  if (n == 0) return HS_OK;
+  int32_t st;
+  // g = W^{GH(K)} v = Omega(F_box Omega_+(v))   (plus D v)
+  hipLaunchKernelGGL(hs::k_zero, dim3(hs::nb(box->size)), dim3(256), 0, s, box->size, x);
+  hipLaunchKernelGGL(hs::k_scatter, dim3(hs::nb(n)), dim3(256), 0, s, n, box_map_dev, (const double2 *)v, x);
+  if ((st = hs::launch_apply(box, box_dev, pot, pot_dev, HS_C128, x, y, aws, s, nullptr, nullptr, nullptr, nullptr)) != HS_OK)
+    return st;
+  hipLaunchKernelGGL(hs::k_gather, dim3(hs::nb(n)), dim3(256), 0, s, n, box_map_dev, (const double2 *)y, g);
+  // E^red = F_K v - g
+  if ((st = hs::launch_apply(sub, sub_dev, pot, pot_dev, HS_C128, v, e_red, aws, s, nullptr, nullptr, nullptr, nullptr)) != HS_OK)
+    return st;
+  hipLaunchKernelGGL(hs::k_diff, dim3(hs::nb(n)), dim3(256), 0, s, n, (const double2 *)e_red, (const double2 *)g,
+                     (double2 *)e_red);
+  if (pad) {
+    // E^quad = Omega(F_pad Omega_+(v)) - g
+    hipLaunchKernelGGL(hs::k_zero, dim3(hs::nb(pad->size)), dim3(256), 0, s, pad->size, x);
+    hipLaunchKernelGGL(hs::k_scatter, dim3(hs::nb(n)), dim3(256), 0, s, n, pad_map_dev, (const double2 *)v, x);
+    if ((st = hs::launch_apply(pad, pad_dev, pot, pot_dev, HS_C128, x, y, aws, s, nullptr, nullptr, nullptr, nullptr)) != HS_OK)
+      return st;
+    hipLaunchKernelGGL(hs::k_gather, dim3(hs::nb(n)), dim3(256), 0, s, n, pad_map_dev, (const double2 *)y, (double2 *)e_quad);
+    hipLaunchKernelGGL(hs::k_diff, dim3(hs::nb(n)), dim3(256), 0, s, n, (const double2 *)e_quad, (const double2 *)g,
+                       (double2 *)e_quad);
+  }
+  HS_HIP(hipGetLastError());
+  return HS_OK;
+}

@@ -8,6 +8,7 @@
 // sorted by (prod(1 + s), lex s), so the row (p, s) sits at tstart[p] + pos_G(s) and a
 // move along a prefix axis keeps the offset inside the tile.
 #include <algorithm>
+#include <memory>
 #include <cstring>
 #include <new>
 
@@ -133,6 +134,68 @@ void enumerate(int n, int64_t B, F &&f) {
   }
 }
 
+// Lexicographic enumeration of the box {0..K}^n.
+template <class F>
+void enumerate_box(int n, int64_t K, F &&f) {
+  std::vector<int32_t> k(n, 0);
+  while (true) {
+    f(k.data());
+    int i = n - 1;
+    while (i >= 0 && k[i] == K) k[i--] = 0;
+    if (i < 0) return;
+    ++k[i];
+  }
+}
+
+// The set the layout is built for: the hyperbolic cross prod(1 + k_l) <= B, or the box
+// {0..K}^n (every tile then holds the whole suffix list, in lexicographic order).
+struct SetOps {
+  bool box = false;
+  int64_t B = 0, K = 0;
+  std::unique_ptr<Counter> C;
+  SetOps(bool box_, int64_t B_, int64_t K_, int N) : box(box_), B(B_), K(K_) {
+    if (!box) C.reset(new Counter(B, N));
+  }
+  int64_t count(int n) const {
+    if (!box) return C->count(n, B);
+    int64_t r = 1;
+    for (int i = 0; i < n; ++i) r = std::min<int64_t>(r * (K + 1), kSat);
+    return r;
+  }
+  bool member(const int32_t *k, int n) const {
+    if (!box) return ::member(k, n, B);
+    for (int i = 0; i < n; ++i)
+      if (k[i] < 0 || k[i] > K) return false;
+    return true;
+  }
+  template <class F> void each(int n, F &&f) const {
+    if (box) enumerate_box(n, K, f); else enumerate(n, B, f);
+  }
+  // grade of a suffix in the global list (hyperbolic: prod(1 + s); box: one grade)
+  int64_t grade(const int32_t *s, int d) const {
+    if (box) return 0;
+    int64_t p = 1;
+    for (int a = 0; a < d; ++a) p *= 1 + s[a];
+    return p;
+  }
+};
+
+// Lexicographic rank among the members of dimension n.
+struct Ranker {
+  const SetOps *S;
+  int n;
+  std::unique_ptr<LexRank> R;
+  Ranker(const SetOps *S_, int n_) : S(S_), n(n_) {
+    if (!S->box) R.reset(new LexRank(S->C.get(), n, S->B));
+  }
+  int64_t rank(const int32_t *k) const {
+    if (!S->box) return R->rank(k);
+    int64_t r = 0;
+    for (int i = 0; i < n; ++i) r = r * (S->K + 1) + k[i];
+    return r;
+  }
+};
+
 }  // namespace
 
 hs::IndexDev hs_index_s::view(const void *dev) const {
@@ -176,11 +239,11 @@ static int32_t default_tile_dim(int32_t N) { return N <= 2 ? N : (N <= 4 ? 2 : (
 static int32_t build_index(hs_index_s *ix) {
   const int N = ix->N, d = ix->d, np = ix->np;
   const int64_t B = ix->B;
-  Counter C(B, N);
-  const int64_t total = C.count(N, B);
+  const SetOps S(ix->box, B, ix->kmax, N);
+  const int64_t total = S.count(N);
   if (total >= (INT64_C(1) << 31) - 1) return hs::fail(HS_E_OVERFLOW, "index set has 2^31 or more rows");
-  const int64_t ntiles = C.count(np, B);
-  const int64_t ng = C.count(d, B);
+  const int64_t ntiles = S.count(np);
+  const int64_t ng = S.count(d);
   ix->size = total;
   ix->ntiles = ntiles;
   ix->ng = ng;
@@ -190,13 +253,9 @@ static int32_t build_index(hs_index_s *ix) {
   std::vector<int64_t> gprod(ng);
   {
     int64_t i = 0;
-    enumerate(d, B, [&](const int32_t *k) {
-      int64_t p = 1;
-      for (int a = 0; a < d; ++a) {
-        glex[i * d + a] = k[a];
-        p *= 1 + k[a];
-      }
-      gprod[i] = p;
+    S.each(d, [&](const int32_t *k) {
+      for (int a = 0; a < d; ++a) glex[i * d + a] = k[a];
+      gprod[i] = S.grade(k, d);
       ++i;
     });
   }
@@ -215,21 +274,23 @@ static int32_t build_index(hs_index_s *ix) {
     }
     ix->gssum[g] = s;
   }
-  // length of the initial segment with prod <= b
-  std::vector<int32_t> seglen(B + 1, 0);
-  for (int64_t g = 0; g < ng; ++g) seglen[gprod[order[g]]]++;
-  for (int64_t b = 1; b <= B; ++b) seglen[b] += seglen[b - 1];
+  // length of the initial segment with prod <= b (hyperbolic sets)
+  std::vector<int32_t> seglen(S.box ? 1 : B + 1, 0);
+  if (!S.box) {
+    for (int64_t g = 0; g < ng; ++g) seglen[gprod[order[g]]]++;
+    for (int64_t b = 1; b <= B; ++b) seglen[b] += seglen[b - 1];
+  }
   // suffix neighbours
   ix->gnbr.assign((size_t)ng * 2 * d, -1);
   if (d > 0) {
-    LexRank R(&C, d, B);
+    Ranker R(&S, d);
     std::vector<int32_t> k(d);
     for (int64_t g = 0; g < ng; ++g) {
       for (int a = 0; a < d; ++a) k[a] = ix->gsidx[g * d + a];
       for (int a = 0; a < d; ++a)
         for (int dir = 0; dir < 2; ++dir) {
           k[a] += dir ? 1 : -1;
-          if (member(k.data(), d, B)) ix->gnbr[g * 2 * d + 2 * a + dir] = (int32_t)gpos_of_lex[R.rank(k.data())];
+          if (S.member(k.data(), d)) ix->gnbr[g * 2 * d + 2 * a + dir] = (int32_t)gpos_of_lex[R.rank(k.data())];
           k[a] -= dir ? 1 : -1;
         }
     }
@@ -242,7 +303,7 @@ static int32_t build_index(hs_index_s *ix) {
   ix->tstart.resize(ntiles + 1);
   {
     int64_t t = 0, start = 0;
-    enumerate(np, B, [&](const int32_t *p) {
+    S.each(np, [&](const int32_t *p) {
       int64_t prod = 1;
       int32_t s = 0;
       for (int i = 0; i < np; ++i) {
@@ -250,7 +311,7 @@ static int32_t build_index(hs_index_s *ix) {
         prod *= 1 + p[i];
         s += p[i];
       }
-      ix->tlen[t] = seglen[B / prod];
+      ix->tlen[t] = S.box ? (int32_t)ng : seglen[B / prod];
       ix->tpsum[t] = s;
       ix->tstart[t] = start;
       start += ix->tlen[t];
@@ -261,14 +322,14 @@ static int32_t build_index(hs_index_s *ix) {
   }
   ix->tnbr.assign((size_t)ntiles * 2 * np, -1);
   if (np > 0) {
-    LexRank R(&C, np, B);
+    Ranker R(&S, np);
     std::vector<int32_t> p(np);
     for (int64_t t = 0; t < ntiles; ++t) {
       for (int i = 0; i < np; ++i) p[i] = ix->tpfx[t * np + i];
       for (int i = 0; i < np; ++i)
         for (int dir = 0; dir < 2; ++dir) {
           p[i] += dir ? 1 : -1;
-          if (member(p.data(), np, B)) ix->tnbr[t * 2 * np + 2 * i + dir] = (int32_t)R.rank(p.data());
+          if (S.member(p.data(), np)) ix->tnbr[t * 2 * np + 2 * i + dir] = (int32_t)R.rank(p.data());
           p[i] -= dir ? 1 : -1;
         }
     }
@@ -281,13 +342,13 @@ static int32_t build_index(hs_index_s *ix) {
   ix->ns = 6 * d + 8 * (d - 1);
   ix->gst.assign((size_t)ix->ns * ng, -1);
   if (d > 0) {
-    LexRank R(&C, d, B);
+    Ranker R(&S, d);
     std::vector<int32_t> k(d);
     auto lookup = [&](int64_t g, int a, int s, int b, int r) -> int32_t {
       for (int i = 0; i < d; ++i) k[i] = ix->gsidx[g * d + i];
       k[a] += s;
       if (b >= 0) k[b] += r;
-      if (!member(k.data(), d, B)) return -1;
+      if (!S.member(k.data(), d)) return -1;
       return (int32_t)gpos_of_lex[R.rank(k.data())];
     };
     for (int64_t g = 0; g < ng; ++g) {
@@ -451,6 +512,59 @@ extern "C" int32_t hs_index_create(int32_t N, int64_t B, int32_t tile_dim, hs_in
     return st;
   }
   *out = ix;
+  return HS_OK;
+}
+
+extern "C" int32_t hs_index_create_box(int32_t N, int64_t Kmax, int32_t tile_dim, hs_index *out) {
+  if (!out) return hs::fail(HS_E_INVALID, "hs_index_create_box: out is NULL");
+  *out = nullptr;
+  if (N < 1 || N > HS_NMAX) return hs::fail(HS_E_INVALID, "hs_index_create_box: N out of range 1..16");
+  if (Kmax < 0 || Kmax > 65535) return hs::fail(HS_E_INVALID, "hs_index_create_box: Kmax out of range 0..65535");
+  if (tile_dim < 0 || tile_dim > N) return hs::fail(HS_E_INVALID, "hs_index_create_box: tile_dim out of range 0..N");
+  int64_t total = 1;
+  for (int i = 0; i < N; ++i) {
+    total *= Kmax + 1;
+    if (total >= (INT64_C(1) << 31) - 1) return hs::fail(HS_E_OVERFLOW, "hs_index_create_box: 2^31 or more rows");
+  }
+  hs_index_s *ix = new (std::nothrow) hs_index_s();
+  if (!ix) return hs::fail(HS_E_NOMEM, "hs_index_create_box: out of host memory");
+  ix->N = N;
+  ix->box = true;
+  ix->kmax = Kmax;
+  ix->B = Kmax + 1;  // coordinates stay below B, as on a hyperbolic set with bound B
+  ix->d = tile_dim ? tile_dim : default_tile_dim(N);
+  ix->np = N - ix->d;
+  int32_t st;
+  try {
+    st = build_index(ix);
+  } catch (const std::bad_alloc &) {
+    st = hs::fail(HS_E_NOMEM, "hs_index_create_box: out of host memory");
+  }
+  if (st != HS_OK) {
+    delete ix;
+    return st;
+  }
+  *out = ix;
+  return HS_OK;
+}
+
+extern "C" int32_t hs_index_embed(hs_index sub, hs_index box, int32_t *map_host) {
+  if (!sub || !box || !map_host) return hs::fail(HS_E_INVALID, "hs_index_embed: NULL argument");
+  if (!box->box) return hs::fail(HS_E_UNSUPPORTED, "hs_index_embed: the target must be a box set");
+  if (sub->N != box->N) return hs::fail(HS_E_INVALID, "hs_index_embed: the sets differ in N");
+  const int N = sub->N, np = box->np, d = box->d;
+  const int64_t K1 = box->kmax + 1;
+  std::vector<uint16_t> k((size_t)sub->size * N);
+  hs_index_multi_indices(sub, k.data());
+  for (int64_t r = 0; r < sub->size; ++r) {
+    const uint16_t *m = k.data() + (size_t)r * N;
+    int64_t t = 0, o = 0;
+    bool in = true;
+    for (int i = 0; i < N; ++i) in = in && m[i] <= box->kmax;
+    for (int i = 0; i < np; ++i) t = t * K1 + m[i];
+    for (int a = 0; a < d; ++a) o = o * K1 + m[np + a];
+    map_host[r] = in ? (int32_t)(box->tstart[t] + o) : -1;
+  }
   return HS_OK;
 }
 

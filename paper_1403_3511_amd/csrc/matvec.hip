@@ -515,6 +515,8 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
   const double *beta = (const double *)(pb + p->off_beta);
   const unsigned g = nblk(idx->size, 256);
   if (idx->size == 0) return HS_OK;
+  if (p->form == HS_FORM_SYM && idx->box)
+    return fail(HS_E_UNSUPPORTED, "symmetrised form: served on hyperbolic sets only");
   if (p->fused && p->form == HS_FORM_SYM) {
     // the symmetrised operator exists only as the specialised kernel serving every row
     const int done = sizeof(T) == 8

@@ -42,6 +42,10 @@ _SIGS = {
     "hs_index_multi_indices": [_vp, _pu16],
     "hs_index_device_bytes": [_vp, _pi64],
     "hs_index_upload": [_vp, _vp, _i64, _vp],
+    "hs_index_create_box": [_i32, _i64, _i32, C.POINTER(_vp)],
+    "hs_index_embed": [_vp, _vp, _pi32],
+    "hs_error_split_workspace_bytes": [_vp, _vp, _vp, _vp, _pi64],
+    "hs_error_split": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "hs_pot_create": [_i32, _i32, _f64, _i32, _pu16, _pf64, _pf64, _pf64, _pf64, _i32, C.POINTER(_vp)],
     "hs_pot_destroy": [_vp],
     "hs_pot_is_fused": [_vp, _pi32],
@@ -151,10 +155,11 @@ def ptr(t):
 class Index:
     """Host handle + uploaded device block of K_N(B)."""
 
-    def __init__(self, N: int, B: int, tile_dim: int = 0, device="cuda", upload=True):
+    def __init__(self, N: int, B: int, tile_dim: int = 0, device="cuda", upload=True, box: bool = False):
+        """box=False: the hyperbolic cross prod(1 + k_l) <= B; box=True: {0..B}^N."""
         h = _vp()
-        hs_index_create(N, B, tile_dim, C.byref(h))
-        self.h, self.N, self.B = h, N, B
+        (hs_index_create_box if box else hs_index_create)(N, B, tile_dim, C.byref(h))
+        self.h, self.N, self.B, self.box = h, N, B, box
         n = C.c_int64()
         hs_index_size(h, C.byref(n))
         self.size = n.value
@@ -171,6 +176,12 @@ class Index:
     def multi_indices(self) -> np.ndarray:
         out = np.empty((self.size, self.N), dtype=np.uint16)
         hs_index_multi_indices(self.h, out.ctypes.data_as(_pu16))
+        return out
+
+    def embed_map(self, box: "Index") -> np.ndarray:
+        """Row of box holding each of this set's multi-indices (-1 outside)."""
+        out = np.empty(self.size, dtype=np.int32)
+        hs_index_embed(self.h, box.h, out.ctypes.data_as(_pi32))
         return out
 
     def __del__(self):
@@ -306,6 +317,28 @@ def step_magnus4(idx: Index, pot: Pot, c, t: float, h: float, m: int, dtype: int
     hs_step_magnus4(idx.h, ptr(idx.dev), pot.h, ptr(d1), ptr(d2), dtype, float(t), ptr(t_dev),
                     float(h), int(m), 1 if reorth else 0, ptr(c), ptr(ws), ptr(diag), stream_ptr())
     return c
+
+
+def error_split(sub: Index, box: Index, pad, pot: Pot, v, e_quad=None, e_red=None, maps=None):
+    """(e_quad, e_red) of the fast algorithm for v on sub (complex128 device tensor): the
+    quadrature error against the padded box pad (None: e_quad is None) and the index-set
+    reduction error against the box."""
+    torch = _torch()
+    if maps is None:
+        maps = (torch.from_numpy(sub.embed_map(box)).to(v.device),
+                torch.from_numpy(sub.embed_map(pad)).to(v.device) if pad is not None else None)
+    if e_red is None:
+        e_red = torch.empty_like(v)
+    if pad is not None and e_quad is None:
+        e_quad = torch.empty_like(v)
+    nb = C.c_int64()
+    hs_error_split_workspace_bytes(sub.h, box.h, pad.h if pad is not None else None, pot.h, C.byref(nb))
+    ws = dev_buffer(nb.value, v.device)
+    hs_error_split(sub.h, ptr(sub.dev), box.h, ptr(box.dev), ptr(maps[0]),
+                   pad.h if pad is not None else None, ptr(pad.dev) if pad is not None else None,
+                   ptr(maps[1]) if pad is not None else None, pot.h, ptr(pot.dev), ptr(v),
+                   ptr(e_quad) if pad is not None else None, ptr(e_red), ptr(ws), stream_ptr())
+    return e_quad, e_red
 
 
 class Batch:

@@ -59,6 +59,40 @@ def test_host_index_matches_oracle(hs, N, B, d):
         assert g == sorted(g)
 
 
+@pytest.mark.parametrize("N,K,d", [(1, 7, 0), (2, 9, 0), (3, 5, 1), (3, 5, 3), (4, 4, 0), (4, 4, 2)])
+def test_box_index_matches_full_box(hs, N, K, d):
+    """Box sets: the rows are exactly {0..K}^N; tiles share prefixes and every tile holds
+    the whole suffix list in lexicographic order."""
+    from oracle.index import full_box
+    idx = hs.Index(N, K, d, upload=False, box=True)
+    assert idx.size == (K + 1) ** N
+    k = idx.multi_indices().astype(np.int64)
+    assert sorted(map(tuple, k)) == sorted(map(tuple, full_box(N, K).astype(np.int64)))
+    dd = idx.tile_dim
+    assert idx.ntiles == (K + 1) ** (N - dd)
+    tile = (K + 1) ** dd
+    for t in range(idx.ntiles):
+        blk = k[t * tile:(t + 1) * tile]
+        assert len({tuple(p) for p in blk[:, :N - dd]}) == 1
+        assert [tuple(s) for s in blk[:, N - dd:]] == sorted(tuple(s) for s in blk[:, N - dd:])
+
+
+def test_embedding_into_a_box(hs):
+    """hs_index_embed: each row of a hyperbolic set maps to the box row with the same
+    multi-index, or to -1 outside a smaller box."""
+    sub = hs.Index(3, 30, upload=False)
+    ks = sub.multi_indices().astype(np.int64)
+    for K, d in ((29, 0), (5, 1), (5, 3)):
+        box = hs.Index(3, K, d, upload=False, box=True)
+        kb = box.multi_indices().astype(np.int64)
+        m = sub.embed_map(box)
+        inside = np.all(ks <= K, axis=1)
+        assert np.array_equal(m >= 0, inside)
+        assert np.array_equal(kb[m[inside]], ks[inside])
+    with pytest.raises(hs.HSError):
+        sub.embed_map(hs.Index(3, 10, upload=False))   # the target must be a box
+
+
 def test_prefix_tiles_are_initial_segments(hs):
     """A tile with remaining bound b holds the first |K_d(b)| suffixes of the global list."""
     N, B = 5, 400
