@@ -20,8 +20,8 @@ Also measured inside this run:
                    workload with its error against the float64 run, the batched form
                    (256 instances, one persistent launch per H application) against the
                    same instances stepped one by one, the N = 10 FP32 form, the learned
-                   coefficient path, the fourth-order two-stage Magnus step, and the
-                   symmetrised operator.
+                   coefficient path, the fourth-order two-stage Magnus step, the
+                   symmetrised operator, and the local error diagnostics of Fig. 9.
   cpu_baseline  -- the CPU oracle's fast algorithm on the same workload (rank 0 only).
 
 --calibrate-copy MIB runs only a device-to-device copy of that size (the reference
@@ -118,7 +118,7 @@ def main():
     ap.add_argument("--tile-dim", type=int, default=0)
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--forms", type=int, default=1, help="also measure the FP32 and batched forms")
-    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4,sym",
+    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4,sym,diag",
                     help="comma-separated forms measured when --forms is set")
     ap.add_argument("--batch-log2-bmax", type=float, default=10.0)
     ap.add_argument("--n10-steps", type=int, default=20, help="steps of the N=10 FP32/FP64 comparison")
@@ -208,6 +208,8 @@ def main():
             forms["magnus4"] = magnus4_form(hs, idx, pot, c0, stream, args, value)
         if "sym" in want:
             forms["sym"] = sym_form(hs, idx, pot, c0, stream, args, value)
+        if "diag" in want:
+            forms["diag"] = diag_form(hs, stream, args)
 
     cpu = None
     if not args.no_cpu:
@@ -373,6 +375,52 @@ def sym_form(hs, idx, pot, c0, stream, args, paper_matvec_per_s, nsteps=10):
             "sym": out["sym"], "paper_same_run": out["paper"],
             "step_time_vs_paper": round(out["sym"]["ms_per_step"] / out["paper"]["ms_per_step"], 3),
             "state_distance_after_steps": d}
+
+
+# Fig. 9 of the paper, N = 4 column: infinity norms of E^quad v and E^red(v) for the
+# torsional potential (L = 16, degree 8, beta = 5), and the paper's own times at K = 75
+# (assembly of the Gauss-Hermite matrix and one product; one fast-algorithm product)
+FIG9_N4 = {25: (6.347e-10, 6.834e-05), 50: (3.812e-11, 1.426e-06), 75: (7.328e-12, 1.879e-07)}
+FIG9_N4_PAPER_SECONDS = {"gh_assembly_and_product": 55.8 * 60, "fast_algorithm": 0.047}
+
+
+def diag_form(hs, stream, args, reps=5):
+    """Local errors of the fast algorithm at the sizes of Fig. 9's N = 4 column: E^quad v
+    (against the fast algorithm on a box padded by 4, which is the exact Galerkin product
+    for degree 8) and E^red(v) (against the box {0..K}^4), torsional potential in its
+    degree-8 Chebyshev series, v_k = prod max(k_l, 1)^-5 normalised."""
+    import numpy as np
+    import torch
+    from synth import decay_vector, torsional_series
+    N = 4
+    pot = hs.Pot(N, torsional_series(N), basis="cheb", scale=16.0)
+    out = {}
+    for K in (25, 50, 75):
+        t0 = time.perf_counter()
+        sub = hs.Index(N, K + 1)
+        box = hs.Index(N, K, box=True)
+        pad = hs.Index(N, K + 4, box=True)
+        host_s = time.perf_counter() - t0
+        v = decay_vector(sub.multi_indices(), 5.0)
+        v /= np.linalg.norm(v)
+        vt = torch.from_numpy(v).to("cuda")
+        maps = (torch.from_numpy(sub.embed_map(box)).to("cuda"), torch.from_numpy(sub.embed_map(pad)).to("cuda"))
+        eq, er = torch.empty_like(vt), torch.empty_like(vt)
+        import ctypes
+        nb = ctypes.c_int64()
+        hs.hs_error_split_workspace_bytes(sub.h, box.h, pad.h, pot.h, ctypes.byref(nb))
+        ws = hs.dev_buffer(nb.value)
+        hs.error_split(sub, box, pad, pot, vt, e_quad=eq, e_red=er, maps=maps, ws=ws)
+        torch.cuda.synchronize()
+        ms = event_time_ms(lambda: hs.error_split(sub, box, pad, pot, vt, e_quad=eq, e_red=er, maps=maps, ws=ws),
+                           reps, stream) / reps
+        nq, nr = float(eq.abs().max()), float(er.abs().max())
+        out[f"K{K}"] = {"set_rows": sub.size, "box_rows": box.size, "padded_box_rows": pad.size,
+                        "einf_quad": nq, "einf_red": nr, "paper_quad": FIG9_N4[K][0], "paper_red": FIG9_N4[K][1],
+                        "ms_both_errors": round(ms, 3), "host_index_build_s": round(host_s, 2)}
+        del sub, box, pad, vt, eq, er, maps, ws
+    return {"workload": "Fig. 9, N = 4 column: torsional potential (L = 16, Chebyshev degree 8), beta = 5",
+            "cases": out, "paper_seconds_at_K75": FIG9_N4_PAPER_SECONDS}
 
 
 def fp32_n10_form(hs, stream, args):

@@ -319,7 +319,7 @@ def step_magnus4(idx: Index, pot: Pot, c, t: float, h: float, m: int, dtype: int
     return c
 
 
-def error_split(sub: Index, box: Index, pad, pot: Pot, v, e_quad=None, e_red=None, maps=None):
+def error_split(sub: Index, box: Index, pad, pot: Pot, v, e_quad=None, e_red=None, maps=None, ws=None):
     """(e_quad, e_red) of the fast algorithm for v on sub (complex128 device tensor): the
     quadrature error against the padded box pad (None: e_quad is None) and the index-set
     reduction error against the box."""
@@ -331,9 +331,10 @@ def error_split(sub: Index, box: Index, pad, pot: Pot, v, e_quad=None, e_red=Non
         e_red = torch.empty_like(v)
     if pad is not None and e_quad is None:
         e_quad = torch.empty_like(v)
-    nb = C.c_int64()
-    hs_error_split_workspace_bytes(sub.h, box.h, pad.h if pad is not None else None, pot.h, C.byref(nb))
-    ws = dev_buffer(nb.value, v.device)
+    if ws is None:
+        nb = C.c_int64()
+        hs_error_split_workspace_bytes(sub.h, box.h, pad.h if pad is not None else None, pot.h, C.byref(nb))
+        ws = dev_buffer(nb.value, v.device)
     hs_error_split(sub.h, ptr(sub.dev), box.h, ptr(box.dev), ptr(maps[0]),
                    pad.h if pad is not None else None, ptr(pad.dev) if pad is not None else None,
                    ptr(maps[1]) if pad is not None else None, pot.h, ptr(pot.dev), ptr(v),

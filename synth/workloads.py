@@ -15,7 +15,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "TimeTerm", "henon_heiles_chain", "stretched_hh_cw_laser", "lex_order",
+    "TimeTerm", "henon_heiles_chain", "stretched_hh_cw_laser", "torsional_series", "lex_order",
     "complex_normal_by_index", "coherent_state", "decay_vector",
     "batch_instances", "surrogate_geometry", "surrogate_param_box",
     "draw_surrogate_params", "mlp_initial_weights",
@@ -75,6 +75,22 @@ def stretched_hh_cw_laser(N: int, L: float = 16.0):
         terms.append(TimeTerm(1.0 / L ** 3, _deg(N, [(l, 2), (l + 1, 1)])))
         terms.append(TimeTerm(-1.0 / (3.0 * L ** 3), _deg(N, [(l + 1, 3)])))
     terms.append(TimeTerm(-0.5 / L, _deg(N, [(0, 1)]), amp=0.5 / L, freq=2.0, phase=0.5 * math.pi))
+    return terms
+
+
+def torsional_series(N: int, L: float = 16.0, R: int = 8):
+    """The torsional potential W = sum_l (1 - cos(x_l / L)) written in the Chebyshev basis
+    T_r(x_l / L) up to degree R, with the closed-form (Jacobi-Anger) coefficients
+        1 - cos(y) = 1 - J_0(1) - 2 sum_{k >= 1} (-1)^k J_{2k}(1) T_{2k}(y)
+    truncated at degree R (the neglected tail is below |J_{R+2}(1)|, 2.6e-10 for R = 8).
+    Returns (coef, degrees) pairs; the N constant terms are merged."""
+    from scipy.special import jv
+    terms = [(N * (1.0 - jv(0, 1.0)), (0,) * N)]
+    for l in range(N):
+        for r in range(2, R + 1, 2):
+            a = [0] * N
+            a[l] = r
+            terms.append((-2.0 * (-1.0) ** (r // 2) * jv(r, 1.0), tuple(a)))
     return terms
 
 
