@@ -55,6 +55,10 @@ extern "C" {
 
 #define HS_NMAX 16
 
+#define HS_SET_HYPERBOLIC 0   /* prod(1 + k_l) <= B (paper Sec. 1.2)                       */
+#define HS_SET_BOX 1          /* {0..K}^N (K_full)                                          */
+#define HS_SET_TOTAL_DEGREE 2 /* |k|_1 <= D                                                 */
+
 #define HS_FORM_PAPER 0 /* the fast operator F: factors applied axis N first (eq. Horner)   */
 #define HS_FORM_SYM 1   /* its symmetric part D + (F + F_rev)/2 (see hs_pot_set_form)     */
 
@@ -93,6 +97,11 @@ int32_t hs_index_upload(hs_index idx, void *dev, int64_t bytes, void *stream);
  * the error diagnostics below; every H application and step accepts them in the
  * paper's operator form.  Kmax <= 65535, fewer than 2^31 rows.                       */
 int32_t hs_index_create_box(int32_t N, int64_t Kmax, int32_t tile_dim, hs_index *out);
+/* Total-degree sets {k : |k|_1 <= D}, another downward-closed family on which the
+ * method applies unchanged (paper Sec. 1.2 requires only that k - e_l stays in the set),
+ * in the same tiled layout (suffixes graded by |s|_1).  D <= 65535, fewer than 2^31
+ * rows.  Every H application and step accepts them in the paper's operator form.    */
+int32_t hs_index_create_total_degree(int32_t N, int64_t D, int32_t tile_dim, hs_index *out);
 /* map_host[r] = the row of box that holds row r's multi-index of sub (sub->size int32),
  * -1 when it lies outside the box.  HS_E_UNSUPPORTED when box is not a box set.      */
 int32_t hs_index_embed(hs_index sub, hs_index box, int32_t *map_host);

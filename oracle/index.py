@@ -157,3 +157,29 @@ class BoxIndex:
         for l in range(self.N):
             r = r * n1 + k[:, l]
         return r
+
+
+class TotalDegreeIndex:
+    """The total-degree set {k in N_0^N : |k|_1 <= D} (a downward-closed set other than
+    the hyperbolic cross, Sec. 1.2) in lex order, with neighbour maps and rank, same
+    interface as IndexSet.  Enumerated by brute force over the box {0..D}^N."""
+
+    def __init__(self, N: int, D: int):
+        self.N, self.D = N, D
+        grid = np.indices((D + 1,) * N).reshape(N, -1).T
+        self.k = grid[grid.sum(axis=1) <= D].astype(np.uint16)   # lex order (last axis fastest)
+        self.size = self.k.shape[0]
+        self._pos = {tuple(int(x) for x in row): i for i, row in enumerate(self.k)}
+        self.nbr_plus = np.full((N, self.size), -1, dtype=np.int64)
+        self.nbr_minus = np.full((N, self.size), -1, dtype=np.int64)
+        for i, row in enumerate(self.k):
+            for l in range(N):
+                m = [int(x) for x in row]
+                m[l] += 1
+                self.nbr_plus[l, i] = self._pos.get(tuple(m), -1)
+                m[l] -= 2
+                if m[l] >= 0:
+                    self.nbr_minus[l, i] = self._pos[tuple(m)]
+
+    def rank(self, k: np.ndarray) -> np.ndarray:
+        return np.array([self._pos[tuple(int(x) for x in row)] for row in np.atleast_2d(k)], dtype=np.int64)

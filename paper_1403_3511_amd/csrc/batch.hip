@@ -197,7 +197,7 @@ extern "C" int32_t hs_batch_create(int32_t n, const hs_index *idx, const void *c
         delete b;
         return hs::fail(HS_E_UNSUPPORTED, "hs_batch_create: an instance has 2^27 or more rows");
       }
-      if (idx[i]->box) {
+      if (idx[i]->kind != HS_SET_HYPERBOLIC) {
         delete b;
         return hs::fail(HS_E_UNSUPPORTED, "hs_batch_create: batches serve hyperbolic sets only");
       }

@@ -79,7 +79,8 @@ extern "C" int32_t hs_error_split(hs_index sub, const void *sub_dev, hs_index bo
     return hs::fail(HS_E_INVALID, "hs_error_split: NULL argument");
   if (pad && (!pad_dev || !pad_map_dev || !e_quad))
     return hs::fail(HS_E_INVALID, "hs_error_split: padded box given without its buffers");
-  if (!box->box || (pad && !pad->box)) return hs::fail(HS_E_INVALID, "hs_error_split: box and pad must be box sets");
+  if (box->kind != HS_SET_BOX || (pad && pad->kind != HS_SET_BOX))
+    return hs::fail(HS_E_INVALID, "hs_error_split: box and pad must be box sets");
   if (sub->N != pot->N || box->N != pot->N || (pad && pad->N != pot->N))
     return hs::fail(HS_E_INVALID, "hs_error_split: sets and potential differ in N");
   if (pad && pad->kmax < box->kmax) return hs::fail(HS_E_INVALID, "hs_error_split: the padded box is smaller than the box");

@@ -95,8 +95,8 @@ constexpr int kLongTile = 32;    // tiles at least this long go to the long-tile
 struct hs_index_s {
   int32_t N = 0, d = 0, np = 0;
   int64_t B = 0, size = 0, ntiles = 0, ng = 0;
-  bool box = false;           // the box {0..kmax}^N instead of the hyperbolic cross
-  int64_t kmax = 0;
+  int32_t kind = HS_SET_HYPERBOLIC;   // HS_SET_BOX: {0..kmax}^N; HS_SET_TOTAL_DEGREE: |k|_1 <= deg
+  int64_t kmax = 0, deg = 0;
   std::vector<uint16_t> tpfx;
   std::vector<int64_t> tstart;
   std::vector<int32_t> tlen, tnbr, tpsum;

@@ -147,36 +147,87 @@ void enumerate_box(int n, int64_t K, F &&f) {
   }
 }
 
-// The set the layout is built for: the hyperbolic cross prod(1 + k_l) <= B, or the box
-// {0..K}^n (every tile then holds the whole suffix list, in lexicographic order).
+// Lexicographic enumeration of the simplex {k : |k|_1 <= D}.
+template <class F>
+void enumerate_simplex(int n, int64_t D, F &&f) {
+  std::vector<int32_t> k(n, 0);
+  int64_t sum = 0;
+  while (true) {
+    f(k.data());
+    int i = n - 1;
+    // raise the deepest coordinate that still fits, clearing the ones after it
+    while (i >= 0 && sum >= D) {
+      sum -= k[i];
+      k[i] = 0;
+      --i;
+    }
+    if (i < 0) return;
+    ++k[i];
+    ++sum;
+  }
+}
+
+// |{k in N_0^n : |k|_1 <= b}| = C(n + b, n), saturated
+int64_t simplex_count(int n, int64_t b) {
+  if (b < 0) return 0;
+  double c = 1.0;
+  for (int i = 1; i <= n; ++i) c = c * (double)(b + i) / i;
+  return c > (double)kSat ? kSat : (int64_t)(c + 0.5);
+}
+
+// The set the layout is built for, as a budget that the coordinates spend:
+//   hyperbolic cross prod(1 + k_l) <= B  (grade of a suffix: prod(1 + s_a));
+//   box {0..K}^n                          (one grade);
+//   total degree |k|_1 <= D               (grade: |s|_1).
+// A tile with prefix p keeps the suffixes whose grade fits the budget p leaves, and
+// these are an initial segment of the suffix list sorted by (grade, lex): that is what
+// lets a move along a prefix axis keep the row's offset inside the tile.
 struct SetOps {
-  bool box = false;
-  int64_t B = 0, K = 0;
+  int kind = HS_SET_HYPERBOLIC;
+  int64_t B = 0, K = 0, D = 0;
   std::unique_ptr<Counter> C;
-  SetOps(bool box_, int64_t B_, int64_t K_, int N) : box(box_), B(B_), K(K_) {
-    if (!box) C.reset(new Counter(B, N));
+  SetOps(int kind_, int64_t B_, int64_t K_, int64_t D_, int N) : kind(kind_), B(B_), K(K_), D(D_) {
+    if (kind == HS_SET_HYPERBOLIC) C.reset(new Counter(B, N));
   }
   int64_t count(int n) const {
-    if (!box) return C->count(n, B);
+    if (kind == HS_SET_HYPERBOLIC) return C->count(n, B);
+    if (kind == HS_SET_TOTAL_DEGREE) return simplex_count(n, D);
     int64_t r = 1;
     for (int i = 0; i < n; ++i) r = std::min<int64_t>(r * (K + 1), kSat);
     return r;
   }
   bool member(const int32_t *k, int n) const {
-    if (!box) return ::member(k, n, B);
-    for (int i = 0; i < n; ++i)
-      if (k[i] < 0 || k[i] > K) return false;
-    return true;
+    if (kind == HS_SET_HYPERBOLIC) return ::member(k, n, B);
+    int64_t sum = 0;
+    for (int i = 0; i < n; ++i) {
+      if (k[i] < 0 || (kind == HS_SET_BOX && k[i] > K)) return false;
+      sum += k[i];
+    }
+    return kind == HS_SET_BOX || sum <= D;
   }
   template <class F> void each(int n, F &&f) const {
-    if (box) enumerate_box(n, K, f); else enumerate(n, B, f);
+    if (kind == HS_SET_BOX) enumerate_box(n, K, f);
+    else if (kind == HS_SET_TOTAL_DEGREE) enumerate_simplex(n, D, f);
+    else enumerate(n, B, f);
   }
-  // grade of a suffix in the global list (hyperbolic: prod(1 + s); box: one grade)
   int64_t grade(const int32_t *s, int d) const {
-    if (box) return 0;
-    int64_t p = 1;
-    for (int a = 0; a < d; ++a) p *= 1 + s[a];
-    return p;
+    if (kind == HS_SET_BOX) return 0;
+    int64_t g = kind == HS_SET_HYPERBOLIC ? 1 : 0;
+    for (int a = 0; a < d; ++a) g = kind == HS_SET_HYPERBOLIC ? g * (1 + s[a]) : g + s[a];
+    return g;
+  }
+  int64_t max_grade() const { return kind == HS_SET_HYPERBOLIC ? B : (kind == HS_SET_TOTAL_DEGREE ? D : 0); }
+  // largest suffix grade that fits after prefix p
+  int64_t budget(const int32_t *p, int np) const {
+    if (kind == HS_SET_BOX) return 0;
+    if (kind == HS_SET_TOTAL_DEGREE) {
+      int64_t sum = 0;
+      for (int i = 0; i < np; ++i) sum += p[i];
+      return D - sum;
+    }
+    int64_t prod = 1;
+    for (int i = 0; i < np; ++i) prod *= 1 + p[i];
+    return B / prod;
   }
 };
 
@@ -186,12 +237,20 @@ struct Ranker {
   int n;
   std::unique_ptr<LexRank> R;
   Ranker(const SetOps *S_, int n_) : S(S_), n(n_) {
-    if (!S->box) R.reset(new LexRank(S->C.get(), n, S->B));
+    if (S->kind == HS_SET_HYPERBOLIC) R.reset(new LexRank(S->C.get(), n, S->B));
   }
   int64_t rank(const int32_t *k) const {
-    if (!S->box) return R->rank(k);
+    if (S->kind == HS_SET_HYPERBOLIC) return R->rank(k);
     int64_t r = 0;
-    for (int i = 0; i < n; ++i) r = r * (S->K + 1) + k[i];
+    if (S->kind == HS_SET_BOX) {
+      for (int i = 0; i < n; ++i) r = r * (S->K + 1) + k[i];
+      return r;
+    }
+    int64_t left = S->D;  // members before k: those that differ first at position i below k_i
+    for (int i = 0; i < n; ++i) {
+      for (int32_t a = 0; a < k[i]; ++a) r += simplex_count(n - 1 - i, left - a);
+      left -= k[i];
+    }
     return r;
   }
 };
@@ -239,7 +298,7 @@ static int32_t default_tile_dim(int32_t N) { return N <= 2 ? N : (N <= 4 ? 2 : (
 static int32_t build_index(hs_index_s *ix) {
   const int N = ix->N, d = ix->d, np = ix->np;
   const int64_t B = ix->B;
-  const SetOps S(ix->box, B, ix->kmax, N);
+  const SetOps S(ix->kind, B, ix->kmax, ix->deg, N);
   const int64_t total = S.count(N);
   if (total >= (INT64_C(1) << 31) - 1) return hs::fail(HS_E_OVERFLOW, "index set has 2^31 or more rows");
   const int64_t ntiles = S.count(np);
@@ -274,12 +333,10 @@ static int32_t build_index(hs_index_s *ix) {
     }
     ix->gssum[g] = s;
   }
-  // length of the initial segment with prod <= b (hyperbolic sets)
-  std::vector<int32_t> seglen(S.box ? 1 : B + 1, 0);
-  if (!S.box) {
-    for (int64_t g = 0; g < ng; ++g) seglen[gprod[order[g]]]++;
-    for (int64_t b = 1; b <= B; ++b) seglen[b] += seglen[b - 1];
-  }
+  // length of the initial segment with grade <= b
+  std::vector<int32_t> seglen(S.max_grade() + 1, 0);
+  for (int64_t g = 0; g < ng; ++g) seglen[gprod[order[g]]]++;
+  for (int64_t b = 1; b <= S.max_grade(); ++b) seglen[b] += seglen[b - 1];
   // suffix neighbours
   ix->gnbr.assign((size_t)ng * 2 * d, -1);
   if (d > 0) {
@@ -311,7 +368,7 @@ static int32_t build_index(hs_index_s *ix) {
         prod *= 1 + p[i];
         s += p[i];
       }
-      ix->tlen[t] = S.box ? (int32_t)ng : seglen[B / prod];
+      ix->tlen[t] = seglen[S.budget(p, np)];
       ix->tpsum[t] = s;
       ix->tstart[t] = start;
       start += ix->tlen[t];
@@ -529,7 +586,7 @@ extern "C" int32_t hs_index_create_box(int32_t N, int64_t Kmax, int32_t tile_dim
   hs_index_s *ix = new (std::nothrow) hs_index_s();
   if (!ix) return hs::fail(HS_E_NOMEM, "hs_index_create_box: out of host memory");
   ix->N = N;
-  ix->box = true;
+  ix->kind = HS_SET_BOX;
   ix->kmax = Kmax;
   ix->B = Kmax + 1;  // coordinates stay below B, as on a hyperbolic set with bound B
   ix->d = tile_dim ? tile_dim : default_tile_dim(N);
@@ -548,9 +605,39 @@ extern "C" int32_t hs_index_create_box(int32_t N, int64_t Kmax, int32_t tile_dim
   return HS_OK;
 }
 
+extern "C" int32_t hs_index_create_total_degree(int32_t N, int64_t D, int32_t tile_dim, hs_index *out) {
+  if (!out) return hs::fail(HS_E_INVALID, "hs_index_create_total_degree: out is NULL");
+  *out = nullptr;
+  if (N < 1 || N > HS_NMAX) return hs::fail(HS_E_INVALID, "hs_index_create_total_degree: N out of range 1..16");
+  if (D < 0 || D > 65535) return hs::fail(HS_E_INVALID, "hs_index_create_total_degree: D out of range 0..65535");
+  if (tile_dim < 0 || tile_dim > N) return hs::fail(HS_E_INVALID, "hs_index_create_total_degree: tile_dim out of range 0..N");
+  if (simplex_count(N, D) >= (INT64_C(1) << 31) - 1)
+    return hs::fail(HS_E_OVERFLOW, "hs_index_create_total_degree: 2^31 or more rows");
+  hs_index_s *ix = new (std::nothrow) hs_index_s();
+  if (!ix) return hs::fail(HS_E_NOMEM, "hs_index_create_total_degree: out of host memory");
+  ix->N = N;
+  ix->kind = HS_SET_TOTAL_DEGREE;
+  ix->deg = D;
+  ix->B = D + 1;  // coordinates stay below B, as on a hyperbolic set with bound B
+  ix->d = tile_dim ? tile_dim : default_tile_dim(N);
+  ix->np = N - ix->d;
+  int32_t st;
+  try {
+    st = build_index(ix);
+  } catch (const std::bad_alloc &) {
+    st = hs::fail(HS_E_NOMEM, "hs_index_create_total_degree: out of host memory");
+  }
+  if (st != HS_OK) {
+    delete ix;
+    return st;
+  }
+  *out = ix;
+  return HS_OK;
+}
+
 extern "C" int32_t hs_index_embed(hs_index sub, hs_index box, int32_t *map_host) {
   if (!sub || !box || !map_host) return hs::fail(HS_E_INVALID, "hs_index_embed: NULL argument");
-  if (!box->box) return hs::fail(HS_E_UNSUPPORTED, "hs_index_embed: the target must be a box set");
+  if (box->kind != HS_SET_BOX) return hs::fail(HS_E_UNSUPPORTED, "hs_index_embed: the target must be a box set");
   if (sub->N != box->N) return hs::fail(HS_E_INVALID, "hs_index_embed: the sets differ in N");
   const int N = sub->N, np = box->np, d = box->d;
   const int64_t K1 = box->kmax + 1;

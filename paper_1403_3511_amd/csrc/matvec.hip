@@ -515,7 +515,7 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
   const double *beta = (const double *)(pb + p->off_beta);
   const unsigned g = nblk(idx->size, 256);
   if (idx->size == 0) return HS_OK;
-  if (p->form == HS_FORM_SYM && idx->box)
+  if (p->form == HS_FORM_SYM && idx->kind != HS_SET_HYPERBOLIC)
     return fail(HS_E_UNSUPPORTED, "symmetrised form: served on hyperbolic sets only");
   if (p->fused && p->form == HS_FORM_SYM) {
     // the symmetrised operator exists only as the specialised kernel serving every row

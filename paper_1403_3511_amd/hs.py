@@ -44,6 +44,7 @@ _SIGS = {
     "hs_index_upload": [_vp, _vp, _i64, _vp],
     "hs_index_create_box": [_i32, _i64, _i32, C.POINTER(_vp)],
     "hs_index_embed": [_vp, _vp, _pi32],
+    "hs_index_create_total_degree": [_i32, _i64, _i32, C.POINTER(_vp)],
     "hs_error_split_workspace_bytes": [_vp, _vp, _vp, _vp, _pi64],
     "hs_error_split": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "hs_pot_create": [_i32, _i32, _f64, _i32, _pu16, _pf64, _pf64, _pf64, _pf64, _i32, C.POINTER(_vp)],
@@ -155,10 +156,13 @@ def ptr(t):
 class Index:
     """Host handle + uploaded device block of K_N(B)."""
 
-    def __init__(self, N: int, B: int, tile_dim: int = 0, device="cuda", upload=True, box: bool = False):
-        """box=False: the hyperbolic cross prod(1 + k_l) <= B; box=True: {0..B}^N."""
+    def __init__(self, N: int, B: int, tile_dim: int = 0, device="cuda", upload=True, box: bool = False,
+                 total_degree: bool = False):
+        """The hyperbolic cross prod(1 + k_l) <= B; with box=True the box {0..B}^N; with
+        total_degree=True the set |k|_1 <= B."""
         h = _vp()
-        (hs_index_create_box if box else hs_index_create)(N, B, tile_dim, C.byref(h))
+        make = hs_index_create_box if box else (hs_index_create_total_degree if total_degree else hs_index_create)
+        make(N, B, tile_dim, C.byref(h))
         self.h, self.N, self.B, self.box = h, N, B, box
         n = C.c_int64()
         hs_index_size(h, C.byref(n))

@@ -1,0 +1,109 @@
+"""Index sets other than the hyperbolic cross on the GPU: total-degree sets
+{|k|_1 <= D} in the tiled layout, against the oracle's fast operator on the same set
+(fused and generic potentials, every prefix/suffix split), Lanczos steps and the
+fourth-order operator on them, and the symmetrised form refused there."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.index import TotalDegreeIndex
+from oracle.operators import Potential, fast_apply_H, torsional_potential
+from oracle.propagate import lanczos_expm, magnus4_operator
+from synth import coherent_state, complex_normal_by_index
+from tests.hsutil import hh_workload, lib_terms, oracle_W, rel2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hs():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1403_3511_amd import hs as _hs
+    return _hs
+
+
+def _setup(hs, N, D, d, kind):
+    ix = TotalDegreeIndex(N, D)
+    if kind == "hh":
+        tt = hh_workload(N, 0.111, 0.05)
+        W_at = lambda t: oracle_W(N, tt, t)  # noqa: E731
+        pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    else:
+        W = torsional_potential(N)
+        W_at = lambda t: W  # noqa: E731
+        pot = hs.Pot(N, [(float(c), a) for c, a in W.terms], basis="cheb", scale=W.scale)
+    idx = hs.Index(N, D, d, total_degree=True)
+    pos = ix.rank(idx.multi_indices().astype(np.int64))
+    return ix, W_at, pot, idx, pos
+
+
+@pytest.mark.parametrize("N,D,d,kind", [(2, 60, 0, "hh"), (3, 30, 0, "hh"), (3, 30, 1, "hh"), (4, 16, 3, "hh"),
+                                        (4, 16, 4, "hh"), (6, 9, 0, "hh"), (3, 24, 0, "torsional")])
+def test_apply_on_total_degree_set(hs, N, D, d, kind):
+    import torch
+    ix, W_at, pot, idx, pos = _setup(hs, N, D, d, kind)
+    assert pot.fused == (kind == "hh")
+    pot.set_time(0.3)
+    c = complex_normal_by_index(ix.k, 60 + N)
+    y_ref = fast_apply_H(ix, W_at(0.3), c)
+    cl = torch.from_numpy(np.ascontiguousarray(c[pos])).to("cuda")
+    yl = torch.empty_like(cl)
+    hs.apply_h(idx, pot, cl, yl)
+    torch.cuda.synchronize()
+    y = np.empty_like(c)
+    y[pos] = yl.cpu().numpy()
+    assert rel2(y, y_ref) <= 1e-12
+
+
+def test_steps_and_magnus4_on_total_degree_set(hs):
+    import torch
+    N, D, m, h, n = 3, 30, 8, 0.02, 4
+    ix, W_at, pot, idx, pos = _setup(hs, N, D, 0, "hh")
+    c0 = coherent_state(ix.k, [0.8, -0.4, 0.3])
+    c0 /= np.linalg.norm(c0)
+    ref = c0.copy()
+    t = 0.0
+    for _ in range(n):
+        W = W_at(t + 0.5 * h)
+        ref = lanczos_expm(lambda v: fast_apply_H(ix, W, v), ref, h, m)[0]
+        t += h
+    c = torch.from_numpy(np.ascontiguousarray(c0[pos])).to("cuda")
+    t = 0.0
+    for _ in range(n):
+        hs.step(idx, pot, c, t, h, m)
+        t += h
+    torch.cuda.synchronize()
+    got = np.empty_like(c0)
+    got[pos] = c.cpu().numpy()
+    assert rel2(got, ref) <= 1e-11
+    # fourth-order operator (fused passes) on the same set
+    c1, c2 = 0.5 - math.sqrt(3.0) / 6.0, 0.5 + math.sqrt(3.0) / 6.0
+    hh = 0.5
+    W1, W2 = W_at(0.4 + c1 * hh), W_at(0.4 + c2 * hh)
+    v = complex_normal_by_index(ix.k, 71)
+    y_ref = magnus4_operator(lambda x: fast_apply_H(ix, W1, x), lambda x: fast_apply_H(ix, W2, x), hh)(v)
+    d1, d2 = pot.blocks2()
+    hs.hs_pot_set_time(pot.h, hs.ptr(d1), 0.4 + c1 * hh, None, hs.stream_ptr())
+    hs.hs_pot_set_time(pot.h, hs.ptr(d2), 0.4 + c2 * hh, None, hs.stream_ptr())
+    vl = torch.from_numpy(np.ascontiguousarray(v[pos])).to("cuda")
+    yl = torch.empty_like(vl)
+    hs.apply_magnus4(idx, pot, hh, vl, yl)
+    torch.cuda.synchronize()
+    y = np.empty_like(v)
+    y[pos] = yl.cpu().numpy()
+    assert rel2(y, y_ref) <= 1e-12
+
+
+def test_symmetrised_form_refused_off_the_hyperbolic_cross(hs):
+    import torch
+    idx = hs.Index(3, 10, total_degree=True)
+    tt = hh_workload(3, 0.111, 0.05)
+    pot = hs.Pot(3, lib_terms(tt), subtract_harmonic=True)
+    pot.set_form(hs.HS_FORM_SYM)
+    x = torch.zeros(idx.size, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    with pytest.raises(hs.HSError) as e:
+        hs.apply_h(idx, pot, x, y)
+    assert e.value.code == -5

@@ -77,6 +77,32 @@ def test_box_index_matches_full_box(hs, N, K, d):
         assert [tuple(s) for s in blk[:, N - dd:]] == sorted(tuple(s) for s in blk[:, N - dd:])
 
 
+@pytest.mark.parametrize("N,D,d", [(1, 9, 0), (2, 12, 0), (3, 8, 1), (3, 8, 2), (4, 7, 0), (4, 7, 4), (6, 6, 0)])
+def test_total_degree_index_matches_oracle(hs, N, D, d):
+    """Total-degree sets: the rows are exactly {|k|_1 <= D}; tiles share prefixes; a tile
+    with prefix p holds the first C(d + D - |p|, d) suffixes of the list graded by
+    (|s|_1, lex)."""
+    import math
+    from oracle.index import TotalDegreeIndex
+    idx = hs.Index(N, D, d, upload=False, total_degree=True)
+    ref = TotalDegreeIndex(N, D)
+    assert idx.size == ref.size == math.comb(N + D, N)
+    k = idx.multi_indices().astype(np.int64)
+    assert sorted(map(tuple, k)) == sorted(map(tuple, ref.k.astype(np.int64)))
+    dd = idx.tile_dim
+    pre = [tuple(p) for p in k[:, :N - dd]]
+    glob = sorted({(int(s.sum()), tuple(s)) for s in k[:, N - dd:]})
+    i = 0
+    while i < len(pre):
+        j = i
+        while j < len(pre) and pre[j] == pre[i]:
+            j += 1
+        n = math.comb(dd + D - sum(pre[i]), dd)
+        assert j - i == n
+        assert [tuple(s) for s in k[i:j, N - dd:]] == [g[1] for g in glob[:n]]
+        i = j
+
+
 def test_embedding_into_a_box(hs):
     """hs_index_embed: each row of a hyperbolic set maps to the box row with the same
     multi-index, or to -1 outside a smaller box."""

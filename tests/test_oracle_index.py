@@ -94,3 +94,22 @@ def test_ranker_on_random_members():
             k2 = k.copy()
             k2[-1] += 1
             assert r.rank(k2)[0] - r.rank(k)[0] == 1
+
+
+def test_total_degree_index():
+    """|{|k|_1 <= D}| = C(N + D, N); downward closed; neighbour maps consistent."""
+    import math
+    from oracle.index import TotalDegreeIndex
+    for N, D in [(1, 5), (2, 7), (3, 6), (4, 4)]:
+        ix = TotalDegreeIndex(N, D)
+        assert ix.size == math.comb(N + D, N)
+        k = ix.k.astype(np.int64)
+        assert np.all(k.sum(axis=1) <= D)
+        for l in range(N):
+            p = ix.nbr_plus[l]
+            ok = p >= 0
+            assert np.array_equal(ok, k.sum(axis=1) < D)
+            assert np.all(k[p[ok], l] == k[ok, l] + 1)
+            m = ix.nbr_minus[l]
+            assert np.array_equal(m >= 0, k[:, l] > 0)
+        assert np.array_equal(ix.rank(k), np.arange(ix.size))
