@@ -9,6 +9,8 @@
 // per-axis degree (a polynomial of degree r moves an index by at most r/2 and back, so
 // the padded truncation is not seen by rows of the box).  The diagonal D is applied on
 // every set and cancels in both differences.
+#include <algorithm>
+
 #include "hs_internal.h"
 
 namespace hs {
@@ -23,10 +25,15 @@ __global__ void __launch_bounds__(256) k_zero(int64_t n, double2 *__restrict__ y
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = make_double2(0.0, 0.0);
 }
+// map entries outside [0, nbox) are skipped (the host checks containment; this keeps a
+// wrong map from writing out of bounds)
 __global__ void __launch_bounds__(256)
-k_scatter(int64_t n, const int32_t *__restrict__ map, const double2 *__restrict__ x, double2 *__restrict__ y) {
+k_scatter(int64_t n, const int32_t *__restrict__ map, int64_t nbox, const double2 *__restrict__ x,
+          double2 *__restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[map[i]] = x[i];
+  if (i >= n) return;
+  const int32_t m = map[i];
+  if (m >= 0 && m < nbox) y[m] = x[i];
 }
 // e = a - b (e may alias a)
 __global__ void __launch_bounds__(256)
@@ -37,9 +44,12 @@ k_diff(int64_t n, const double2 *a, const double2 *__restrict__ b, double2 *e) {
   e[i] = make_double2(u.x - w.x, u.y - w.y);
 }
 __global__ void __launch_bounds__(256)
-k_gather(int64_t n, const int32_t *__restrict__ map, const double2 *__restrict__ ybox, double2 *__restrict__ g) {
+k_gather(int64_t n, const int32_t *__restrict__ map, int64_t nbox, const double2 *__restrict__ ybox,
+         double2 *__restrict__ g) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) g[i] = ybox[map[i]];
+  if (i >= n) return;
+  const int32_t m = map[i];
+  g[i] = (m >= 0 && m < nbox) ? ybox[m] : make_double2(0.0, 0.0);
 }
 
 static unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -85,6 +95,14 @@ extern "C" int32_t hs_error_split(hs_index sub, const void *sub_dev, hs_index bo
     return hs::fail(HS_E_INVALID, "hs_error_split: sets and potential differ in N");
   if (pad && pad->kmax < box->kmax) return hs::fail(HS_E_INVALID, "hs_error_split: the padded box is smaller than the box");
   if (pot->form != HS_FORM_PAPER) return hs::fail(HS_E_UNSUPPORTED, "hs_error_split: the paper's operator form only");
+  // the box must contain the set: its largest coordinate is B - 1 (coordinates stay below B)
+  if (sub->B - 1 > box->kmax) return hs::fail(HS_E_INVALID, "hs_error_split: the box does not contain the set");
+  if (pad) {
+    int maxdeg = 0;
+    for (uint16_t a : pot->deg) maxdeg = std::max<int>(maxdeg, a);
+    if (pad->kmax - box->kmax < (maxdeg + 1) / 2)
+      return hs::fail(HS_E_INVALID, "hs_error_split: the padded box must exceed the box by half the largest degree");
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const hs::DiagLayout L = hs::diag_layout(sub, box, pad, pot);
   uint8_t *w8 = static_cast<uint8_t *>(ws);
@@ -95,10 +113,10 @@ extern "C" int32_t hs_error_split(hs_index sub, const void *sub_dev, hs_index bo
   int32_t st;
   // g = W^{GH(K)} v = Omega(F_box Omega_+(v))   (plus D v)
   hipLaunchKernelGGL(hs::k_zero, dim3(hs::nb(box->size)), dim3(256), 0, s, box->size, x);
-  hipLaunchKernelGGL(hs::k_scatter, dim3(hs::nb(n)), dim3(256), 0, s, n, box_map_dev, (const double2 *)v, x);
+  hipLaunchKernelGGL(hs::k_scatter, dim3(hs::nb(n)), dim3(256), 0, s, n, box_map_dev, box->size, (const double2 *)v, x);
   if ((st = hs::launch_apply(box, box_dev, pot, pot_dev, HS_C128, x, y, aws, s, nullptr, nullptr, nullptr, nullptr)) != HS_OK)
     return st;
-  hipLaunchKernelGGL(hs::k_gather, dim3(hs::nb(n)), dim3(256), 0, s, n, box_map_dev, (const double2 *)y, g);
+  hipLaunchKernelGGL(hs::k_gather, dim3(hs::nb(n)), dim3(256), 0, s, n, box_map_dev, box->size, (const double2 *)y, g);
   // E^red = F_K v - g
   if ((st = hs::launch_apply(sub, sub_dev, pot, pot_dev, HS_C128, v, e_red, aws, s, nullptr, nullptr, nullptr, nullptr)) != HS_OK)
     return st;
@@ -107,10 +125,11 @@ extern "C" int32_t hs_error_split(hs_index sub, const void *sub_dev, hs_index bo
   if (pad) {
     // E^quad = Omega(F_pad Omega_+(v)) - g
     hipLaunchKernelGGL(hs::k_zero, dim3(hs::nb(pad->size)), dim3(256), 0, s, pad->size, x);
-    hipLaunchKernelGGL(hs::k_scatter, dim3(hs::nb(n)), dim3(256), 0, s, n, pad_map_dev, (const double2 *)v, x);
+    hipLaunchKernelGGL(hs::k_scatter, dim3(hs::nb(n)), dim3(256), 0, s, n, pad_map_dev, pad->size, (const double2 *)v, x);
     if ((st = hs::launch_apply(pad, pad_dev, pot, pot_dev, HS_C128, x, y, aws, s, nullptr, nullptr, nullptr, nullptr)) != HS_OK)
       return st;
-    hipLaunchKernelGGL(hs::k_gather, dim3(hs::nb(n)), dim3(256), 0, s, n, pad_map_dev, (const double2 *)y, (double2 *)e_quad);
+    hipLaunchKernelGGL(hs::k_gather, dim3(hs::nb(n)), dim3(256), 0, s, n, pad_map_dev, pad->size, (const double2 *)y,
+                       (double2 *)e_quad);
     hipLaunchKernelGGL(hs::k_diff, dim3(hs::nb(n)), dim3(256), 0, s, n, (const double2 *)e_quad, (const double2 *)g,
                        (double2 *)e_quad);
   }

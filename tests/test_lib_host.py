@@ -119,6 +119,22 @@ def test_embedding_into_a_box(hs):
         sub.embed_map(hs.Index(3, 10, upload=False))   # the target must be a box
 
 
+def test_error_split_argument_checks(hs):
+    """Containment and padding are checked on the host before anything runs."""
+    fake = (C.c_double * 64)()
+    fp = C.cast(fake, C.c_void_p)
+    sub = hs.Index(2, 30, upload=False)
+    small = hs.Index(2, 10, upload=False, box=True)
+    box = hs.Index(2, 29, upload=False, box=True)
+    pad2 = hs.Index(2, 31, upload=False, box=True)
+    pot = hs.Pot(2, [(0.1, (8, 0)), (0.2, (0, 2))], basis="cheb", scale=16.0, upload=False)
+    for b, p in ((small, None), (box, pad2)):   # box too small; pad by 2 < 8 / 2
+        with pytest.raises(hs.HSError) as e:
+            hs.hs_error_split(sub.h, fp, b.h, fp, fp, p.h if p else None, fp if p else None,
+                              fp if p else None, pot.h, fp, fp, fp, fp, fp, None)
+        assert e.value.code == -1
+
+
 def test_prefix_tiles_are_initial_segments(hs):
     """A tile with remaining bound b holds the first |K_d(b)| suffixes of the global list."""
     N, B = 5, 400
