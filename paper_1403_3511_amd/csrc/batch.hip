@@ -359,6 +359,15 @@ int32_t batch_matvec(hs_batch_s *b, const uint8_t *bd, const void *x, void *y, c
   return HS_OK;
 }
 
+// the batched kernel evaluates the paper's operator form; a form set on an instance's
+// potential after the batch was created is refused here rather than ignored
+int32_t check_forms(const hs_batch_s *b, const char *who) {
+  for (const hs_pot_s *p : b->pot)
+    if (p->form != HS_FORM_PAPER)
+      return hs::fail(HS_E_UNSUPPORTED, std::string(who) + ": an instance's potential is not in the paper's form");
+  return HS_OK;
+}
+
 }  // namespace
 
 extern "C" int32_t hs_batch_apply_h(hs_batch b, const void *batch_dev, const void *c, void *y,
@@ -366,6 +375,7 @@ extern "C" int32_t hs_batch_apply_h(hs_batch b, const void *batch_dev, const voi
   (void)ws;
   if (!b || !batch_dev || !c || !y) return hs::fail(HS_E_INVALID, "hs_batch_apply_h: NULL argument");
   if (c == y) return hs::fail(HS_E_INVALID, "hs_batch_apply_h: input and output must differ");
+  if (int32_t st = check_forms(b, "hs_batch_apply_h")) return st;
   return batch_matvec(b, static_cast<const uint8_t *>(batch_dev), c, y, nullptr, nullptr, 0,
                       static_cast<hipStream_t>(stream));
 }
@@ -375,6 +385,7 @@ extern "C" int32_t hs_batch_step(hs_batch b, void *batch_dev, double t, double *
   if (!b || !batch_dev || !c || !ws) return hs::fail(HS_E_INVALID, "hs_batch_step: NULL argument");
   if (m < 1 || m > hs::kMaxM) return hs::fail(HS_E_INVALID, "hs_batch_step: m out of range 1..32");
   if (!std::isfinite(h) || (!t_dev && !std::isfinite(t))) return hs::fail(HS_E_NONFINITE, "hs_batch_step: t or h not finite");
+  if (int32_t st = check_forms(b, "hs_batch_step")) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const uint8_t *bd = static_cast<const uint8_t *>(batch_dev);
   hs::StepJob J;

@@ -157,3 +157,31 @@ def test_autotune_and_graph_replay(hs):
         torch.cuda.synchronize()
         assert np.array_equal(xg.cpu().numpy(), eager[i]), f"replay {i}"
     assert torch.equal(y, y_ref)
+
+
+def test_batch_refuses_other_forms_and_sets(hs):
+    """Batches serve the paper's operator form on hyperbolic sets: a symmetrised
+    potential or a box set is refused at creation, and a form set after creation is
+    refused at the next call instead of being ignored."""
+    import torch
+    draws = DRAWS[:2]
+    idxs, pots, ks, cs = make_batch(hs, draws)
+    pots[1].set_form(hs.HS_FORM_SYM)
+    with pytest.raises(hs.HSError) as e:
+        hs.Batch(idxs, pots)
+    assert e.value.code == -5
+    pots[1].set_form(hs.HS_FORM_PAPER)
+    box = hs.Index(draws[0]["N"], 6, box=True)
+    with pytest.raises(hs.HSError):
+        hs.Batch([box], pots[:1])
+    b = hs.Batch(idxs, pots)
+    x = pack(b, cs)
+    y = torch.empty_like(x)
+    b.apply_h(x, y)
+    pots[0].set_form(hs.HS_FORM_SYM)
+    with pytest.raises(hs.HSError) as e:
+        b.apply_h(x, y)
+    assert e.value.code == -5
+    pots[0].set_form(hs.HS_FORM_PAPER)
+    b.apply_h(x, y)
+    torch.cuda.synchronize()

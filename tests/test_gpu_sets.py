@@ -107,3 +107,32 @@ def test_symmetrised_form_refused_off_the_hyperbolic_cross(hs):
     with pytest.raises(hs.HSError) as e:
         hs.apply_h(idx, pot, x, y)
     assert e.value.code == -5
+
+
+@pytest.mark.parametrize("kind,N,n", [("total_degree", 3, 0), ("total_degree", 4, 1), ("box", 2, 0), ("box", 3, 1)])
+def test_degenerate_sets(hs, kind, N, n):
+    """One-row and (N + 1)-row total-degree sets, the one-point box and the 2^N box: H,
+    a Lanczos step and the fourth-order operator against the oracle."""
+    import torch
+    from oracle.index import BoxIndex
+    ix = TotalDegreeIndex(N, n) if kind == "total_degree" else BoxIndex(N, n)
+    tt = hh_workload(N, 0.111, 0.05)
+    W = oracle_W(N, tt, 0.2)
+    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    pot.set_time(0.2)
+    idx = hs.Index(N, n, total_degree=(kind == "total_degree"), box=(kind == "box"))
+    assert idx.size == ix.size
+    pos = ix.rank(idx.multi_indices().astype(np.int64))
+    c = complex_normal_by_index(ix.k, 5)
+    cl = torch.from_numpy(np.ascontiguousarray(c[pos])).to("cuda")
+    yl = torch.empty_like(cl)
+    hs.apply_h(idx, pot, cl, yl)
+    hs.step(idx, pot, cl, 0.0, 0.01, 4)
+    torch.cuda.synchronize()
+    y = np.empty_like(c)
+    y[pos] = yl.cpu().numpy()
+    assert rel2(y, fast_apply_H(ix, W, c)) <= 1e-12
+    ref = lanczos_expm(lambda v: fast_apply_H(ix, oracle_W(N, tt, 0.005), v), c, 0.01, 4)[0]
+    got = np.empty_like(c)
+    got[pos] = cl.cpu().numpy()
+    assert rel2(got, ref) <= 1e-11
