@@ -95,3 +95,20 @@ def test_steps_with_device_interpolation(hs):
     got = np.empty_like(c0)
     got[lexpos] = c.cpu().numpy()
     assert rel2(got, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("N,R,D", [(2, 0, 0), (3, 1, 0), (1, 4, 2)])
+def test_interp_smallest_grids(hs, N, R, D):
+    """One point per axis (R = 0: the constant W(0)), degree 0 output, and a
+    total-degree cut below R."""
+    import torch
+    geom = _geom(N)
+    P = draw_surrogate_params(3, seed=900 + N)
+    out = hs.cheb_interp(geom, torch.from_numpy(P).to("cuda"), D, R, 3.0)
+    torch.cuda.synchronize()
+    rset = hs.cheb_degrees(N, D, R)
+    for s in range(3):
+        ref = cheb_interpolate(_W(geom, P[s]), N, R, 3.0, rset)
+        assert np.max(np.abs(out.cpu().numpy()[s] - ref)) <= 1e-14 * max(1.0, np.max(np.abs(ref)))
+        if R == 0:
+            assert abs(ref[0] - _W(geom, P[s])(np.zeros((1, N)))[0]) < 1e-15

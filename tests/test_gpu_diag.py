@@ -107,3 +107,19 @@ def test_fig9_n4_column(hs, Kp):
           f"Ered {nr:.4e} (paper {table[('Ered', Kp, 4)]:.3e})")
     assert nq == pytest.approx(table[("Equad", Kp, 4)], rel=2e-3)
     assert nr == pytest.approx(table[("Ered", Kp, 4)], rel=2e-3)
+
+
+def test_error_split_on_the_box_itself(hs):
+    """With the set equal to the box, the index-set reduction error vanishes exactly
+    (the same fast algorithm on the same rows)."""
+    import torch
+    N, K = 2, 12
+    W = torsional_potential(N)
+    pot = _lib_pot(hs, W)
+    box = hs.Index(N, K, box=True)
+    pad = hs.Index(N, K + 4, box=True)
+    v = torch.from_numpy(complex_normal_by_index(box.multi_indices(), 3)).to("cuda")
+    eq, er = hs.error_split(box, box, pad, pot, v)
+    torch.cuda.synchronize()
+    assert float(er.abs().max()) == 0.0
+    assert float(eq.abs().max()) > 0.0

@@ -300,3 +300,34 @@ def test_constant_potential_equals_midpoint_step(hs):
     hs.step_magnus4(idx, pot, b, 0.0, h, m, reorth=True)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("case", ["m1", "h0", "zero"])
+def test_degenerate_steps(hs, case):
+    """m = 1 (c <- exp(-i h alpha_0) c), h = 0 (the identity) and the zero vector
+    (m_eff = 0, c stays 0) through the fourth-order step, against the oracle."""
+    import torch
+    N, B = 3, 120
+    tt = hh_workload(N, 0.111, 0.05)
+    ix = IndexSet(N, B)
+    c0 = coherent_state(ix.k, [0.5, 0.2, -0.1])
+    c0 /= np.linalg.norm(c0)
+    if case == "zero":
+        c0 = np.zeros_like(c0)
+    m, h = (1, 0.05) if case == "m1" else (6, 0.0 if case == "h0" else 0.05)
+    ref, meffs = propagate(ix, lambda t: oracle_W(N, tt, t), lambda W: (lambda v: fast_apply_H(ix, W, v)),
+                           c0, 0.0, h, 1, m, scheme=4)
+    idx = hs.Index(N, B)
+    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    c, lexpos = _to_lib(idx, N, B, c0)
+    diag = torch.full((1 + 2 * m,), -1.0, dtype=torch.float64, device="cuda")
+    hs.step_magnus4(idx, pot, c, 0.0, h, m, diag=diag)
+    torch.cuda.synchronize()
+    got = _from_lib(c, lexpos)
+    assert int(diag[0].item()) == meffs[0]
+    if case == "zero":
+        assert np.max(np.abs(got)) == 0.0
+    elif case == "h0":
+        assert rel2(got, c0) <= 1e-14
+    else:
+        assert rel2(got, ref) <= 1e-12

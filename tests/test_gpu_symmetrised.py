@@ -142,3 +142,22 @@ def test_symmetry_at_bench_size(hs):
         out[form] = abs(lhs - rhs) / abs(lhs)
     assert out[hs.HS_FORM_SYM] <= 1e-13
     assert out[hs.HS_FORM_PAPER] > 1e3 * max(out[hs.HS_FORM_SYM], 1e-16)
+
+
+def test_one_axis_and_no_coupling_equal_the_paper_form(hs):
+    """N = 1, and a potential without coupling terms: both forms are the same operator,
+    and the kernel returns the same values."""
+    import torch
+    for N, terms in [(1, [(0.05, (3,)), (0.1, (1,)), (0.2, (2,))]),
+                     (3, [(0.05, (3, 0, 0)), (-0.02, (0, 0, 3)), (0.1, (0, 1, 0))])]:
+        idx = hs.Index(N, 200)
+        pot = hs.Pot(N, terms)
+        assert pot.fused
+        g = torch.Generator(device="cuda").manual_seed(1)
+        x = torch.randn(idx.size, dtype=torch.complex128, device="cuda", generator=g)
+        ya, yb = torch.empty_like(x), torch.empty_like(x)
+        hs.apply_h(idx, pot, x, ya)
+        pot.set_form(hs.HS_FORM_SYM)
+        hs.apply_h(idx, pot, x, yb)
+        torch.cuda.synchronize()
+        assert float(torch.linalg.norm(ya - yb) / torch.linalg.norm(ya)) <= 1e-15
