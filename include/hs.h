@@ -58,6 +58,7 @@ extern "C" {
 #define HS_SET_HYPERBOLIC 0   /* prod(1 + k_l) <= B (paper Sec. 1.2)                       */
 #define HS_SET_BOX 1          /* {0..K}^N (K_full)                                          */
 #define HS_SET_TOTAL_DEGREE 2 /* |k|_1 <= D                                                 */
+#define HS_SET_LIST 3         /* an explicit downward-closed set                            */
 
 #define HS_FORM_PAPER 0 /* the fast operator F: factors applied axis N first (eq. Horner)   */
 #define HS_FORM_SYM 1   /* its symmetric part D + (F + F_rev)/2 (see hs_pot_set_form)     */
@@ -102,6 +103,15 @@ int32_t hs_index_create_box(int32_t N, int64_t Kmax, int32_t tile_dim, hs_index 
  * in the same tiled layout (suffixes graded by |s|_1).  D <= 65535, fewer than 2^31
  * rows.  Every H application and step accepts them in the paper's operator form.    */
 int32_t hs_index_create_total_degree(int32_t N, int64_t D, int32_t tile_dim, hs_index *out);
+/* Any downward-closed set, given as n distinct multi-indices (host, n x N uint16, any
+ * order; the library keeps them in lexicographic order, see hs_index_multi_indices).
+ * The paper's method needs only that k - e_l lies in the set whenever k does and
+ * k_l > 0 (Sec. 1.2); the call checks this and returns HS_E_INVALID otherwise (also
+ * for repeated rows).  Such sets have no common suffix structure, so the layout makes
+ * every axis a prefix axis (one row per tile, neighbours through the tile table) and
+ * the H application runs the generic row kernels: the same operator, without the
+ * specialised gathers.  Paper's operator form only.                                 */
+int32_t hs_index_create_from_list(int32_t N, int64_t n, const uint16_t *k_host, hs_index *out);
 /* map_host[r] = the row of box that holds row r's multi-index of sub (sub->size int32),
  * -1 when it lies outside the box.  HS_E_UNSUPPORTED when box is not a box set.      */
 int32_t hs_index_embed(hs_index sub, hs_index box, int32_t *map_host);

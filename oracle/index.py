@@ -183,3 +183,28 @@ class TotalDegreeIndex:
 
     def rank(self, k: np.ndarray) -> np.ndarray:
         return np.array([self._pos[tuple(int(x) for x in row)] for row in np.atleast_2d(k)], dtype=np.int64)
+
+
+class ListIndex:
+    """An explicit downward-closed set given by its rows (sorted lexicographically here),
+    with neighbour maps and rank, same interface as IndexSet."""
+
+    def __init__(self, rows: np.ndarray):
+        rows = np.asarray(rows, dtype=np.int64)
+        order = np.lexsort(rows.T[::-1])
+        self.k = rows[order].astype(np.uint16)
+        self.size, self.N = self.k.shape
+        self._pos = {tuple(int(x) for x in row): i for i, row in enumerate(self.k)}
+        self.nbr_plus = np.full((self.N, self.size), -1, dtype=np.int64)
+        self.nbr_minus = np.full((self.N, self.size), -1, dtype=np.int64)
+        for i, row in enumerate(self.k):
+            for l in range(self.N):
+                m = [int(x) for x in row]
+                m[l] += 1
+                self.nbr_plus[l, i] = self._pos.get(tuple(m), -1)
+                m[l] -= 2
+                if m[l] >= 0:
+                    self.nbr_minus[l, i] = self._pos.get(tuple(m), -1)
+
+    def rank(self, k: np.ndarray) -> np.ndarray:
+        return np.array([self._pos[tuple(int(x) for x in row)] for row in np.atleast_2d(k)], dtype=np.int64)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -95,8 +96,10 @@ constexpr int kLongTile = 32;    // tiles at least this long go to the long-tile
 struct hs_index_s {
   int32_t N = 0, d = 0, np = 0;
   int64_t B = 0, size = 0, ntiles = 0, ng = 0;
-  int32_t kind = HS_SET_HYPERBOLIC;   // HS_SET_BOX: {0..kmax}^N; HS_SET_TOTAL_DEGREE: |k|_1 <= deg
+  int32_t kind = HS_SET_HYPERBOLIC;   // HS_SET_BOX: {0..kmax}^N; HS_SET_TOTAL_DEGREE: |k|_1 <= deg;
+                                      // HS_SET_LIST: an explicit downward-closed set
   int64_t kmax = 0, deg = 0;
+  std::shared_ptr<struct ListSet> list;  // HS_SET_LIST rows (index.cpp)
   std::vector<uint16_t> tpfx;
   std::vector<int64_t> tstart;
   std::vector<int32_t> tlen, tnbr, tpsum;

@@ -9,10 +9,28 @@
 // move along a prefix axis keeps the offset inside the tile.
 #include <algorithm>
 #include <memory>
+#include <string>
+#include <unordered_map>
 #include <cstring>
 #include <new>
 
 #include "hs_internal.h"
+
+// An explicit downward-closed set (HS_SET_LIST) is laid out with every axis a prefix
+// axis: one row per tile, the empty suffix, moves through the tile neighbour table.
+struct ListSet {
+  int N = 0;
+  std::vector<uint16_t> k;                         // rows, lexicographic
+  std::unordered_map<std::string, int64_t> pos;    // key -> row
+  static std::string key(const int32_t *m, int n) {
+    std::string s((size_t)n * 2, '\0');
+    for (int i = 0; i < n; ++i) {
+      s[2 * i] = (char)(m[i] & 0xFF);
+      s[2 * i + 1] = (char)((m[i] >> 8) & 0xFF);
+    }
+    return s;
+  }
+};
 
 namespace {
 
@@ -186,10 +204,13 @@ struct SetOps {
   int kind = HS_SET_HYPERBOLIC;
   int64_t B = 0, K = 0, D = 0;
   std::unique_ptr<Counter> C;
-  SetOps(int kind_, int64_t B_, int64_t K_, int64_t D_, int N) : kind(kind_), B(B_), K(K_), D(D_) {
+  const ListSet *L = nullptr;
+  SetOps(int kind_, int64_t B_, int64_t K_, int64_t D_, int N, const ListSet *L_ = nullptr)
+      : kind(kind_), B(B_), K(K_), D(D_), L(L_) {
     if (kind == HS_SET_HYPERBOLIC) C.reset(new Counter(B, N));
   }
   int64_t count(int n) const {
+    if (kind == HS_SET_LIST) return n == 0 ? 1 : (int64_t)L->pos.size();
     if (kind == HS_SET_HYPERBOLIC) return C->count(n, B);
     if (kind == HS_SET_TOTAL_DEGREE) return simplex_count(n, D);
     int64_t r = 1;
@@ -197,6 +218,12 @@ struct SetOps {
     return r;
   }
   bool member(const int32_t *k, int n) const {
+    if (kind == HS_SET_LIST) {
+      if (n == 0) return true;
+      for (int i = 0; i < n; ++i)
+        if (k[i] < 0 || k[i] > 65535) return false;
+      return L->pos.count(ListSet::key(k, n)) > 0;
+    }
     if (kind == HS_SET_HYPERBOLIC) return ::member(k, n, B);
     int64_t sum = 0;
     for (int i = 0; i < n; ++i) {
@@ -206,12 +233,25 @@ struct SetOps {
     return kind == HS_SET_BOX || sum <= D;
   }
   template <class F> void each(int n, F &&f) const {
+    if (kind == HS_SET_LIST) {
+      std::vector<int32_t> m(n);
+      if (n == 0) {
+        f(m.data());
+        return;
+      }
+      const int64_t rows = (int64_t)L->pos.size();
+      for (int64_t r = 0; r < rows; ++r) {
+        for (int i = 0; i < n; ++i) m[i] = L->k[(size_t)r * n + i];
+        f(m.data());
+      }
+      return;
+    }
     if (kind == HS_SET_BOX) enumerate_box(n, K, f);
     else if (kind == HS_SET_TOTAL_DEGREE) enumerate_simplex(n, D, f);
     else enumerate(n, B, f);
   }
   int64_t grade(const int32_t *s, int d) const {
-    if (kind == HS_SET_BOX) return 0;
+    if (kind == HS_SET_BOX || kind == HS_SET_LIST) return 0;
     int64_t g = kind == HS_SET_HYPERBOLIC ? 1 : 0;
     for (int a = 0; a < d; ++a) g = kind == HS_SET_HYPERBOLIC ? g * (1 + s[a]) : g + s[a];
     return g;
@@ -219,7 +259,7 @@ struct SetOps {
   int64_t max_grade() const { return kind == HS_SET_HYPERBOLIC ? B : (kind == HS_SET_TOTAL_DEGREE ? D : 0); }
   // largest suffix grade that fits after prefix p
   int64_t budget(const int32_t *p, int np) const {
-    if (kind == HS_SET_BOX) return 0;
+    if (kind == HS_SET_BOX || kind == HS_SET_LIST) return 0;
     if (kind == HS_SET_TOTAL_DEGREE) {
       int64_t sum = 0;
       for (int i = 0; i < np; ++i) sum += p[i];
@@ -240,6 +280,7 @@ struct Ranker {
     if (S->kind == HS_SET_HYPERBOLIC) R.reset(new LexRank(S->C.get(), n, S->B));
   }
   int64_t rank(const int32_t *k) const {
+    if (S->kind == HS_SET_LIST) return n == 0 ? 0 : S->L->pos.at(ListSet::key(k, n));
     if (S->kind == HS_SET_HYPERBOLIC) return R->rank(k);
     int64_t r = 0;
     if (S->kind == HS_SET_BOX) {
@@ -298,7 +339,7 @@ static int32_t default_tile_dim(int32_t N) { return N <= 2 ? N : (N <= 4 ? 2 : (
 static int32_t build_index(hs_index_s *ix) {
   const int N = ix->N, d = ix->d, np = ix->np;
   const int64_t B = ix->B;
-  const SetOps S(ix->kind, B, ix->kmax, ix->deg, N);
+  const SetOps S(ix->kind, B, ix->kmax, ix->deg, N, ix->list.get());
   const int64_t total = S.count(N);
   if (total >= (INT64_C(1) << 31) - 1) return hs::fail(HS_E_OVERFLOW, "index set has 2^31 or more rows");
   const int64_t ntiles = S.count(np);
@@ -396,7 +437,7 @@ static int32_t build_index(hs_index_s *ix) {
     for (int64_t r = ix->tstart[t]; r < ix->tstart[t + 1]; ++r) ix->rowtile[r] = (int32_t)t;
 
   // ---- suffix stencil (displacements used by the fused two-axis kernel) ----
-  ix->ns = 6 * d + 8 * (d - 1);
+  ix->ns = d > 0 ? 6 * d + 8 * (d - 1) : 0;
   ix->gst.assign((size_t)ix->ns * ng, -1);
   if (d > 0) {
     Ranker R(&S, d);
@@ -626,6 +667,67 @@ extern "C" int32_t hs_index_create_total_degree(int32_t N, int64_t D, int32_t ti
     st = build_index(ix);
   } catch (const std::bad_alloc &) {
     st = hs::fail(HS_E_NOMEM, "hs_index_create_total_degree: out of host memory");
+  }
+  if (st != HS_OK) {
+    delete ix;
+    return st;
+  }
+  *out = ix;
+  return HS_OK;
+}
+
+extern "C" int32_t hs_index_create_from_list(int32_t N, int64_t n, const uint16_t *k_host, hs_index *out) {
+  if (!out) return hs::fail(HS_E_INVALID, "hs_index_create_from_list: out is NULL");
+  *out = nullptr;
+  if (N < 1 || N > HS_NMAX) return hs::fail(HS_E_INVALID, "hs_index_create_from_list: N out of range 1..16");
+  if (n < 1 || !k_host) return hs::fail(HS_E_INVALID, "hs_index_create_from_list: empty list");
+  if (n >= (INT64_C(1) << 31) - 1) return hs::fail(HS_E_OVERFLOW, "hs_index_create_from_list: 2^31 or more rows");
+  hs_index_s *ix = new (std::nothrow) hs_index_s();
+  if (!ix) return hs::fail(HS_E_NOMEM, "hs_index_create_from_list: out of host memory");
+  int32_t st = HS_OK;
+  try {
+    std::unique_ptr<ListSet> L(new ListSet());
+    L->N = N;
+    // lexicographic order of the rows
+    std::vector<int64_t> order(n);
+    for (int64_t r = 0; r < n; ++r) order[r] = r;
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+      return std::lexicographical_compare(k_host + a * N, k_host + (a + 1) * N, k_host + b * N, k_host + (b + 1) * N);
+    });
+    L->k.resize((size_t)n * N);
+    std::vector<int32_t> m(N);
+    int64_t maxc = 0;
+    for (int64_t r = 0; r < n && st == HS_OK; ++r) {
+      for (int i = 0; i < N; ++i) {
+        m[i] = k_host[order[r] * N + i];
+        L->k[(size_t)r * N + i] = (uint16_t)m[i];
+        maxc = std::max<int64_t>(maxc, m[i]);
+      }
+      if (!L->pos.emplace(ListSet::key(m.data(), N), r).second)
+        st = hs::fail(HS_E_INVALID, "hs_index_create_from_list: a multi-index appears twice");
+    }
+    // downward closed: k - e_l is in the set whenever k_l > 0
+    for (int64_t r = 0; r < n && st == HS_OK; ++r) {
+      for (int i = 0; i < N; ++i) m[i] = L->k[(size_t)r * N + i];
+      for (int i = 0; i < N && st == HS_OK; ++i) {
+        if (m[i] == 0) continue;
+        --m[i];
+        if (!L->pos.count(ListSet::key(m.data(), N)))
+          st = hs::fail(HS_E_INVALID, "hs_index_create_from_list: the set is not downward closed");
+        ++m[i];
+      }
+    }
+    if (st == HS_OK) {
+      ix->N = N;
+      ix->kind = HS_SET_LIST;
+      ix->B = maxc + 1;  // coordinates stay below B
+      ix->d = 0;         // every axis a prefix axis: one row per tile
+      ix->np = N;
+      ix->list = std::move(L);
+      st = build_index(ix);
+    }
+  } catch (const std::bad_alloc &) {
+    st = hs::fail(HS_E_NOMEM, "hs_index_create_from_list: out of host memory");
   }
   if (st != HS_OK) {
     delete ix;

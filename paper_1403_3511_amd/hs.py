@@ -45,6 +45,7 @@ _SIGS = {
     "hs_index_create_box": [_i32, _i64, _i32, C.POINTER(_vp)],
     "hs_index_embed": [_vp, _vp, _pi32],
     "hs_index_create_total_degree": [_i32, _i64, _i32, C.POINTER(_vp)],
+    "hs_index_create_from_list": [_i32, _i64, _pu16, C.POINTER(_vp)],
     "hs_error_split_workspace_bytes": [_vp, _vp, _vp, _vp, _pi64],
     "hs_error_split": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "hs_pot_create": [_i32, _i32, _f64, _i32, _pu16, _pf64, _pf64, _pf64, _pf64, _i32, C.POINTER(_vp)],
@@ -156,13 +157,18 @@ def ptr(t):
 class Index:
     """Host handle + uploaded device block of K_N(B)."""
 
-    def __init__(self, N: int, B: int, tile_dim: int = 0, device="cuda", upload=True, box: bool = False,
-                 total_degree: bool = False):
+    def __init__(self, N: int, B: int = 0, tile_dim: int = 0, device="cuda", upload=True, box: bool = False,
+                 total_degree: bool = False, rows=None):
         """The hyperbolic cross prod(1 + k_l) <= B; with box=True the box {0..B}^N; with
-        total_degree=True the set |k|_1 <= B."""
+        total_degree=True the set |k|_1 <= B; with rows (n x N integers) that explicit
+        downward-closed set."""
         h = _vp()
-        make = hs_index_create_box if box else (hs_index_create_total_degree if total_degree else hs_index_create)
-        make(N, B, tile_dim, C.byref(h))
+        if rows is not None:
+            k = np.ascontiguousarray(np.asarray(rows, dtype=np.uint16).reshape(-1, N))
+            hs_index_create_from_list(N, k.shape[0], k.ctypes.data_as(_pu16), C.byref(h))
+        else:
+            make = hs_index_create_box if box else (hs_index_create_total_degree if total_degree else hs_index_create)
+            make(N, B, tile_dim, C.byref(h))
         self.h, self.N, self.B, self.box = h, N, B, box
         n = C.c_int64()
         hs_index_size(h, C.byref(n))

@@ -16,6 +16,7 @@ import numpy as np
 
 __all__ = [
     "TimeTerm", "henon_heiles_chain", "stretched_hh_cw_laser", "torsional_series", "lex_order",
+    "random_downward_set",
     "complex_normal_by_index", "coherent_state", "decay_vector",
     "batch_instances", "surrogate_geometry", "surrogate_param_box",
     "draw_surrogate_params", "mlp_initial_weights",
@@ -92,6 +93,19 @@ def torsional_series(N: int, L: float = 16.0, R: int = 8):
             a[l] = r
             terms.append((-2.0 * (-1.0) ** (r // 2) * jv(r, 1.0), tuple(a)))
     return terms
+
+
+def random_downward_set(N: int, npoints: int, maxc: int, seed: int) -> np.ndarray:
+    """A seeded downward-closed set: the union of the boxes below npoints random corners
+    (coordinates uniform in 0..maxc), rows in lexicographic order, shape (n, N)."""
+    rng = np.random.default_rng(seed)
+    corners = rng.integers(0, maxc + 1, size=(npoints, N))
+    rows = set()
+    for c in corners:
+        for k in np.ndindex(*(int(x) + 1 for x in c)):
+            rows.add(k)
+    out = np.array(sorted(rows), dtype=np.int64).reshape(-1, N)
+    return out
 
 
 def lex_order(k: np.ndarray) -> np.ndarray:

@@ -136,3 +136,42 @@ def test_degenerate_sets(hs, kind, N, n):
     got = np.empty_like(c)
     got[pos] = cl.cpu().numpy()
     assert rel2(got, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("N,npts,maxc,kind", [(2, 5, 40, "hh"), (3, 8, 20, "hh"), (4, 6, 9, "hh"),
+                                             (3, 8, 20, "torsional")])
+def test_explicit_downward_closed_set(hs, N, npts, maxc, kind):
+    """A random downward-closed set (union of boxes below random corners) given as a list:
+    H against the oracle on the same set, and a Lanczos step."""
+    import torch
+    from oracle.index import ListIndex
+    from synth import random_downward_set
+    rows = random_downward_set(N, npts, maxc, seed=40 + N)
+    ix = ListIndex(rows)
+    if kind == "hh":
+        tt = hh_workload(N, 0.111, 0.05)
+        W_at = lambda t: oracle_W(N, tt, t)  # noqa: E731
+        pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    else:
+        W = torsional_potential(N)
+        W_at = lambda t: W  # noqa: E731
+        pot = hs.Pot(N, [(float(c), a) for c, a in W.terms], basis="cheb", scale=W.scale)
+    idx = hs.Index(N, rows=rows)
+    pos = ix.rank(idx.multi_indices().astype(np.int64))
+    pot.set_time(0.3)
+    c = complex_normal_by_index(ix.k, 80 + N)
+    cl = torch.from_numpy(np.ascontiguousarray(c[pos])).to("cuda")
+    yl = torch.empty_like(cl)
+    hs.apply_h(idx, pot, cl, yl)
+    torch.cuda.synchronize()
+    y = np.empty_like(c)
+    y[pos] = yl.cpu().numpy()
+    assert rel2(y, fast_apply_H(ix, W_at(0.3), c)) <= 1e-12
+    c0 = c / np.linalg.norm(c)
+    ref = lanczos_expm(lambda v: fast_apply_H(ix, W_at(0.005), v), c0, 0.01, 6)[0]
+    cs = torch.from_numpy(np.ascontiguousarray(c0[pos])).to("cuda")
+    hs.step(idx, pot, cs, 0.0, 0.01, 6)
+    torch.cuda.synchronize()
+    got = np.empty_like(c0)
+    got[pos] = cs.cpu().numpy()
+    assert rel2(got, ref) <= 1e-11

@@ -103,6 +103,24 @@ def test_total_degree_index_matches_oracle(hs, N, D, d):
         i = j
 
 
+def test_explicit_downward_closed_sets(hs):
+    """hs_index_create_from_list: the rows come back in lexicographic order, one per tile;
+    a repeated row or a set that is not downward closed is refused."""
+    from synth import random_downward_set
+    k = random_downward_set(4, 6, 7, seed=3)
+    rng = np.random.default_rng(0)
+    shuffled = k[rng.permutation(len(k))]
+    idx = hs.Index(4, rows=shuffled, upload=False)
+    assert idx.size == len(k) == idx.ntiles
+    assert np.array_equal(idx.multi_indices().astype(np.int64), k)
+    with pytest.raises(hs.HSError) as e:
+        hs.Index(4, rows=np.vstack([k, k[:1]]), upload=False)
+    assert e.value.code == -1
+    with pytest.raises(hs.HSError) as e:
+        hs.Index(2, rows=[[0, 0], [0, 2]], upload=False)   # (0, 1) missing
+    assert e.value.code == -1
+
+
 def test_embedding_into_a_box(hs):
     """hs_index_embed: each row of a hyperbolic set maps to the box row with the same
     multi-index, or to -1 outside a smaller box."""
