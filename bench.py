@@ -210,6 +210,8 @@ def main():
             forms["sym"] = sym_form(hs, idx, pot, c0, stream, args, value)
         if "diag" in want:
             forms["diag"] = diag_form(hs, stream, args)
+        if "n10_big" in want:   # opt-in: not in the default list
+            forms["n10_big"] = n10_big_form(hs, stream, args)
 
     cpu = None
     if not args.no_cpu:
@@ -421,6 +423,42 @@ def diag_form(hs, stream, args, reps=5):
         del sub, box, pad, vt, eq, er, maps, ws
     return {"workload": "Fig. 9, N = 4 column: torsional potential (L = 16, Chebyshev degree 8), beta = 5",
             "cases": out, "paper_seconds_at_K75": FIG9_N4_PAPER_SECONDS}
+
+
+def n10_big_form(hs, stream, args, reps=3):
+    """Matvec-only throughput at N = 10, product bound 2^14 (1,064,429,409 rows), chained
+    Henon-Heiles + laser, complex64 and complex128.  Beyond the 32-bit buffer range of the
+    specialised kernels, so the 64-bit row kernels serve it; the input is a normalised
+    constant vector (throughput only: the 64-bit path's parity is tested at 247 million
+    rows).  Opt-in (--form-names n10_big): the host index build takes tens of seconds
+    and about 30 GB of host memory."""
+    import math
+    import torch
+    from synth import henon_heiles_chain
+    N, B = 10, 16384
+    t0 = time.perf_counter()
+    idx = hs.Index(N, B)
+    build_s = time.perf_counter() - t0
+    print(f"n10_big: index of {idx.size} rows built and uploaded in {build_s:.1f} s", file=sys.stderr, flush=True)
+    tt = henon_heiles_chain(N, 0.111, 0.05)
+    pot = hs.Pot(N, [(x[0], x[1], x[2], x[3], x.degrees) for x in tt], subtract_harmonic=True)
+    pot.set_time(0.1)
+    out = {"rows": idx.size, "host_index_build_s": round(build_s, 1)}
+    for name, dt, tdt in (("fp32", hs.HS_C64, torch.complex64), ("fp64", hs.HS_C128, torch.complex128)):
+        x = torch.full((idx.size,), 1.0 / math.sqrt(idx.size), dtype=tdt, device="cuda")
+        y = torch.empty_like(x)
+        ws = hs.workspace(idx, pot, dt, 0)
+        hs.apply_h(idx, pot, x, y, dt, ws)
+        torch.cuda.synchronize()
+        ms = event_time_ms(lambda: hs.apply_h(idx, pot, x, y, dt, ws), reps, stream) / reps
+        S = 8 if dt == hs.HS_C64 else 16
+        print(f"n10_big: {name} {ms:.1f} ms per H application", file=sys.stderr, flush=True)
+        out[name] = {"ms_per_matvec": round(ms, 2), "matvec_per_s": round(1e3 / ms, 3),
+                     "row_matvec_per_s": round(idx.size / (ms * 1e-3), 1),
+                     "alg_gbs": round(2 * S * idx.size / (ms * 1e-3) / 1e9, 1)}
+        del x, y, ws
+    return {"workload": "N=10, product bound 16384 (%d rows), chained HH lambda=0.111 + laser; matvec only" % idx.size,
+            **out}
 
 
 def fp32_n10_form(hs, stream, args):

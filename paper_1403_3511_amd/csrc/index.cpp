@@ -470,7 +470,9 @@ static int32_t build_index(hs_index_s *ix) {
   // records for every tile when they cost at most 96 bytes per row (then the short
   // tiles use them too), else for the long tiles only
   const int64_t nlong = std::count_if(ix->tlen.begin(), ix->tlen.end(), [](int32_t l) { return l >= hs::kLongTile; });
-  ix->recs_all = (int64_t)ix->rstride * 4 * ntiles <= std::max<int64_t>(total * 96, INT64_C(64) << 20);
+  // (at most 8 GB in any case: beyond that the short tiles take the row kernel)
+  ix->recs_all = (int64_t)ix->rstride * 4 * ntiles <= std::min<int64_t>(
+                     std::max<int64_t>(total * 96, INT64_C(64) << 20), INT64_C(8) << 30);
   ix->recs.reserve((size_t)ix->rstride * (ix->recs_all ? ntiles : nlong));
   ix->tile_rec.assign(ix->recs_all ? ntiles : 0, -1);
   for (int64_t t = 0; t < ntiles; ++t) {

@@ -23,15 +23,30 @@
 
 namespace hs {
 
-// Complex loads through a raw buffer resource with 32-bit element offsets: an absent
-// neighbour gets an offset beyond the buffer, for which the hardware returns zero, so
-// no predication or select is needed and no 64-bit address arithmetic is done.
-constexpr uint32_t kAbsent = 0x0FFFFFFFu;  // element offset that is always out of range
+// Complex loads through a structured buffer resource: the element index times the record
+// stride (the complex size), checked against the record count.  An absent neighbour gets
+// an index beyond every vector (kAbsent), for which the hardware returns zero, so no
+// predication or select is needed, and 32-bit indices reach vectors of up to 2^32 - 1
+// elements without 64-bit address arithmetic.
+constexpr uint32_t kAbsent = 0xFFFFFFFFu;  // element index that is always out of range
+
+typedef int hs_v4i __attribute__((ext_vector_type(4)));
+typedef int hs_v2i __attribute__((ext_vector_type(2)));
+__device__ hs_v4i hs_struct_load_b128(__amdgpu_buffer_rsrc_t rsrc, int vindex, int voffset, int soffset,
+                                      int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
+__device__ hs_v2i hs_struct_load_b64(__amdgpu_buffer_rsrc_t rsrc, int vindex, int voffset, int soffset,
+                                     int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
+
+// resource over n complex elements of type V2<T>
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const void *x, int64_t n) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)sizeof(typename V2<T>::t), (int)n, 0x00020000);
+}
 
 template <typename T> struct BufLoad;
 template <> struct BufLoad<double> {
   static __device__ __forceinline__ double2 ld(__amdgpu_buffer_rsrc_t r, uint32_t i) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(i << 4), 0, 0);
+    const hs_v4i v = hs_struct_load_b128(r, (int)i, 0, 0, 0);
     double2 d;
     __builtin_memcpy(&d, &v, 16);
     return d;
@@ -39,7 +54,7 @@ template <> struct BufLoad<double> {
 };
 template <> struct BufLoad<float> {
   static __device__ __forceinline__ float2 ld(__amdgpu_buffer_rsrc_t r, uint32_t i) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(i << 3), 0, 0);
+    const hs_v2i v = hs_struct_load_b64(r, (int)i, 0, 0, 0);
     float2 d;
     __builtin_memcpy(&d, &v, 8);
     return d;
@@ -82,8 +97,7 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
                                        const typename V2<T>::t *__restrict__ prev, T pcoef) {
   using C = typename V2<T>::t;
   constexpr int D = N - NP;
-  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
-      (void *)x, (short)0, (int)(ix.size * (int64_t)sizeof(C)), 0x00020000);
+  const __amdgpu_buffer_rsrc_t xr = vec_rsrc<T>(x, ix.size);
   const uint32_t base = (uint32_t)rec[0];
   const int32_t len = rec[1];
   const T *__restrict__ wt;
@@ -440,9 +454,8 @@ int launch_hh_long_impl(const IndexDev &ix, const double *hh, const void *x, voi
                         const double *out_scale, const void *prev, const double *prev_coef,
                         const double *prev_scale, hipStream_t s, bool x2) {
   if (ix.rstride != rec_stride(ix.np)) return 0;
-  // raw buffer loads take a 32-bit byte size and 32-bit byte offsets: larger sets use the
-  // generic row kernels, which index with 64 bits
-  if (ix.size > (int64_t)(INT32_MAX / (2 * sizeof(T)))) return 0;
+  // row indices are 32-bit and kAbsent must lie beyond every row
+  if (ix.size >= (int64_t)INT32_MAX) return 0;
   const bool small = ix.tile_rec != nullptr;
 #define HS_LONG_CASE(NN, PP)                                                                    \
   case NN * 32 + PP:                                                                            \

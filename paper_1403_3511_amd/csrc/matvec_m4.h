@@ -37,11 +37,8 @@ __device__ __forceinline__ void m4_row(const IndexDev &ix, const double *__restr
   constexpr int NI = MODE == 1 ? 1 : 2;
   auto inp = [](int p) { return MODE == 1 ? 0 : p; };
   __amdgpu_buffer_rsrc_t xr[NI];
-  xr[0] = __builtin_amdgcn_make_buffer_rsrc((void *)x0, (short)0, (int)(ix.size * (int64_t)sizeof(C)),
-                                            0x00020000);
-  if constexpr (NI == 2)
-    xr[NI - 1] = __builtin_amdgcn_make_buffer_rsrc((void *)x1, (short)0,
-                                                   (int)(ix.size * (int64_t)sizeof(C)), 0x00020000);
+  xr[0] = vec_rsrc<T>(x0, ix.size);
+  if constexpr (NI == 2) xr[NI - 1] = vec_rsrc<T>(x1, ix.size);
   const uint32_t base = (uint32_t)rec[0];
   const int32_t len = rec[1];
   const T *__restrict__ wt;
@@ -410,15 +407,15 @@ static void launch_m4_passes(const IndexDev &ix, const double *hh1, const double
 }
 
 // w = M v through the two fused passes (a, d: scratch vectors of |K| elements).  Returns
-// false, launching nothing, when (N, NP) has no specialisation, the set has no
-// short-tile row list, or it exceeds the 32-bit buffer range.
+// false, launching nothing, when (N, NP) has no specialisation or the set has no
+// short-tile row list.
 template <typename T>
 bool launch_m4_impl(const IndexDev &ix, const double *hh1, const double *hh2, const void *v, void *a,
                     void *d, void *w, const double *in_scale, double g2, const void *prev,
                     const double *prev_coef, const double *prev_scale, hipStream_t s, bool x2,
                     bool dl) {
   if (ix.rstride != rec_stride(ix.np)) return false;
-  if (ix.size > (int64_t)(INT32_MAX / (2 * sizeof(T)))) return false;
+  if (ix.size >= (int64_t)INT32_MAX) return false;
   if (ix.tile_rec == nullptr && ix.nsmall > 0) return false;
 #define HS_M4_CASE(NN, PP)                                                                            \
   case NN * 32 + PP:                                                                                  \
