@@ -193,10 +193,6 @@ extern "C" int32_t hs_batch_create(int32_t n, const hs_index *idx, const void *c
         delete b;
         return hs::fail(HS_E_INVALID, "hs_batch_create: instance potential and index differ in N");
       }
-      if (idx[i]->size > (int64_t)(INT32_MAX / 16)) {  // 32-bit buffer offsets of the row kernel
-        delete b;
-        return hs::fail(HS_E_UNSUPPORTED, "hs_batch_create: an instance has 2^27 or more rows");
-      }
       if (idx[i]->kind != HS_SET_HYPERBOLIC) {
         delete b;
         return hs::fail(HS_E_UNSUPPORTED, "hs_batch_create: batches serve hyperbolic sets only");
