@@ -12,7 +12,7 @@
  *     must be 16-byte aligned (256 recommended).
  *   - Work is enqueued on the caller's hipStream_t (passed as void*; NULL means the
  *     default stream).  Nothing synchronises unless its name ends in _sync.
- *   - Handles (hs_index, hs_pot, hs_plan, hs_batch, hs_mlp) are host objects owned by the
+ *   - Handles (hs_index, hs_pot, hs_batch, hs_mlp) are host objects owned by the
  *     library; destroy them with the matching *_destroy call.  A handle may be used by
  *     one thread at a time.
  *   - Complex vectors are interleaved (re, im): complex128 = 2 x float64 (HS_C128) or
@@ -23,6 +23,9 @@
  * i.e. B = K_paper + 1.  H = D + W^pol(X_K) with D = diag(sum_l (k_l + 1/2)) and W the
  * potential minus |x|^2/2 (Sec. 1.2), W^pol(X_K) the formal insertion of the coordinate
  * matrices X_K^(l) (Sec. 3.1-3.2, eq. Horner), axis N applied first, axis 1 last.
+ * Besides the hyperbolic cross, index sets may be boxes, total-degree sets or any
+ * downward-closed set given as a list (HS_SET_*); the operator is defined the same way
+ * on each.
  */
 #ifndef HS_H
 #define HS_H
@@ -78,7 +81,8 @@ const char *hs_version(void);
  * that share the prefix (k_1..k_{N-d}); inside a tile the suffix (k_{N-d+1}..k_N) runs
  * over one global list of K_d(B) sorted by (prod(1+s), lex), so a tile with remaining
  * bound b holds exactly the first |K_d(b)| entries of that list.  tile_dim d in 1..N
- * (0 = library choice).  Requires 1 <= N <= HS_NMAX, 1 <= B <= 65536, |K| < 2^31.   */
+ * (0 = library choice).  Requires 1 <= N <= HS_NMAX, 1 <= B <= 65536, |K| < 2^31.
+ * (Sets given as a list have tile dimension 0: one row per tile.)                   */
 int32_t hs_index_create(int32_t N, int64_t B, int32_t tile_dim, hs_index *out);
 int32_t hs_index_destroy(hs_index idx);
 /* |K|, the number of rows of every vector over this set. */
@@ -183,8 +187,11 @@ int32_t hs_step(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev, in
  *   c_{1,2} = 1/2 -+ sqrt(3)/6.
  * The two coefficient sets live in two device parameter blocks of the same potential
  * (pot_dev1, pot_dev2: distinct buffers of hs_pot_device_bytes bytes, both uploaded
- * with hs_pot_upload; the step overwrites their coefficients).  One application of M
- * costs four H applications and one combination pass.
+ * with hs_pot_upload; the step overwrites their coefficients).  For fused-class
+ * potentials on sets with a specialised kernel, M is applied by two fused passes with
+ * Abar = (A_1 + A_2)/2, Delta = (A_2 - A_1)/2, A_2 A_1 - A_1 A_2 = 2 (Delta Abar - Abar
+ * Delta) (the fast operator is linear in the coefficients); otherwise by four H
+ * applications and one combination pass.
  * hs_magnus4_workspace_bytes(m = 0) sizes the workspace of hs_apply_magnus4, m >= 1
  * that of hs_step_magnus4 (three vectors more than hs_workspace_bytes).
  * hs_apply_magnus4: y = M c with the coefficients currently in the two blocks (c != y).
@@ -220,8 +227,10 @@ int32_t hs_error_split(hs_index sub, const void *sub_dev, hs_index box, const vo
  * Instances are described by handles plus their uploaded device blocks (which must stay
  * alive); vectors of all instances are packed back to back in one device buffer with
  * offsets given by hs_batch_offsets (complex elements, host int64[n+1]).  Supported:
- * fused-class potentials on index sets built with the default tile dimension, N 2..8,
- * fewer than 2^31 rows in total (else HS_E_UNSUPPORTED / HS_E_OVERFLOW).            */
+ * fused-class potentials in the paper's operator form on hyperbolic index sets built
+ * with the default tile dimension, N 2..8, fewer than 2^31 rows in total (else
+ * HS_E_UNSUPPORTED / HS_E_OVERFLOW; a form changed after creation is refused by the
+ * next call).                                                                        */
 int32_t hs_batch_create(int32_t n, const hs_index *idx, const void *const *idx_dev,
                         const hs_pot *pot, void *const *pot_dev, hs_batch *out);
 int32_t hs_batch_destroy(hs_batch b);
@@ -262,6 +271,8 @@ int32_t hs_batch_autotune_sync(hs_batch b, const void *batch_dev, const void *c,
  * eigenvalues of the Hermite Jacobi matrix); one workgroup per sample; asynchronous on
  * the stream.  HS_E_INVALID for sizes out of range.                                  */
 int32_t hs_gh_ncoef(int32_t N, int32_t D, int32_t *ncoef);
+int32_t hs_gh_project(int32_t N, int32_t G, int32_t D, int32_t Q, const double *geometry_host,
+                      int32_t nsamp, const double *params_dev, double *coef_dev, void *stream);
 /* hs_cheb_interp: Chebyshev interpolation of the same Gaussian-well W on the cube
  * [-L, L]^N (paper Sec. 1.3, step (1) of Fig. 4): the tensor interpolant on the
  * (R + 1)^N first-kind Chebyshev points L cos((2k + 1) pi / (2 (R + 1))),
@@ -276,8 +287,6 @@ int32_t hs_gh_ncoef(int32_t N, int32_t D, int32_t *ncoef);
 int32_t hs_cheb_ncoef(int32_t N, int32_t D, int32_t R, int32_t *ncoef);
 int32_t hs_cheb_interp(int32_t N, int32_t G, int32_t D, int32_t R, double L, const double *geometry_host,
                        int32_t nsamp, const double *params_dev, double *coef_dev, void *stream);
-int32_t hs_gh_project(int32_t N, int32_t G, int32_t D, int32_t Q, const double *geometry_host,
-                      int32_t nsamp, const double *params_dev, double *coef_dev, void *stream);
 
 /* MLP in -> hidden -> hidden -> out with SiLU; BF16 operands on MFMA, FP32 accumulate,
  * FP32 master weights and Adam.  in <= 32, hidden a multiple of 64 (<= 512), out <= 512.
