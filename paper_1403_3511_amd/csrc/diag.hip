@@ -89,6 +89,8 @@ extern "C" int32_t hs_error_split(hs_index sub, const void *sub_dev, hs_index bo
     return hs::fail(HS_E_INVALID, "hs_error_split: NULL argument");
   if (pad && (!pad_dev || !pad_map_dev || !e_quad))
     return hs::fail(HS_E_INVALID, "hs_error_split: padded box given without its buffers");
+  if (v == e_red || (pad && (v == e_quad || e_quad == e_red)))
+    return hs::fail(HS_E_INVALID, "hs_error_split: v, e_quad and e_red must be distinct buffers");
   if (box->kind != HS_SET_BOX || (pad && pad->kind != HS_SET_BOX))
     return hs::fail(HS_E_INVALID, "hs_error_split: box and pad must be box sets");
   if (sub->N != pot->N || box->N != pot->N || (pad && pad->N != pot->N))

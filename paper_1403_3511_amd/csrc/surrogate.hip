@@ -353,7 +353,7 @@ constexpr size_t kChLdsBytes = 64 * 1024;   // grid values and the cosine table
 struct ChArgs {
   int N, G, P, grid, ncoef;
   double xk[kChMaxP];              // L cos(theta_k), theta_k = (2k + 1) pi / (2P)
-  int16_t digits[kChMaxCoef];      // requested r, 4 bits per axis (axis 0 highest)
+  uint16_t digits[kChMaxCoef];     // requested r, 4 bits per axis (axis 0 highest)
   double base[kGhMaxG][kGhMaxN], u[kGhMaxG][kGhMaxN], w[kGhMaxG][kGhMaxN], phase[kGhMaxG];
 };
 
@@ -836,7 +836,7 @@ int32_t cheb_launch(int32_t N, int32_t G, int32_t D, int32_t R, double L, const 
     if (sum > D) continue;
     for (int l = 0; l < N; ++l) code |= r[l] << (4 * (N - 1 - l));
     if (nc >= hs::kChMaxCoef) return hs::fail(HS_E_UNSUPPORTED, "Chebyshev interpolation: more than 512 coefficients");
-    A.digits[nc++] = (int16_t)code;
+    A.digits[nc++] = (uint16_t)code;
   }
   A.ncoef = nc;
   for (int k = 0; k < A.P; ++k) A.xk[k] = L * std::cos((2.0 * k + 1.0) * M_PI / (2.0 * A.P));
