@@ -30,6 +30,7 @@ kernel for scaling the byte counters) and exits.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -120,7 +121,9 @@ def main():
     ap.add_argument("--forms", type=int, default=1, help="also measure the FP32 and batched forms")
     ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4,sym,diag",
                     help="comma-separated forms measured when --forms is set")
-    ap.add_argument("--batch-log2-bmax", type=float, default=10.0)
+    ap.add_argument("--batch-log2-bmax", type=float, default=14.0)
+    ap.add_argument("--batch-max-rows", type=int, default=1 << 23,
+                    help="redraw batched instances with more rows than this (0: keep every draw)")
     ap.add_argument("--n10-steps", type=int, default=20, help="steps of the N=10 FP32/FP64 comparison")
     ap.add_argument("--train-steps", type=int, default=3000, help="Adam steps of the learned form")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
@@ -633,14 +636,17 @@ def learned_form(hs, stream, args):
 
 def batched_form(hs, stream, args, nsteps=3):
     """256 instances (N uniform in 3..8, B = floor(2^U(8, log2_bmax)), lambda in
-    [0.05, 0.15], laser-free chained Henon-Heiles), complex normal start vectors: the
-    batched step (persistent launch, graph replay) against the instances stepped one by
-    one with the single-instance path."""
+    [0.05, 0.15], laser-free chained Henon-Heiles; an instance with more than max_rows
+    rows is drawn again), complex normal start vectors: one batched application of H
+    (persistent launch) and the batched step (graph replay), against the instances
+    stepped one by one with the single-instance path."""
     import numpy as np
     import torch
     from synth import batch_instances, henon_heiles_chain
 
-    draws = batch_instances(256, seed=0, log2_bmax=args.batch_log2_bmax)
+    cap = args.batch_max_rows
+    accept = (lambda N, B: hs.index_count(N, B) <= cap) if cap > 0 else None
+    draws = batch_instances(256, seed=0, log2_bmax=args.batch_log2_bmax, accept=accept)
     t0 = time.time()
     idxs, pots = [], []
     for d in draws:
@@ -650,6 +656,7 @@ def batched_form(hs, stream, args, nsteps=3):
     b = hs.Batch(idxs, pots)
     build_s = time.time() - t0
     off = b.offsets
+    rows = sum(int(i.size) for i in idxs)
     gen = torch.Generator(device="cuda")
     c_init = torch.empty(b.total, dtype=torch.complex128, device="cuda")
     for i, d in enumerate(draws):
@@ -660,6 +667,9 @@ def batched_form(hs, stream, args, nsteps=3):
     c = c_init.clone()
     y = torch.empty_like(c)
     b.autotune(c, y)
+    # one batched application of H over all instances
+    b.apply_h(c, y)
+    ms_apply = event_time_ms(lambda: b.apply_h(c, y), 10, stream) / 10
     ws = b.workspace(M_KRYLOV)
     t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     g = capture(lambda: b.step(c, 0.0, H_STEP, M_KRYLOV, ws=ws, t_dev=t_dev), stream)
@@ -669,11 +679,17 @@ def batched_form(hs, stream, args, nsteps=3):
     del g
     # one by one
     singles = [c_init[off[i]:off[i + 1]].clone() for i in range(len(draws))]
-    wss = [hs.workspace(idxs[i], pots[i], hs.HS_C128, M_KRYLOV) for i in range(len(draws))]
+    # the instances run one after another on one stream, so they share one workspace
+    nbmax = 0
+    for i in range(len(draws)):
+        nb = ctypes.c_int64()
+        hs.hs_workspace_bytes(idxs[i].h, pots[i].h, hs.HS_C128, M_KRYLOV, ctypes.byref(nb))
+        nbmax = max(nbmax, nb.value)
+    ws1 = hs.dev_buffer(nbmax)
 
     def all_single(t):
         for i in range(len(draws)):
-            hs.step(idxs[i], pots[i], singles[i], t, H_STEP, M_KRYLOV, ws=wss[i])
+            hs.step(idxs[i], pots[i], singles[i], t, H_STEP, M_KRYLOV, ws=ws1)
 
     t = 0.0
     torch.cuda.synchronize()
@@ -692,10 +708,14 @@ def batched_form(hs, stream, args, nsteps=3):
         d = float(torch.linalg.norm(c[off[i]:off[i + 1]] - ref) / torch.linalg.norm(ref))
         dev_max = max(dev_max, d)
     inst_mv = len(draws) * M_KRYLOV * nsteps
-    return {"workload": "256 instances, N in 3..8, B=floor(2^U(8,%g)), %d rows in total, %d steps"
-                        % (args.batch_log2_bmax, int(b.total), nsteps),
+    apply_gbs = 2 * 16 * rows / (ms_apply / 1e3) / 1e9
+    return {"workload": "256 instances, N in 3..8, B=floor(2^U(8,%g))%s, %d rows in total, %d steps"
+                        % (args.batch_log2_bmax,
+                           ", instances over %d rows drawn again" % cap if cap > 0 else "", rows, nsteps),
+            "apply_ms": round(ms_apply, 4), "apply_row_matvec_per_s": float("%.4g" % (rows / (ms_apply / 1e3))),
+            "apply_algorithmic_gbs": round(apply_gbs, 1), "apply_hbm_frac": round(apply_gbs / HBM_PEAK_GBS, 4),
             "instance_matvec_per_s": round(inst_mv / (ms_b / 1e3), 1),
-            "row_matvec_per_s": float("%.4g" % (b.total * M_KRYLOV * nsteps / (ms_b / 1e3))),
+            "row_matvec_per_s": float("%.4g" % (rows * M_KRYLOV * nsteps / (ms_b / 1e3))),
             "one_by_one_instance_matvec_per_s": round(inst_mv / (ms_s / 1e3), 1),
             "speedup_vs_one_by_one": round(ms_s / ms_b, 3),
             "max_rel_dev_vs_one_by_one": dev_max, "launch": list(b.get_launch()),

@@ -85,6 +85,9 @@ const char *hs_version(void);
  * (Sets given as a list have tile dimension 0: one row per tile.)                   */
 int32_t hs_index_create(int32_t N, int64_t B, int32_t tile_dim, hs_index *out);
 int32_t hs_index_destroy(hs_index idx);
+/* |K_N(B)| without enumerating the set (the same bounds on N and B as hs_index_create;
+ * counts saturate at 2^62).  Host only; for sizing batches and buffers beforehand.   */
+int32_t hs_index_count(int32_t N, int64_t B, int64_t *n);
 /* |K|, the number of rows of every vector over this set. */
 int32_t hs_index_size(hs_index idx, int64_t *n);
 /* tile_dim actually used, number of tiles, length of the global suffix list. */

@@ -615,6 +615,20 @@ extern "C" int32_t hs_index_create(int32_t N, int64_t B, int32_t tile_dim, hs_in
   return HS_OK;
 }
 
+extern "C" int32_t hs_index_count(int32_t N, int64_t B, int64_t *n) {
+  if (!n) return hs::fail(HS_E_INVALID, "hs_index_count: n is NULL");
+  *n = 0;
+  if (N < 1 || N > HS_NMAX) return hs::fail(HS_E_INVALID, "hs_index_count: N out of range 1..16");
+  if (B < 1 || B > 65536) return hs::fail(HS_E_INVALID, "hs_index_count: B out of range 1..65536");
+  try {
+    Counter C(B, N);
+    *n = C.count(N, B);
+  } catch (const std::bad_alloc &) {
+    return hs::fail(HS_E_NOMEM, "hs_index_count: out of host memory");
+  }
+  return HS_OK;
+}
+
 extern "C" int32_t hs_index_create_box(int32_t N, int64_t Kmax, int32_t tile_dim, hs_index *out) {
   if (!out) return hs::fail(HS_E_INVALID, "hs_index_create_box: out is NULL");
   *out = nullptr;

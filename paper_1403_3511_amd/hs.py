@@ -38,6 +38,7 @@ _SIGS = {
     "hs_index_create": [_i32, _i64, _i32, C.POINTER(_vp)],
     "hs_index_destroy": [_vp],
     "hs_index_size": [_vp, _pi64],
+    "hs_index_count": [_i32, _i64, _pi64],
     "hs_index_info": [_vp, _pi32, _pi64, _pi64],
     "hs_index_multi_indices": [_vp, _pu16],
     "hs_index_device_bytes": [_vp, _pi64],
@@ -201,6 +202,13 @@ class Index:
                 self.h = None
         except Exception:
             pass
+
+
+def index_count(N: int, B: int) -> int:
+    """|K_N(B)| without building the set."""
+    n = C.c_int64()
+    hs_index_count(int(N), int(B), C.byref(n))
+    return n.value
 
 
 class Pot:

@@ -158,15 +158,21 @@ def decay_vector(k: np.ndarray, beta: float) -> np.ndarray:
 
 def batch_instances(n: int, seed: int, nmin: int = 3, nmax: int = 8,
                     log2_bmin: float = 8.0, log2_bmax: float = 14.0,
-                    lam_lo: float = 0.05, lam_hi: float = 0.15):
+                    lam_lo: float = 0.05, lam_hi: float = 0.15, accept=None):
     """Instance draws of the batched workload: N ~ U{nmin..nmax},
-    B = floor(2^U(log2_bmin, log2_bmax)), lambda ~ U[lam_lo, lam_hi]."""
+    B = floor(2^U(log2_bmin, log2_bmax)), lambda ~ U[lam_lo, lam_hi].
+
+    accept(N, B) -> bool, if given, is a size rule: an instance it rejects is drawn
+    again (all three values, from the same stream) until one is accepted."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):
-        N = int(rng.integers(nmin, nmax + 1))
-        B = int(math.floor(2.0 ** rng.uniform(log2_bmin, log2_bmax)))
-        lam = float(rng.uniform(lam_lo, lam_hi))
+        while True:
+            N = int(rng.integers(nmin, nmax + 1))
+            B = int(math.floor(2.0 ** rng.uniform(log2_bmin, log2_bmax)))
+            lam = float(rng.uniform(lam_lo, lam_hi))
+            if accept is None or accept(N, B):
+                break
         out.append({"N": N, "B": B, "lam": lam, "seed": 1000 + i})
     return out
 

@@ -185,3 +185,44 @@ def test_batch_refuses_other_forms_and_sets(hs):
     pots[0].set_form(hs.HS_FORM_PAPER)
     b.apply_h(x, y)
     torch.cuda.synchronize()
+
+
+def test_full_range_draw_with_size_rule(hs):
+    """B over the whole range 2^8..2^14 with the bench's redraw rule (here at 2^17 rows):
+    batched application bit for bit equal to the per-instance path, and batched steps equal
+    to per-instance steps that share one workspace."""
+    import ctypes
+    import torch
+    cap = 1 << 17
+    draws = batch_instances(16, seed=5, log2_bmax=14.0, accept=lambda N, B: hs.index_count(N, B) <= cap)
+    assert max(d["B"] for d in draws) > 2 ** 11
+    print("draws", [(d["N"], d["B"]) for d in draws], flush=True)
+    idxs, pots, ks, cs = make_batch(hs, draws)
+    b = hs.Batch(idxs, pots)
+    x = pack(b, cs)
+    y = torch.zeros_like(x)
+    b.apply_h(x, y)
+    yb = y.cpu().numpy()
+    for i, (idx, pot, c) in enumerate(zip(idxs, pots, cs)):
+        ci = torch.from_numpy(c).to("cuda")
+        yi = torch.empty_like(ci)
+        hs.apply_h(idx, pot, ci, yi)
+        torch.cuda.synchronize()
+        assert np.array_equal(yb[b.offsets[i]:b.offsets[i] + c.size], yi.cpu().numpy()), f"instance {i}"
+    m, h = 10, 0.005
+    ws = b.workspace(m)
+    b.step(x, 0.0, h, m, ws=ws)
+    xb = x.cpu().numpy()
+    nbmax = 0
+    for idx, pot in zip(idxs, pots):
+        nb = ctypes.c_int64()
+        hs.hs_workspace_bytes(idx.h, pot.h, hs.HS_C128, m, ctypes.byref(nb))
+        nbmax = max(nbmax, nb.value)
+    ws1 = hs.dev_buffer(nbmax)
+    singles = [torch.from_numpy(c.copy()).to("cuda") for c in cs]
+    for idx, pot, ci in zip(idxs, pots, singles):
+        hs.step(idx, pot, ci, 0.0, h, m, ws=ws1)
+    torch.cuda.synchronize()
+    for i, ci in enumerate(singles):
+        seg = xb[b.offsets[i]:b.offsets[i] + cs[i].size]
+        assert rel2(seg, ci.cpu().numpy()) <= 1e-13, f"instance {i}: batched vs per-instance"

@@ -290,3 +290,33 @@ def test_sizes_and_counts(hs):
     herm = hs.Pot(3, [(0.1, (2, 2, 2)), (0.2, (6, 0, 0))], basis="herm", upload=False)
     hs.hs_workspace_bytes(idx.h, herm.h, 0, 0, C.byref(nb))
     assert nb.value >= 16 * idx.size
+
+
+@pytest.mark.parametrize("N,B", [(1, 1), (1, 50), (2, 64), (3, 500), (5, 97), (8, 30), (16, 3)])
+def test_index_count_without_enumeration(hs, N, B):
+    assert hs.index_count(N, B) == count(N, B)
+
+
+def test_index_count_agrees_with_built_sets(hs):
+    for N, B in [(6, 4096), (8, 700), (3, 16384)]:
+        assert hs.index_count(N, B) == hs.Index(N, B, upload=False).size
+    n = C.c_int64()
+    assert hs._lib.hs_index_count(0, 10, C.byref(n)) != 0
+    assert hs._lib.hs_index_count(3, 0, C.byref(n)) != 0
+    assert hs._lib.hs_index_count(3, 65537, C.byref(n)) != 0
+    assert hs._lib.hs_index_count(3, 10, None) != 0
+
+
+def test_batched_draw_size_rule(hs):
+    """The batched workload's redraw rule keeps every accepted draw as it was and draws a
+    rejected instance again from the same stream."""
+    from synth import batch_instances
+    cap = 1 << 16
+    plain = batch_instances(64, seed=3)
+    ruled = batch_instances(64, seed=3, accept=lambda N, B: hs.index_count(N, B) <= cap)
+    assert all(hs.index_count(d["N"], d["B"]) <= cap for d in ruled)
+    assert [d["seed"] for d in ruled] == [1000 + i for i in range(64)]
+    # up to the first rejected draw the two sequences agree
+    first = next(i for i, d in enumerate(plain) if hs.index_count(d["N"], d["B"]) > cap)
+    assert ruled[:first] == plain[:first]
+    assert ruled[first] != plain[first]
