@@ -42,6 +42,8 @@ sys.path.insert(0, ROOT)
 
 N_DIM, B_BOUND, M_KRYLOV, H_STEP = 6, 4096, 10, 0.005
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6
+FP32_VALU_PEAK_TFLOPS = 157.3
 METRIC = "Galerkin matvecs/s + HBM GB/s (% peak), batched/FP32 vs plain FP64 at 1e-10"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hh_long_N6_B4096_traffic.json")
 # sources whose change invalidates the recorded counter traffic of the H kernel
@@ -95,6 +97,37 @@ def capture(fn, stream):
     stream.wait_stream(s2)
     torch.cuda.synchronize()
     return g
+
+
+def alg_flops_per_row(N: int, degrees) -> int:
+    """Algorithmic flops per row of one H application by the shared-prefix evaluation of a
+    monomial potential (the complexity count of Sec. 3, linear in the sum of the term
+    degrees): complex multiply-adds for each distinct partial product X_j^e of a term,
+    applied axis N first (8 flops each), one complex axpy per term (4) and the diagonal (4).
+    The fused kernel's own instruction count differs; this is the work the method needs."""
+    nodes = set()
+    for a in degrees:
+        done = []
+        for j in range(N - 1, -1, -1):
+            for e in range(1, a[j] + 1):
+                nodes.add(tuple(done) + ((j, e),))
+            if a[j]:
+                done.append((j, a[j]))
+    return 8 * len(nodes) + 4 * len(degrees) + 4
+
+
+def w_degrees(terms, N: int):
+    """Degree vectors of W = V - (1/2)|x|^2 for a monomial term list of V."""
+    base, timed = {}, set()
+    for t in terms:
+        key = tuple(t.degrees)
+        base[key] = base.get(key, 0.0) + t[0]
+        if t[1] != 0.0:
+            timed.add(key)
+    for l in range(N):
+        key = tuple(2 if i == l else 0 for i in range(N))
+        base[key] = base.get(key, 0.0) - 0.5
+    return [k for k, b in base.items() if b != 0.0 or k in timed]
 
 
 def calibrate_copy(mib: int, reps: int = 5):
@@ -194,6 +227,11 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": kernel, "us_per_launch": round(us_matvec, 2),
                 "alg_bytes_per_launch": int(alg_bytes)}
+    fpr = alg_flops_per_row(N_DIM, w_degrees(terms, N_DIM))
+    tflops = fpr * idx.size / (us_matvec * 1e-6) / 1e12
+    roofline.update({"alg_flops_per_row": fpr, "fp64_valu_tflops": round(tflops, 3),
+                     "fp64_valu_peak": FP64_VALU_PEAK_TFLOPS,
+                     "fp64_valu_frac": round(tflops / FP64_VALU_PEAK_TFLOPS, 4)})
 
     forms = None
     if args.forms:
@@ -504,13 +542,18 @@ def fp32_n10_form(hs, stream, args):
         del ws, x, y
     err = float(torch.linalg.norm(vec["fp32"] - vec["fp64"]) / torch.linalg.norm(vec["fp64"]))
     S = {"fp64": 16, "fp32": 8}
+    fpr = alg_flops_per_row(N, w_degrees(tt, N))
+    peak = {"fp64": FP64_VALU_PEAK_TFLOPS, "fp32": FP32_VALU_PEAK_TFLOPS}
+    vfrac = {k: fpr * idx.size / (mv_us[k] * 1e-6) / 1e12 / peak[k] for k in mv_us}
     return {"workload": "N=10 B=4096 (%d rows) HH lambda=0.111 + laser, packet x_d=0.5, %d steps, "
                         "m=10, h=0.005" % (idx.size, args.n10_steps),
             "fp32_matvec_per_s": round(rate["fp32"], 2), "fp64_matvec_per_s": round(rate["fp64"], 2),
             "speedup_vs_fp64": round(rate["fp32"] / rate["fp64"], 3), "rel_err_vs_fp64": err,
             "fp32_us_per_matvec": round(mv_us["fp32"], 1), "fp64_us_per_matvec": round(mv_us["fp64"], 1),
             "fp32_alg_gbs": round(2 * S["fp32"] * idx.size / mv_us["fp32"] / 1e3, 1),
-            "fp64_alg_gbs": round(2 * S["fp64"] * idx.size / mv_us["fp64"] / 1e3, 1)}
+            "fp64_alg_gbs": round(2 * S["fp64"] * idx.size / mv_us["fp64"] / 1e3, 1),
+            "alg_flops_per_row": fpr, "fp32_valu_frac": round(vfrac["fp32"], 4),
+            "fp64_valu_frac": round(vfrac["fp64"], 4)}
 
 
 def learned_form(hs, stream, args):
