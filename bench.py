@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--tile-dim", type=int, default=0)
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--forms", type=int, default=1, help="also measure the FP32 and batched forms")
-    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4,sym,diag",
+    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4,sym,diag,xop",
                     help="comma-separated forms measured when --forms is set")
     ap.add_argument("--batch-log2-bmax", type=float, default=14.0)
     ap.add_argument("--batch-max-rows", type=int, default=1 << 23,
@@ -251,6 +251,8 @@ def main():
             forms["sym"] = sym_form(hs, idx, pot, c0, stream, args, value)
         if "diag" in want:
             forms["diag"] = diag_form(hs, stream, args)
+        if "xop" in want:
+            forms["xop"] = xop_form(hs, idx, c0, stream)
         if "n10_big" in want:   # opt-in: not in the default list
             forms["n10_big"] = n10_big_form(hs, stream, args)
 
@@ -366,6 +368,22 @@ def magnus4_form(hs, idx, pot, c0, stream, args, midpoint_matvec_per_s, nsteps=1
             # two fused passes: read v, write a and d; read a and d, write w (6 S per row)
             "m_alg_gbs": round(6 * 16.0 * idx.size / (us_m * 1e-6) / 1e9, 1),
             "rel_err_8_steps_vs_h_over_4": err}
+
+
+def xop_form(hs, idx, c0, stream, reps=50):
+    """The direct operation y = X^(l) c alone on the main workload's set, per axis: one
+    pass over the rows, 32 algorithmic bytes per row (read c, write y) in FP64."""
+    import torch
+    x = torch.from_numpy(c0).to("cuda")
+    y = torch.empty_like(x)
+    us = []
+    for axis in range(idx.N):
+        hs.apply_x(idx, axis, x, y)
+        us.append(event_time_ms(lambda: hs.apply_x(idx, axis, x, y), reps, stream) * 1e3 / reps)
+    gbs = [32.0 * idx.size / (u * 1e-6) / 1e9 for u in us]
+    return {"workload": "X^(l) c on the main line's set (%d rows), FP64, each axis" % idx.size,
+            "us_per_axis": [round(u, 2) for u in us], "alg_gbs_per_axis": [round(g, 1) for g in gbs],
+            "hbm_frac_best": round(max(gbs) / HBM_PEAK_GBS, 4)}
 
 
 def sym_form(hs, idx, pot, c0, stream, args, paper_matvec_per_s, nsteps=10):

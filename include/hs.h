@@ -169,6 +169,15 @@ int32_t hs_workspace_bytes(hs_index idx, hs_pot pot, int32_t dtype, int32_t m, i
 int32_t hs_apply_h(hs_index idx, const void *idx_dev, hs_pot pot, const void *pot_dev,
                    int32_t dtype, const void *c, void *y, void *ws, void *stream);
 
+/* ---- direct operation (paper Sec. 3.1, eq. DirectOperationWithX; Fig. 3) --------
+ * y = X_K^(l) c, the Galerkin matrix of the coordinate x_l on the set, applied without
+ * assembly: y_k = sqrt(k_l / 2) c_{k - e_l} + sqrt((k_l + 1) / 2) c_{k + e_l}, where a
+ * neighbour outside K contributes nothing.  axis = l - 1 (0-based, as the columns of
+ * the degree arrays).  c and y: device vectors of |K| complex values of the given dtype
+ * in library row order, c != y.  Serves every set kind; no workspace.               */
+int32_t hs_apply_x(hs_index idx, const void *idx_dev, int32_t axis, int32_t dtype, const void *c,
+                   void *y, void *stream);
+
 /* ---- time step (paper Sec. 2, eq. expMPR; Fig. 4) ----------------------------
  * One exponential-midpoint step of length h with an m-step Lanczos exponential:
  * coefficients at t + h/2, m applications of H, c <- V_m exp(-i h T_m) e_1 ||c||.

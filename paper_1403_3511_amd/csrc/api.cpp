@@ -20,10 +20,6 @@ int32_t hip_fail(hipError_t e, const char *what) {
 }
 
 int32_t launch_copy_coeffs(const hs_pot_s *p, void *pot_dev, const double *coef, hipStream_t s);
-int32_t launch_apply(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p,
-                     const void *pot_dev, int32_t dtype, const void *x, void *y, void *ws,
-                     hipStream_t s, const double *out_scale, const void *prev,
-                     const double *prev_coef, const double *prev_scale);
 int32_t launch_step(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p, void *pot_dev,
                     int32_t dtype, double t, double *t_dev, double h, int m, int reorth, void *c,
                     void *ws, double *diag, hipStream_t s);
@@ -139,6 +135,17 @@ extern "C" int32_t hs_apply_h(hs_index idx, const void *idx_dev, hs_pot pot, con
     return hs::fail(HS_E_WORKSPACE, "hs_apply_h: this potential needs a workspace");
   return hs::launch_apply(idx, idx_dev, pot, pot_dev, dtype, c, y, ws,
                           static_cast<hipStream_t>(stream), nullptr, nullptr, nullptr, nullptr);
+}
+
+extern "C" int32_t hs_apply_x(hs_index idx, const void *idx_dev, int32_t axis, int32_t dtype, const void *c,
+                              void *y, void *stream) {
+  if (!idx || !idx_dev || !c || !y) return hs::fail(HS_E_INVALID, "hs_apply_x: NULL argument");
+  if (axis < 0 || axis >= idx->N) return hs::fail(HS_E_INVALID, "hs_apply_x: axis out of range 0..N-1");
+  if (dtype != HS_C128 && dtype != HS_C64) return hs::fail(HS_E_INVALID, "hs_apply_x: bad dtype");
+  if (c == y) return hs::fail(HS_E_INVALID, "hs_apply_x: input and output must differ");
+  if (!hs::aligned16(c) || !hs::aligned16(y) || !hs::aligned16(idx_dev))
+    return hs::fail(HS_E_INVALID, "hs_apply_x: device pointer not 16-byte aligned");
+  return hs::launch_apply_x(idx, idx_dev, axis, dtype, c, y, static_cast<hipStream_t>(stream));
 }
 
 extern "C" int32_t hs_step(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev,

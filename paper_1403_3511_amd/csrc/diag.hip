@@ -15,11 +15,6 @@
 
 namespace hs {
 
-int32_t launch_apply(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p,
-                     const void *pot_dev, int32_t dtype, const void *x, void *y, void *ws,
-                     hipStream_t s, const double *out_scale, const void *prev,
-                     const double *prev_coef, const double *prev_scale);
-
 // y_box = Omega_+(x): zero, then the set's entries at their box rows
 __global__ void __launch_bounds__(256) k_zero(int64_t n, double2 *__restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -185,8 +185,12 @@ int32_t compile_potential(hs_pot_s *p);
 // kernels (implemented in the .hip translation units)
 int32_t launch_set_time(const hs_pot_s *p, void *pot_dev, double t, const double *t_dev,
                         double dt_offset, hipStream_t s);
-int32_t launch_apply_h(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p,
-                       const void *pot_dev, int32_t dtype, const void *c, void *y, void *ws,
-                       hipStream_t s, double out_scale_unused);
+// y = out_scale * H x - prev_coef * prev_scale * prev (the optional terms when non-NULL)
+int32_t launch_apply(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p,
+                     const void *pot_dev, int32_t dtype, const void *x, void *y, void *ws,
+                     hipStream_t s, const double *out_scale, const void *prev,
+                     const double *prev_coef, const double *prev_scale);
+int32_t launch_apply_x(const hs_index_s *idx, const void *idx_dev, int32_t axis, int32_t dtype,
+                       const void *x, void *y, hipStream_t s);
 int64_t apply_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32_t dtype);
 }  // namespace hs

@@ -509,11 +509,6 @@ template int32_t run_step<float>(const StepJob &, int, int, double, void *, void
                                  double *, double *, hipStream_t);
 
 // ---- single instance ----------------------------------------------------------------------
-int32_t launch_apply(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p,
-                     const void *pot_dev, int32_t dtype, const void *x, void *y, void *ws,
-                     hipStream_t s, const double *out_scale, const void *prev,
-                     const double *prev_coef, const double *prev_scale);
-
 static SegView single_segments(int64_t rows) {
   SegView v{};
   v.n = 1;

@@ -583,4 +583,23 @@ int32_t launch_apply(const hs_index_s *idx, const void *idx_dev, const hs_pot_s 
   return apply_impl<float>(idx, idx_dev, p, pot_dev, x, y, ws, s, out_scale, prev, prev_coef, prev_scale);
 }
 
+// y = X^(axis) x alone: one pass with A = 1 and nothing added
+int32_t launch_apply_x(const hs_index_s *idx, const void *idx_dev, int32_t axis, int32_t dtype,
+                       const void *x, void *y, hipStream_t s) {
+  if (idx->size == 0) return HS_OK;
+  const IndexDev ix = idx->view(idx_dev);
+  const unsigned g = nblk(idx->size, 256);
+  if (dtype == HS_C128) {
+    using C = V2<double>::t;
+    hipLaunchKernelGGL(k_pass<double>, dim3(g), dim3(256), 0, s, ix, (int)axis, 1.0, 0.0, 0.0, (const C *)x,
+                       nullptr, nullptr, (C *)y, nullptr, nullptr, -1);
+  } else {
+    using C = V2<float>::t;
+    hipLaunchKernelGGL(k_pass<float>, dim3(g), dim3(256), 0, s, ix, (int)axis, 1.0, 0.0, 0.0, (const C *)x,
+                       nullptr, nullptr, (C *)y, nullptr, nullptr, -1);
+  }
+  HS_HIP(hipGetLastError());
+  return HS_OK;
+}
+
 }  // namespace hs

@@ -57,6 +57,7 @@ _SIGS = {
     "hs_pot_set_time": [_vp, _vp, _f64, _vp, _vp],
     "hs_pot_set_coeffs_device": [_vp, _vp, _vp, _vp],
     "hs_pot_set_form": [_vp, _i32],
+    "hs_apply_x": [_vp, _vp, _i32, _i32, _vp, _vp, _vp],
     "hs_workspace_bytes": [_vp, _vp, _i32, _i32, _pi64],
     "hs_apply_h": [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "hs_step": [_vp, _vp, _vp, _vp, _i32, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
@@ -295,6 +296,12 @@ def apply_h(idx: Index, pot: Pot, c, y, dtype: int = HS_C128, ws=None):
     if ws is None:
         ws = workspace(idx, pot, dtype, 0, c.device)
     hs_apply_h(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, ptr(c), ptr(y), ptr(ws), stream_ptr())
+    return y
+
+
+def apply_x(idx: Index, axis: int, c, y, dtype: int = HS_C128):
+    """y = X^(axis) c, the direct operation along one axis (0-based); c != y."""
+    hs_apply_x(idx.h, ptr(idx.dev), int(axis), dtype, ptr(c), ptr(y), stream_ptr())
     return y
 
 

@@ -217,6 +217,13 @@ def test_error_paths(hs):
     expect(-1, hs.hs_workspace_bytes, idx.h, pot2.h, 0, 33, C.byref(nb))      # m > 32
     expect(-1, hs.hs_workspace_bytes, idx.h, pot2.h, 5, 10, C.byref(nb))      # dtype
     expect(-1, hs.hs_apply_h, idx.h, None, pot2.h, None, 0, None, None, None, None)  # NULL buffers
+    fk = (C.c_double * 64)()
+    fkp, fkq = C.cast(fk, C.c_void_p), C.cast(C.byref(fk, 256), C.c_void_p)
+    expect(-1, hs.hs_apply_x, idx.h, fkp, 2, 0, fkp, fkq, None)                # axis >= N
+    expect(-1, hs.hs_apply_x, idx.h, fkp, -1, 0, fkp, fkq, None)               # axis < 0
+    expect(-1, hs.hs_apply_x, idx.h, fkp, 0, 4, fkp, fkq, None)                # dtype
+    expect(-1, hs.hs_apply_x, idx.h, fkp, 0, 0, fkp, fkp, None)                # in == out
+    expect(-1, hs.hs_apply_x, idx.h, None, 0, 0, fkp, fkq, None)               # NULL metadata
     expect(-1, hs.hs_pot_set_form, pot2.h, 7)                                 # unknown form
     gz = np.zeros(5 * 3 * 5)
     gp = gz.ctypes.data_as(C.POINTER(C.c_double))
