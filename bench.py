@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--tile-dim", type=int, default=0)
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--forms", type=int, default=1, help="also measure the FP32 and batched forms")
-    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4,sym,diag,xop",
+    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4,sym,diag,xop,small",
                     help="comma-separated forms measured when --forms is set")
     ap.add_argument("--batch-log2-bmax", type=float, default=14.0)
     ap.add_argument("--batch-max-rows", type=int, default=1 << 23,
@@ -253,6 +253,8 @@ def main():
             forms["diag"] = diag_form(hs, stream, args)
         if "xop" in want:
             forms["xop"] = xop_form(hs, idx, c0, stream)
+        if "small" in want:
+            forms["small"] = small_form(hs, stream)
         if "n10_big" in want:   # opt-in: not in the default list
             forms["n10_big"] = n10_big_form(hs, stream, args)
 
@@ -368,6 +370,50 @@ def magnus4_form(hs, idx, pot, c0, stream, args, midpoint_matvec_per_s, nsteps=1
             # two fused passes: read v, write a and d; read a and d, write w (6 S per row)
             "m_alg_gbs": round(6 * 16.0 * idx.size / (us_m * 1e-6) / 1e9, 1),
             "rel_err_8_steps_vs_h_over_4": err}
+
+
+def small_form(hs, stream, nsteps=100, reps=20):
+    """The small workload: N = 2, product bound 64 (280 rows), Henon-Heiles, complex normal
+    start (seed 0), m = 10, h = 0.01.  Latency-bound (one workgroup's worth of rows), so the
+    figures are microseconds: one H application, and 100 steps of time propagation replayed
+    as one captured graph (one-workgroup step) against the same 100 steps launched eagerly
+    and against the graph of the general step."""
+    import numpy as np
+    import torch
+    from synth import complex_normal_by_index, henon_heiles_chain
+
+    N, B, m, h = 2, 64, 10, 0.01
+    tt = henon_heiles_chain(N, 0.111, 0.0)
+    idx = hs.Index(N, B)
+    pot = hs.Pot(N, [(x[0], x[1], x[2], x[3], x.degrees) for x in tt], subtract_harmonic=True)
+    c0 = complex_normal_by_index(idx.multi_indices(), 0)
+    x = torch.from_numpy(c0).to("cuda")
+    y = torch.empty_like(x)
+    aws = hs.workspace(idx, pot, hs.HS_C128, 0)
+    hs.apply_h(idx, pot, x, y, hs.HS_C128, aws)
+    us_h = event_time_ms(lambda: hs.apply_h(idx, pot, x, y, hs.HS_C128, aws), 200, stream) * 1e3 / 200
+    c = x.clone()
+    ws = hs.workspace(idx, pot, hs.HS_C128, m)
+    t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hs.propagate(idx, pot, c, 0.0, h, m, nsteps, ws=ws, t_dev=t_dev)
+    ms_eager = event_time_ms(lambda: hs.propagate(idx, pot, c, 0.0, h, m, nsteps, ws=ws, t_dev=t_dev),
+                             3, stream) / 3
+    g = capture(lambda: hs.propagate(idx, pot, c, 0.0, h, m, nsteps, ws=ws, t_dev=t_dev), stream)
+    ms_graph = event_time_ms(g.replay, reps, stream) / reps
+    del g
+    # the same steps on the general step path (row limit 0)
+    old = hs.set_small_step_rows(0)
+    g = capture(lambda: hs.propagate(idx, pot, c, 0.0, h, m, nsteps, ws=ws, t_dev=t_dev), stream)
+    ms_general = event_time_ms(g.replay, reps, stream) / reps
+    del g
+    hs.set_small_step_rows(old)
+    return {"workload": "N=2 B=64 (%d rows) Henon-Heiles lambda=0.111, complex normal start (seed 0), "
+                        "%d steps, m=10, h=0.01" % (idx.size, nsteps),
+            "us_per_h_application": round(us_h, 2),
+            "us_per_step_graph": round(ms_graph * 1e3 / nsteps, 2),
+            "us_per_step_eager": round(ms_eager * 1e3 / nsteps, 2),
+            "us_per_step_graph_general_path": round(ms_general * 1e3 / nsteps, 2),
+            "matvec_per_s_graph": round(nsteps * m / (ms_graph / 1e3), 1)}
 
 
 def xop_form(hs, idx, c0, stream, reps=50):

@@ -193,6 +193,26 @@ int32_t hs_step(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev, in
                 double t, double *t_dev, double h, int32_t m, int32_t reorth, void *c, void *ws,
                 double *diag_dev, void *stream);
 
+/* Sets of at most `rows` rows (default 1024; the kernel holds one row per thread, at most
+ * 1024, so larger values act as 1024) run hs_step / hs_propagate of the paper's operator
+ * form with a fused-class potential as one launch of one workgroup: the whole
+ * Lanczos step in one kernel, with the same recurrences, breakdown rule and workspace
+ * layout as the general step, and its reductions in another fixed order (results agree
+ * to rounding, and each path repeats bit for bit).  0 always takes the general step.
+ * Process-wide; not meant to change while steps are in flight.                        */
+int32_t hs_set_small_step_rows(int64_t rows);
+int32_t hs_get_small_step_rows(int64_t *rows);
+
+/* ---- time propagation (paper Sec. 2.2; Fig. 4 time_propagation) --------------------
+ * nsteps consecutive hs_step calls on the same stream, with the same arguments: step n
+ * starts at t0 + n h (or at the value in t_dev, which each step advances by h).  c is
+ * overwritten with c(t0 + nsteps h); ws as for hs_step.  nsteps = 0 does nothing.  The
+ * whole call can be captured into one HIP graph.  An error stops at the failing step
+ * (earlier steps have been enqueued).                                                  */
+int32_t hs_propagate(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev, int32_t dtype,
+                     double t0, double *t_dev, double h, int32_t m, int32_t reorth, int64_t nsteps,
+                     void *c, void *ws, void *stream);
+
 /* ---- fourth-order step (paper Sec. 2.1, eq. 2stageMagnus) ------------------------
  * Two-stage Gauss-Legendre Magnus scheme: Omega = -i h M with
  *   M = (A_1 + A_2)/2 - i (sqrt(3) h / 12) (A_2 A_1 - A_1 A_2),  A_j = H(t + c_j h),

@@ -163,6 +163,41 @@ extern "C" int32_t hs_step(hs_index idx, const void *idx_dev, hs_pot pot, void *
                          static_cast<hipStream_t>(stream));
 }
 
+extern "C" int32_t hs_set_small_step_rows(int64_t rows) {
+  if (rows < 0) return hs::fail(HS_E_INVALID, "hs_set_small_step_rows: negative row count");
+  hs::set_small_step_rows(rows);
+  return HS_OK;
+}
+
+extern "C" int32_t hs_get_small_step_rows(int64_t *rows) {
+  if (!rows) return hs::fail(HS_E_INVALID, "hs_get_small_step_rows: rows is NULL");
+  *rows = hs::small_step_rows();
+  return HS_OK;
+}
+
+extern "C" int32_t hs_propagate(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev, int32_t dtype,
+                                double t0, double *t_dev, double h, int32_t m, int32_t reorth, int64_t nsteps,
+                                void *c, void *ws, void *stream) {
+  if (!idx || !pot || !idx_dev || !pot_dev || !c || !ws)
+    return hs::fail(HS_E_INVALID, "hs_propagate: NULL argument");
+  if (pot->N != idx->N) return hs::fail(HS_E_INVALID, "hs_propagate: potential and index differ in N");
+  if (dtype != HS_C128 && dtype != HS_C64) return hs::fail(HS_E_INVALID, "hs_propagate: bad dtype");
+  if (m < 1 || m > 32) return hs::fail(HS_E_INVALID, "hs_propagate: m out of range 1..32");
+  if (nsteps < 0) return hs::fail(HS_E_INVALID, "hs_propagate: negative step count");
+  if (!std::isfinite(h) || (!t_dev && !std::isfinite(t0)))
+    return hs::fail(HS_E_NONFINITE, "hs_propagate: t0 or h not finite");
+  if (!hs::aligned16(c) || !hs::aligned16(ws) || !hs::aligned16(idx_dev) || !hs::aligned16(pot_dev))
+    return hs::fail(HS_E_INVALID, "hs_propagate: device pointer not 16-byte aligned");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int64_t n = 0; n < nsteps; ++n) {
+    // with t_dev the device clock advances by h per step; without it step n starts at t0 + n h
+    const int32_t st = hs::launch_step(idx, idx_dev, pot, pot_dev, dtype, t0 + (double)n * h, t_dev, h, m,
+                                       reorth, c, ws, nullptr, s);
+    if (st != HS_OK) return st;
+  }
+  return HS_OK;
+}
+
 extern "C" int32_t hs_magnus4_workspace_bytes(hs_index idx, hs_pot pot, int32_t dtype, int32_t m,
                                               int64_t *bytes) {
   if (!idx || !pot || !bytes) return hs::fail(HS_E_INVALID, "hs_magnus4_workspace_bytes: NULL argument");

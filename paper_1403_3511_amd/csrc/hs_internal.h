@@ -193,4 +193,7 @@ int32_t launch_apply(const hs_index_s *idx, const void *idx_dev, const hs_pot_s 
 int32_t launch_apply_x(const hs_index_s *idx, const void *idx_dev, int32_t axis, int32_t dtype,
                        const void *x, void *y, hipStream_t s);
 int64_t apply_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32_t dtype);
+// row limit of the one-workgroup step (0: never)
+void set_small_step_rows(int64_t rows);
+int64_t small_step_rows();
 }  // namespace hs

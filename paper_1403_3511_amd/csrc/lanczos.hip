@@ -13,6 +13,7 @@
 // and a finishing block per instance adds its segments' partials in a fixed tree, so
 // results do not depend on scheduling and repeat bit for bit.
 #include <algorithm>
+#include <atomic>
 
 #include "lanczos.h"
 
@@ -264,94 +265,9 @@ k_sfin_beta(SegView sv, const double *__restrict__ part, int k, int m, double to
   }
 }
 
-// y = beta0 exp(-i h T) e1 for the real symmetric tridiagonal T (m <= 32) of instance
-// blockIdx.x, by scaling and squaring: delta = h / 2^q with h ||T||_inf / 2^q <= 1/2,
-// an 18-term Taylor polynomial of exp(-i delta T) (truncation below 1e-22), then q
-// squarings.  One thread per matrix element.
+// exp(-i h T) e1 beta0 for instance blockIdx.x
 __global__ void __launch_bounds__(1024) k_small_expm(double h, double *__restrict__ scall) {
-  __shared__ double2 E[kMaxM][kMaxM + 1], P[kMaxM][kMaxM + 1];
-  __shared__ double td[kMaxM], to[kMaxM];
-  __shared__ double s_delta;
-  __shared__ int s_q;
-  double *sc = scall + (int64_t)blockIdx.x * Scal::size;
-  const int m = (int)sc[Scal::meff];
-  if (m <= 0) return;
-  const int tid = threadIdx.x;
-  const int i = tid / kMaxM, j = tid % kMaxM;
-  const bool act = (i < m) && (j < m);
-  if (tid < m) {
-    td[tid] = sc[Scal::alpha + tid];
-    to[tid] = (tid + 1 < m) ? sc[Scal::beta + tid] : 0.0;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double nrm = 0.0;
-    for (int r = 0; r < m; ++r) {
-      double row = fabs(td[r]) + fabs(to[r]);
-      if (r > 0) row += fabs(to[r - 1]);
-      nrm = fmax(nrm, row);
-    }
-    double rho = fabs(h) * nrm;
-    int q = 0;
-    while (rho > 0.5 && q < 60) {
-      rho *= 0.5;
-      ++q;
-    }
-    s_q = q;
-    s_delta = ldexp(h, -q);
-  }
-  __syncthreads();
-  const double delta = s_delta;
-  const int q = s_q;
-  if (act) {
-    const double2 d = make_double2(i == j ? 1.0 : 0.0, 0.0);
-    E[i][j] = d;
-    P[i][j] = d;
-  }
-  __syncthreads();
-  for (int k = 1; k <= 18; ++k) {
-    double2 nv = make_double2(0.0, 0.0);
-    if (act) {  // P <- P (-i delta T) / k, T tridiagonal
-      double sr = P[i][j].x * td[j], si = P[i][j].y * td[j];
-      if (j > 0) {
-        sr += P[i][j - 1].x * to[j - 1];
-        si += P[i][j - 1].y * to[j - 1];
-      }
-      if (j + 1 < m) {
-        sr += P[i][j + 1].x * to[j];
-        si += P[i][j + 1].y * to[j];
-      }
-      const double f = delta / k;
-      nv = make_double2(si * f, -sr * f);
-    }
-    __syncthreads();
-    if (act) {
-      P[i][j] = nv;
-      E[i][j].x += nv.x;
-      E[i][j].y += nv.y;
-    }
-    __syncthreads();
-  }
-  for (int r = 0; r < q; ++r) {
-    double2 nv = make_double2(0.0, 0.0);
-    if (act) {
-      double ar = 0.0, ai = 0.0;
-      for (int l = 0; l < m; ++l) {
-        const double2 a = E[i][l], b = E[l][j];
-        ar = fma(a.x, b.x, fma(-a.y, b.y, ar));
-        ai = fma(a.x, b.y, fma(a.y, b.x, ai));
-      }
-      nv = make_double2(ar, ai);
-    }
-    __syncthreads();
-    if (act) E[i][j] = nv;
-    __syncthreads();
-  }
-  if (act && j == 0) {
-    const double b0 = sc[Scal::beta0];
-    sc[Scal::yre + i] = b0 * E[i][0].x;
-    sc[Scal::yim + i] = b0 * E[i][0].y;
-  }
+  small_expm_block(h, scall + (int64_t)blockIdx.x * Scal::size);
 }
 
 // c = sum_{k < m_eff} y_k V_k (complex128 result)
@@ -456,7 +372,7 @@ int32_t run_step(const StepJob &J, int m, int reorth, double h, void *cvoid, voi
   double *sc = (double *)(w8 + L.off_sc);
   double2 *c = static_cast<double2 *>(cvoid);
   const unsigned nseg = (unsigned)J.sv.nseg, nin = (unsigned)J.sv.n;
-  const double tol = 1e-12;
+  const double tol = kBreakdownTol;
 
   int32_t st = J.set_time(s);
   if (st != HS_OK) return st;
@@ -524,9 +440,41 @@ int64_t step_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32_t d
                      apply_workspace_bytes(idx, p, dtype)).total;
 }
 
+// Sets of at most this many rows take the one-workgroup step (hs_set_small_step_rows)
+static std::atomic<int64_t> g_small_step_rows{kSmallStepRowsDefault};
+
+void set_small_step_rows(int64_t rows) { g_small_step_rows.store(rows); }
+int64_t small_step_rows() { return g_small_step_rows.load(); }
+
+static bool small_step_eligible(const hs_index_s *idx, const hs_pot_s *p, int m) {
+  return p->fused && p->form == HS_FORM_PAPER && idx->size > 0 && idx->size <= g_small_step_rows.load() &&
+         idx->size <= kSmallStepRowsMax &&
+         idx->recs_all && idx->rstride == rec_stride(idx->np) && m >= 1 && m <= kMaxM &&
+         step_small_supported(idx->N, idx->np);
+}
+
 int32_t launch_step(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *p, void *pot_dev,
                     int32_t dtype, double t, double *t_dev, double h, int m, int reorth, void *c,
                     void *ws, double *diag, hipStream_t s) {
+  if (small_step_eligible(idx, p, m)) {
+    const int64_t elem = dtype == HS_C64 ? 8 : 16;
+    const StepLayout L = step_layout(idx->size, single_segments(idx->size).nseg, 1, elem, m,
+                                     apply_workspace_bytes(idx, p, dtype));
+    uint8_t *w8 = static_cast<uint8_t *>(ws);
+    int32_t st = launch_set_time(p, pot_dev, t, t_dev, 0.5 * h, s);
+    if (st != HS_OK) return st;
+    const IndexDev ix = idx->view(idx_dev);
+    const double *hh = (const double *)(static_cast<const uint8_t *>(pot_dev) + p->off_hh);
+    double *sc = (double *)(w8 + L.off_sc);
+    const int done = dtype == HS_C128
+        ? launch_step_small_f64(ix, hh, c, w8 + L.off_V, L.vec_stride / elem, h, m, reorth, kBreakdownTol, sc,
+                                t_dev, diag, s, p->x2)
+        : launch_step_small_f32(ix, hh, c, w8 + L.off_V, L.vec_stride / elem, h, m, reorth, kBreakdownTol, sc,
+                                t_dev, diag, s, p->x2);
+    if (done != 1) return fail(HS_E_UNSUPPORTED, "small-set step: no instantiation for this set");
+    HS_HIP(hipGetLastError());
+    return HS_OK;
+  }
   StepJob J;
   J.rows = idx->size;
   J.sv = single_segments(idx->size);

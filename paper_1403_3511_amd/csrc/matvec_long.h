@@ -88,13 +88,12 @@ template <> struct WinLoad<float> {
 //   h2_s = a3 (e_s u_{s-1} + e_{s+1} u_{s+1}) + a2 u_s + g2 v_s      (s = -2, 0, 2)
 //   h1_s = e_s h2_{s-1} + e_{s+1} h2_{s+1} + a1 u_s + g1 v_s          (s = -1, 1)
 //   G_l  = e_0 h1_{-1} + e_1 h1_1.
-// One row (offset o of the tile whose record is rec) of y = oscale (D + W) x - pcoef prev.
+// One row (offset o of the tile whose record is rec) of oscale (D + W) x - pcoef prev.
 template <typename T, int N, int NP, bool X2, bool SYM>
-__device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restrict__ hh,
-                                       const typename V2<T>::t *__restrict__ x,
-                                       typename V2<T>::t *__restrict__ y,
-                                       const int32_t *__restrict__ rec, int32_t o, T oscale,
-                                       const typename V2<T>::t *__restrict__ prev, T pcoef) {
+__device__ __forceinline__ typename V2<T>::t hh_row_value(const IndexDev &ix, const double *__restrict__ hh,
+                                                          const typename V2<T>::t *__restrict__ x,
+                                                          const int32_t *__restrict__ rec, int32_t o, T oscale,
+                                                          const typename V2<T>::t *__restrict__ prev, T pcoef) {
   using C = typename V2<T>::t;
   constexpr int D = N - NP;
   const __amdgpu_buffer_rsrc_t xr = vec_rsrc<T>(x, ix.size);
@@ -373,6 +372,18 @@ __device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restr
   });
   acc = scal<T>(oscale, acc);
   if (prev) fma_rc<T>(acc, -pcoef, pv);
+  return acc;
+}
+
+// The same row stored into y.
+template <typename T, int N, int NP, bool X2, bool SYM>
+__device__ __forceinline__ void hh_row(const IndexDev &ix, const double *__restrict__ hh,
+                                       const typename V2<T>::t *__restrict__ x,
+                                       typename V2<T>::t *__restrict__ y,
+                                       const int32_t *__restrict__ rec, int32_t o, T oscale,
+                                       const typename V2<T>::t *__restrict__ prev, T pcoef) {
+  const typename V2<T>::t acc = hh_row_value<T, N, NP, X2, SYM>(ix, hh, x, rec, o, oscale, prev, pcoef);
+  const uint32_t self = (uint32_t)rec[0] + (uint32_t)o;
   // the result is streamed to its consumers (inner products, update): non-temporal store
   if constexpr (sizeof(T) == 8) {
     typedef double v2 __attribute__((ext_vector_type(2)));

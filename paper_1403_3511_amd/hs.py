@@ -58,6 +58,9 @@ _SIGS = {
     "hs_pot_set_coeffs_device": [_vp, _vp, _vp, _vp],
     "hs_pot_set_form": [_vp, _i32],
     "hs_apply_x": [_vp, _vp, _i32, _i32, _vp, _vp, _vp],
+    "hs_propagate": [_vp, _vp, _vp, _vp, _i32, _f64, _vp, _f64, _i32, _i32, _i64, _vp, _vp, _vp],
+    "hs_set_small_step_rows": [_i64],
+    "hs_get_small_step_rows": [_pi64],
     "hs_workspace_bytes": [_vp, _vp, _i32, _i32, _pi64],
     "hs_apply_h": [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "hs_step": [_vp, _vp, _vp, _vp, _i32, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
@@ -312,6 +315,24 @@ def step(idx: Index, pot: Pot, c, t: float, h: float, m: int, dtype: int = HS_C1
         ws = workspace(idx, pot, dtype, m, c.device)
     hs_step(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, float(t), ptr(t_dev), float(h), int(m),
             1 if reorth else 0, ptr(c), ptr(ws), ptr(diag), stream_ptr())
+    return c
+
+
+def set_small_step_rows(rows: int) -> int:
+    """Set the row limit of the one-workgroup step; returns the previous limit."""
+    old = C.c_int64()
+    hs_get_small_step_rows(C.byref(old))
+    hs_set_small_step_rows(int(rows))
+    return old.value
+
+
+def propagate(idx: Index, pot: Pot, c, t0: float, h: float, m: int, nsteps: int, dtype: int = HS_C128,
+              reorth: bool = True, ws=None, t_dev=None):
+    """nsteps exponential-midpoint Lanczos steps in place on c (complex128 device tensor)."""
+    if ws is None:
+        ws = workspace(idx, pot, dtype, m, c.device)
+    hs_propagate(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, float(t0), ptr(t_dev), float(h), int(m),
+                 1 if reorth else 0, int(nsteps), ptr(c), ptr(ws), stream_ptr())
     return c
 
 

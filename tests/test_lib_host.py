@@ -224,6 +224,11 @@ def test_error_paths(hs):
     expect(-1, hs.hs_apply_x, idx.h, fkp, 0, 4, fkp, fkq, None)                # dtype
     expect(-1, hs.hs_apply_x, idx.h, fkp, 0, 0, fkp, fkp, None)                # in == out
     expect(-1, hs.hs_apply_x, idx.h, None, 0, 0, fkp, fkq, None)               # NULL metadata
+    expect(-1, hs.hs_set_small_step_rows, -1)                                 # negative limit
+    expect(-1, hs.hs_propagate, idx.h, fkp, pot2.h, fkp, 0, 0.0, None, 0.1, 4, 1, -1, fkp, fkq, None)  # nsteps < 0
+    expect(-1, hs.hs_propagate, idx.h, fkp, pot2.h, fkp, 0, 0.0, None, 0.1, 0, 1, 5, fkp, fkq, None)   # m < 1
+    expect(-7, hs.hs_propagate, idx.h, fkp, pot2.h, fkp, 0, 0.0, None, float("inf"), 4, 1, 5, fkp, fkq,
+           None)                                                                 # h not finite
     expect(-1, hs.hs_pot_set_form, pot2.h, 7)                                 # unknown form
     gz = np.zeros(5 * 3 * 5)
     gp = gz.ctypes.data_as(C.POINTER(C.c_double))
