@@ -162,8 +162,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus above 1 is not supported "
-              "(the sharded path is described but not built).", file=sys.stderr)
+        print("bench.py: runs on one GPU only; --gpus above 1 is not supported "
+              "(the sharded path is described but not implemented).", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
@@ -624,7 +624,7 @@ def learned_form(hs, stream, args):
     """Learned coefficients, N = 4: Gaussian wells on circles expanded in Hermite
     polynomials of total degree <= 6 (210 coefficients).  Targets from the Gauss-Hermite
     projection (Q = 16) of 4096 parameter draws; the 7-256-256-210 network trained with
-    Adam (batch 256); accuracy against a Q = 24 judge on 256 held-out draws; coefficient
+    Adam (batch 256); accuracy against a Q = 24 quadrature reference on 256 held-out draws; coefficient
     latency of network, quadrature and Chebyshev interpolation (degree 6 on [-4, 4]^4,
     the Chebyshev-basis potential of the same degrees); one propagation step at product
     bound 8192 with each coefficient source."""

@@ -1,6 +1,6 @@
 // Learned potential coefficients.
 //
-// (1) Gauss-Hermite projection (the fallback and the judge): for the potential family
+// (1) Gauss-Hermite projection (the fallback and the accuracy reference): for the potential family
 //     W(x) = - sum_i a_i exp(-|x - c_i(t)|^2 / (2 sigma^2)),
 //     c_i(t) = base_i + rho (cos(omega t + phi_i) u_i + sin(omega t + phi_i) w_i),
 //     alpha_a = <W, H_a> / <H_a, H_a> (weight exp(-|x|^2)) by the product Gauss-Hermite

@@ -188,16 +188,16 @@ def test_training_reduces_loss(trained):
 
 
 def test_surrogate_accuracy_and_gain(hs, trained):
-    """Held-out error of the network against the quadrature judge, and the time per
-    batch of coefficients: the network against the quadrature at the judge's Q and at
+    """Held-out error of the network against the quadrature reference, and the time per
+    batch of coefficients: the network against the quadrature at the reference's Q and at
     the smallest Q that is as accurate as the network."""
     import torch
     net, geom, D = trained["net"], trained["geom"], trained["D"]
     Pv = dev64(draw_surrogate_params(256, seed=12))
-    judge = hs.gh_project(geom, Pv, D, 24)
+    ref24 = hs.gh_project(geom, Pv, D, 24)
     pred = net.predict(Pv)
     torch.cuda.synchronize()
-    J = judge.cpu().numpy()
+    J = ref24.cpu().numpy()
     scale = np.linalg.norm(J, axis=1)
     e_mlp = float(np.median(np.linalg.norm(pred.cpu().numpy() - J, axis=1) / scale))
     errs = {}
@@ -215,7 +215,7 @@ def test_surrogate_accuracy_and_gain(hs, trained):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
-    out = torch.empty_like(judge)
+    out = torch.empty_like(ref24)
     t_mlp = timeit(lambda: net.predict(Pv, out=out))
     t_q16 = timeit(lambda: hs.gh_project(geom, Pv, D, 16, out=out))
     t_qm = timeit(lambda: hs.gh_project(geom, Pv, D, q_match, out=out))

@@ -332,3 +332,15 @@ def test_batched_draw_size_rule(hs):
     first = next(i for i, d in enumerate(plain) if hs.index_count(d["N"], d["B"]) > cap)
     assert ruled[:first] == plain[:first]
     assert ruled[first] != plain[first]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and says why, before
+    any device is touched."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
