@@ -322,3 +322,36 @@ def test_one_workgroup_step_zero_vector_and_limits(hs, step_path):
         got, _, _ = gpu_steps(hs, N, B, tt, c0, 0.0, h, 2, m)
         assert rel2(got, ref) <= 1e-12, limit
     hs.set_small_step_rows(1024)
+
+
+@pytest.mark.parametrize("m", [1, 2, 32])
+def test_one_workgroup_step_krylov_extremes(hs, step_path, m):
+    """m = 1 (one vector: the exponential of a 1x1 matrix), m = 2 and the largest m = 32 (four
+    chunks of inner products): the two step paths agree and match the oracle."""
+    import torch
+    if step_path != "one_workgroup":
+        pytest.skip("compares the two paths itself")
+    N, B, h = 3, 75, 0.01
+    tt = hh_workload(N, 0.111, 0.05)
+    idx = hs.Index(N, B)
+    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    ix = IndexSet(N, B)
+    lexpos = lib_to_lex(idx, N, B)
+    c0 = complex_normal_by_index(ix.k, 90 + m)
+    c0 /= np.linalg.norm(c0)
+    out = {}
+    for limit in (1024, 0):
+        hs.set_small_step_rows(limit)
+        c = torch.from_numpy(c0[lexpos].copy()).to("cuda")
+        ws = hs.workspace(idx, pot, 0, m)
+        for i in range(2):
+            hs.step(idx, pot, c, i * h, h, m, ws=ws)
+        torch.cuda.synchronize()
+        out[limit] = c.cpu().numpy()
+    hs.set_small_step_rows(1024)
+    assert rel2(out[1024], out[0]) <= 1e-13
+    got = np.empty_like(c0)
+    got[lexpos] = out[1024]
+    ref = oracle_steps(N, B, tt, c0, 0.0, h, 2, m)
+    # m = 1, 2 are poor propagators; the comparison is with the oracle's same poor step
+    assert rel2(got, ref) <= 1e-12
