@@ -195,33 +195,49 @@ __global__ void __launch_bounds__(kSegThreads)
 k_supdate(SegView sv, const typename CT<T>::t *__restrict__ V, int64_t stride, int lo, int k,
           int reorth, const typename CT<T>::t *__restrict__ W, typename CT<T>::t *__restrict__ Wout,
           double *__restrict__ part, const double *__restrict__ scall) {
+  using C = typename CT<T>::t;
   __shared__ double sh[kSegThreads / 64];
+  __shared__ double cre[kMaxM], cim[kMaxM];
   int inst, len;
   int64_t r0;
   sv.get(blockIdx.x, inst, r0, len);
   const double *sc = scall + (int64_t)inst * Scal::size;
-  if (sc[Scal::stop] != 0.0) return;
+  if (sc[Scal::stop] != 0.0) return;  // uniform over the block (one instance)
+  // projection coefficients with the stored vectors' scales folded in: d_q s_q over
+  // q = q0 .. q0 + cnt - 1 (reorth), or alpha_k s_k alone
+  const int q0 = reorth ? lo : k;
+  const int cnt = reorth ? k + 1 - lo : 1;
+  if ((int)threadIdx.x < cnt) {
+    const int q = q0 + threadIdx.x;
+    const double vs = vscale(sc, q);
+    cre[threadIdx.x] = (reorth ? sc[Scal::dre + q] : sc[Scal::alpha + k]) * vs;
+    cim[threadIdx.x] = reorth ? sc[Scal::dim + q] * vs : 0.0;
+  }
+  __syncthreads();
   double acc = 0.0;
   for (int i = threadIdx.x; i < len; i += blockDim.x) {
     const int64_t r = r0 + i;
-    const typename CT<T>::t wv = nt_ld(W + r);
+    const C wv = nt_ld(W + r);
     double wr = wv.x, wi = wv.y;
-    if (reorth) {
-      for (int q = lo; q <= k; ++q) {
-        const double vs = vscale(sc, q);
-        const double dr = sc[Scal::dre + q] * vs, di = sc[Scal::dim + q] * vs;
-        const typename CT<T>::t v = nt_ld(V + (int64_t)q * stride + r);
-        const double vr = v.x, vi = v.y;
-        wr -= dr * vr - di * vi;
-        wi -= dr * vi + di * vr;
+    // kDotChunk vectors per round, their loads issued together
+    for (int c0 = 0; c0 < cnt; c0 += kDotChunk) {
+      C v[kDotChunk];
+#pragma unroll
+      for (int q = 0; q < kDotChunk; ++q) {
+        if (c0 + q < cnt) v[q] = nt_ld(V + (int64_t)(q0 + c0 + q) * stride + r);
+        else v[q].x = v[q].y = T(0);
       }
-    } else {
-      const double a = sc[Scal::alpha + k] * vscale(sc, k);
-      const typename CT<T>::t v = nt_ld(V + (int64_t)k * stride + r);
-      wr -= a * (double)v.x;
-      wi -= a * (double)v.y;
+#pragma unroll
+      for (int q = 0; q < kDotChunk; ++q) {
+        if (c0 + q < cnt) {
+          const double dr = cre[c0 + q], di = cim[c0 + q];
+          const double vr = v[q].x, vi = v[q].y;
+          wr -= dr * vr - di * vi;
+          wi -= dr * vi + di * vr;
+        }
+      }
     }
-    typename CT<T>::t o;
+    C o;
     o.x = (T)wr;
     o.y = (T)wi;
     Wout[r] = o;
