@@ -62,6 +62,7 @@ extern "C" {
 #define HS_SET_BOX 1          /* {0..K}^N (K_full)                                          */
 #define HS_SET_TOTAL_DEGREE 2 /* |k|_1 <= D                                                 */
 #define HS_SET_LIST 3         /* an explicit downward-closed set                            */
+#define HS_SET_PADDED 4       /* prod(1 + max(k_l - w, 0)) <= B: the cross widened by w     */
 
 #define HS_FORM_PAPER 0 /* the fast operator F: factors applied axis N first (eq. Horner)   */
 #define HS_FORM_SYM 1   /* its symmetric part D + (F + F_rev)/2 (see hs_pot_set_form)     */
@@ -119,8 +120,17 @@ int32_t hs_index_create_total_degree(int32_t N, int64_t D, int32_t tile_dim, hs_
  * the H application runs the generic row kernels: the same operator, without the
  * specialised gathers.  Paper's operator form only.                                 */
 int32_t hs_index_create_from_list(int32_t N, int64_t n, const uint16_t *k_host, hs_index *out);
+/* Padded crosses {k : prod(1 + max(k_l - w, 0)) <= B}: the hyperbolic cross K_N(B)
+ * widened by w in every axis (it contains every k + d with k in K_N(B), |d_l| <= w), in
+ * the tiled layout with suffixes graded by the same product.  With w at least the
+ * largest per-axis degree of a potential, no intermediate index of the fast algorithm's
+ * product between two rows of K_N(B) leaves it, so on those rows the fast algorithm on
+ * the padded cross is the exact Galerkin product of K_N(B) (see hs_error_split).
+ * 1 <= B, B + w <= 65536, w <= 16, fewer than 2^31 rows.  Paper's operator form.   */
+int32_t hs_index_create_padded(int32_t N, int64_t B, int64_t w, int32_t tile_dim, hs_index *out);
 /* map_host[r] = the row of box that holds row r's multi-index of sub (sub->size int32),
- * -1 when it lies outside the box.  HS_E_UNSUPPORTED when box is not a box set.      */
+ * -1 when it lies outside.  box: a box set or a padded cross (HS_E_UNSUPPORTED
+ * otherwise).                                                                        */
 int32_t hs_index_embed(hs_index sub, hs_index box, int32_t *map_host);
 
 /* ---- potential (paper Sec. 1.3; W = V - |x|^2/2, Sec. 1.2) ---------------------
@@ -248,7 +258,11 @@ int32_t hs_step_magnus4(hs_index idx, const void *idx_dev, hs_pot pot, void *pot
  * restricted to sub is the exact Galerkin product W_{K,pol} v.  pad may be NULL (then
  * e_quad is not written).  box_map / pad_map: hs_index_embed(sub, box / pad), uploaded
  * (device int32, sub->size).  The paper's operator form only.  ws holds
- * hs_error_split_workspace_bytes bytes.                                              */
+ * hs_error_split_workspace_bytes bytes.
+ * At scale, where no box fits: for a hyperbolic cross sub = K_N(B), box may be the
+ * padded cross of the same B widened by w >= the largest per-axis degree, with pad
+ * NULL.  Then e_red = W^pol(X_K) v - W_{K,pol} v, the whole gap between the fast
+ * algorithm and the exact Galerkin product on K (= E^red - E^quad of the box form).    */
 int32_t hs_error_split_workspace_bytes(hs_index sub, hs_index box, hs_index pad, hs_pot pot, int64_t *bytes);
 int32_t hs_error_split(hs_index sub, const void *sub_dev, hs_index box, const void *box_dev,
                        const int32_t *box_map_dev, hs_index pad, const void *pad_dev,

@@ -185,6 +185,34 @@ class TotalDegreeIndex:
         return np.array([self._pos[tuple(int(x) for x in row)] for row in np.atleast_2d(k)], dtype=np.int64)
 
 
+class PaddedIndex:
+    """The padded cross {k : prod(1 + max(k_l - w, 0)) <= B} (the hyperbolic cross of Sec. 1.2
+    widened by w in every axis: it holds every k + d with k in K_N(B) and |d_l| <= w) in
+    lex order, with neighbour maps and rank, same interface as IndexSet.  Enumerated by
+    brute force over the box {0..B-1+w}^N, so for small sets only."""
+
+    def __init__(self, N: int, B: int, w: int):
+        self.N, self.B, self.w = N, B, w
+        grid = np.indices((B + w,) * N).reshape(N, -1).T
+        cost = np.prod(1 + np.maximum(grid - w, 0), axis=1)
+        self.k = grid[cost <= B].astype(np.uint16)   # lex order (last axis fastest)
+        self.size = self.k.shape[0]
+        self._pos = {tuple(int(x) for x in row): i for i, row in enumerate(self.k)}
+        self.nbr_plus = np.full((N, self.size), -1, dtype=np.int64)
+        self.nbr_minus = np.full((N, self.size), -1, dtype=np.int64)
+        for i, row in enumerate(self.k):
+            for l in range(N):
+                m = [int(x) for x in row]
+                m[l] += 1
+                self.nbr_plus[l, i] = self._pos.get(tuple(m), -1)
+                m[l] -= 2
+                if m[l] >= 0:
+                    self.nbr_minus[l, i] = self._pos[tuple(m)]
+
+    def rank(self, k: np.ndarray) -> np.ndarray:
+        return np.array([self._pos[tuple(int(x) for x in row)] for row in np.atleast_2d(k)], dtype=np.int64)
+
+
 class ListIndex:
     """An explicit downward-closed set given by its rows (sorted lexicographically here),
     with neighbour maps and rank, same interface as IndexSet."""

@@ -86,20 +86,27 @@ extern "C" int32_t hs_error_split(hs_index sub, const void *sub_dev, hs_index bo
     return hs::fail(HS_E_INVALID, "hs_error_split: padded box given without its buffers");
   if (v == e_red || (pad && (v == e_quad || e_quad == e_red)))
     return hs::fail(HS_E_INVALID, "hs_error_split: v, e_quad and e_red must be distinct buffers");
-  if (box->kind != HS_SET_BOX || (pad && pad->kind != HS_SET_BOX))
-    return hs::fail(HS_E_INVALID, "hs_error_split: box and pad must be box sets");
+  int maxdeg = 0;
+  for (uint16_t a : pot->deg) maxdeg = std::max<int>(maxdeg, a);
+  // a padded cross in place of the box: e_red becomes the gap to the exact Galerkin product
+  const bool gap = box->kind == HS_SET_PADDED;
+  if (gap) {
+    if (pad) return hs::fail(HS_E_INVALID, "hs_error_split: with a padded cross in place of the box, pad must be NULL");
+    if (sub->kind != HS_SET_HYPERBOLIC || box->B - box->deg != sub->B)
+      return hs::fail(HS_E_INVALID, "hs_error_split: the padded cross must widen the set (same product bound)");
+    if (box->deg < maxdeg)
+      return hs::fail(HS_E_INVALID, "hs_error_split: the padded cross must be widened by the largest per-axis degree");
+  } else if (box->kind != HS_SET_BOX || (pad && pad->kind != HS_SET_BOX)) {
+    return hs::fail(HS_E_INVALID, "hs_error_split: box and pad must be box sets (or box a padded cross)");
+  }
   if (sub->N != pot->N || box->N != pot->N || (pad && pad->N != pot->N))
     return hs::fail(HS_E_INVALID, "hs_error_split: sets and potential differ in N");
   if (pad && pad->kmax < box->kmax) return hs::fail(HS_E_INVALID, "hs_error_split: the padded box is smaller than the box");
   if (pot->form != HS_FORM_PAPER) return hs::fail(HS_E_UNSUPPORTED, "hs_error_split: the paper's operator form only");
   // the box must contain the set: its largest coordinate is B - 1 (coordinates stay below B)
-  if (sub->B - 1 > box->kmax) return hs::fail(HS_E_INVALID, "hs_error_split: the box does not contain the set");
-  if (pad) {
-    int maxdeg = 0;
-    for (uint16_t a : pot->deg) maxdeg = std::max<int>(maxdeg, a);
-    if (pad->kmax - box->kmax < (maxdeg + 1) / 2)
-      return hs::fail(HS_E_INVALID, "hs_error_split: the padded box must exceed the box by half the largest degree");
-  }
+  if (!gap && sub->B - 1 > box->kmax) return hs::fail(HS_E_INVALID, "hs_error_split: the box does not contain the set");
+  if (pad && pad->kmax - box->kmax < (maxdeg + 1) / 2)
+    return hs::fail(HS_E_INVALID, "hs_error_split: the padded box must exceed the box by half the largest degree");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const hs::DiagLayout L = hs::diag_layout(sub, box, pad, pot);
   uint8_t *w8 = static_cast<uint8_t *>(ws);

@@ -97,7 +97,8 @@ struct hs_index_s {
   int32_t N = 0, d = 0, np = 0;
   int64_t B = 0, size = 0, ntiles = 0, ng = 0;
   int32_t kind = HS_SET_HYPERBOLIC;   // HS_SET_BOX: {0..kmax}^N; HS_SET_TOTAL_DEGREE: |k|_1 <= deg;
-                                      // HS_SET_LIST: an explicit downward-closed set
+                                      // HS_SET_LIST: an explicit downward-closed set;
+                                      // HS_SET_PADDED: prod(1 + max(k - deg, 0)) <= B - deg
   int64_t kmax = 0, deg = 0;
   std::shared_ptr<struct ListSet> list;  // HS_SET_LIST rows (index.cpp)
   std::vector<uint16_t> tpfx;

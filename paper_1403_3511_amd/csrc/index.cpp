@@ -36,14 +36,19 @@ namespace {
 
 constexpr int64_t kSat = INT64_C(1) << 62;
 
-// |K_n(b)| for every b in the set {floor(B / q)} that division keeps reaching.
+// Coordinate cost of the product-bound sets: 1 + k on the hyperbolic cross, and on the
+// padded cross 1 + max(k - w, 0), so that the values 0..w all cost 1.
+inline int64_t pcost(int64_t k, int64_t w) { return 1 + (k > w ? k - w : 0); }
+
+// |K_n(b)| for every b in the set {floor(B / q)} that division keeps reaching (with pad
+// width w: the padded cross prod(1 + max(k_l - w, 0)) <= b).
 struct Counter {
-  int64_t B = 0;
+  int64_t B = 0, w = 0;
   int nmax = 0;
   std::vector<int32_t> slot;                 // b -> position in vals (-1: unreachable)
   std::vector<int64_t> vals;                 // reachable bounds, ascending
   std::vector<std::vector<int64_t>> cnt;     // cnt[n][slot]
-  Counter(int64_t B_, int nmax_) : B(B_), nmax(nmax_), slot(B_ + 1, -1) {
+  Counter(int64_t B_, int nmax_, int64_t w_ = 0) : B(B_), w(w_), nmax(nmax_), slot(B_ + 1, -1) {
     for (int64_t q = 1; q <= B; ++q) {
       int64_t b = B / q;
       if (slot[b] < 0) slot[b] = 0;
@@ -69,6 +74,8 @@ struct Counter {
           if (s > kSat) s = kSat;
           a = a2 + 1;
         }
+        // the w further values of cost 1 on the padded cross
+        if (w > 0) s = std::min<int64_t>(kSat, s + w * cnt[n - 1][slot[b]]);
         cnt[n][i] = s;
       }
   }
@@ -80,7 +87,7 @@ struct LexRank {
   const Counter *C;
   int n;
   int64_t B;
-  // cum[i][slot(b)][a] = sum_{a' < a} |K_{n-1-i}(floor(b / (1 + a')))|
+  // cum[i][slot(b)][a] = sum_{a' < a} |K_{n-1-i}(floor(b / cost(a')))|
   std::vector<std::vector<std::vector<int64_t>>> cum;
   LexRank(const Counter *C_, int n_, int64_t B_) : C(C_), n(n_), B(B_) {
     cum.resize(n);
@@ -89,36 +96,37 @@ struct LexRank {
       for (size_t si = 0; si < C->vals.size(); ++si) {
         int64_t b = C->vals[si];
         auto &v = cum[i][si];
-        v.resize(b + 1);
+        v.resize(b + C->w + 1);  // values 0 .. b - 1 + w have cost <= b
         v[0] = 0;
-        for (int64_t a = 0; a < b; ++a) v[a + 1] = v[a] + C->count(n - 1 - i, b / (1 + a));
+        for (int64_t a = 0; a < b + C->w; ++a) v[a + 1] = v[a] + C->count(n - 1 - i, b / pcost(a, C->w));
       }
     }
   }
-  // k must be a member of K_n(B)
+  // k must be a member
   int64_t rank(const int32_t *k) const {
     int64_t r = 0, b = B;
     for (int i = 0; i < n; ++i) {
       r += cum[i][C->slot[b]][k[i]];
-      b /= (1 + k[i]);
+      b /= pcost(k[i], C->w);
     }
     return r;
   }
 };
 
-bool member(const int32_t *k, int n, int64_t B) {
+bool member(const int32_t *k, int n, int64_t B, int64_t w = 0) {
   int64_t p = 1;
   for (int i = 0; i < n; ++i) {
     if (k[i] < 0) return false;
-    p *= (1 + k[i]);
+    p *= pcost(k[i], w);
     if (p > B) return false;
   }
   return true;
 }
 
-// Lexicographic enumeration of K_n(B): calls f(k) for each member.
+// Lexicographic enumeration of K_n(B) (with pad width w: of the padded cross): calls f(k)
+// for each member.
 template <class F>
-void enumerate(int n, int64_t B, F &&f) {
+void enumerate(int n, int64_t B, F &&f, int64_t w = 0) {
   std::vector<int32_t> k(n, 0);
   if (n == 0) {
     f(k.data());
@@ -131,12 +139,12 @@ void enumerate(int n, int64_t B, F &&f) {
   while (true) {
     // descend with zeros
     for (; lvl < n - 1; ++lvl) {
-      bound[lvl + 1] = bound[lvl] / (1 + k[lvl]);
+      bound[lvl + 1] = bound[lvl] / pcost(k[lvl], w);
       k[lvl + 1] = 0;
     }
     // at the last level run over all admissible values
     int64_t b = bound[n - 1];
-    for (int32_t a = 0; a < b; ++a) {
+    for (int32_t a = 0; a < b + w; ++a) {
       k[n - 1] = a;
       f(k.data());
     }
@@ -144,7 +152,7 @@ void enumerate(int n, int64_t B, F &&f) {
     int up = n - 2;
     while (up >= 0) {
       k[up] += 1;
-      if (1 + k[up] <= bound[up]) break;
+      if (pcost(k[up], w) <= bound[up]) break;
       --up;
     }
     if (up < 0) return;
@@ -205,13 +213,17 @@ struct SetOps {
   int64_t B = 0, K = 0, D = 0;
   std::unique_ptr<Counter> C;
   const ListSet *L = nullptr;
+  // B: product bound (hyperbolic and padded); K: box edge; D: total degree, or the pad
+  // width w of the padded cross
   SetOps(int kind_, int64_t B_, int64_t K_, int64_t D_, int N, const ListSet *L_ = nullptr)
       : kind(kind_), B(B_), K(K_), D(D_), L(L_) {
-    if (kind == HS_SET_HYPERBOLIC) C.reset(new Counter(B, N));
+    if (product()) C.reset(new Counter(B, N, pad()));
   }
+  bool product() const { return kind == HS_SET_HYPERBOLIC || kind == HS_SET_PADDED; }
+  int64_t pad() const { return kind == HS_SET_PADDED ? D : 0; }
   int64_t count(int n) const {
     if (kind == HS_SET_LIST) return n == 0 ? 1 : (int64_t)L->pos.size();
-    if (kind == HS_SET_HYPERBOLIC) return C->count(n, B);
+    if (product()) return C->count(n, B);
     if (kind == HS_SET_TOTAL_DEGREE) return simplex_count(n, D);
     int64_t r = 1;
     for (int i = 0; i < n; ++i) r = std::min<int64_t>(r * (K + 1), kSat);
@@ -224,7 +236,7 @@ struct SetOps {
         if (k[i] < 0 || k[i] > 65535) return false;
       return L->pos.count(ListSet::key(k, n)) > 0;
     }
-    if (kind == HS_SET_HYPERBOLIC) return ::member(k, n, B);
+    if (product()) return ::member(k, n, B, pad());
     int64_t sum = 0;
     for (int i = 0; i < n; ++i) {
       if (k[i] < 0 || (kind == HS_SET_BOX && k[i] > K)) return false;
@@ -248,15 +260,15 @@ struct SetOps {
     }
     if (kind == HS_SET_BOX) enumerate_box(n, K, f);
     else if (kind == HS_SET_TOTAL_DEGREE) enumerate_simplex(n, D, f);
-    else enumerate(n, B, f);
+    else enumerate(n, B, f, pad());
   }
   int64_t grade(const int32_t *s, int d) const {
     if (kind == HS_SET_BOX || kind == HS_SET_LIST) return 0;
-    int64_t g = kind == HS_SET_HYPERBOLIC ? 1 : 0;
-    for (int a = 0; a < d; ++a) g = kind == HS_SET_HYPERBOLIC ? g * (1 + s[a]) : g + s[a];
+    int64_t g = product() ? 1 : 0;
+    for (int a = 0; a < d; ++a) g = product() ? g * pcost(s[a], pad()) : g + s[a];
     return g;
   }
-  int64_t max_grade() const { return kind == HS_SET_HYPERBOLIC ? B : (kind == HS_SET_TOTAL_DEGREE ? D : 0); }
+  int64_t max_grade() const { return product() ? B : (kind == HS_SET_TOTAL_DEGREE ? D : 0); }
   // largest suffix grade that fits after prefix p
   int64_t budget(const int32_t *p, int np) const {
     if (kind == HS_SET_BOX || kind == HS_SET_LIST) return 0;
@@ -266,7 +278,7 @@ struct SetOps {
       return D - sum;
     }
     int64_t prod = 1;
-    for (int i = 0; i < np; ++i) prod *= 1 + p[i];
+    for (int i = 0; i < np; ++i) prod *= pcost(p[i], pad());
     return B / prod;
   }
 };
@@ -277,11 +289,11 @@ struct Ranker {
   int n;
   std::unique_ptr<LexRank> R;
   Ranker(const SetOps *S_, int n_) : S(S_), n(n_) {
-    if (S->kind == HS_SET_HYPERBOLIC) R.reset(new LexRank(S->C.get(), n, S->B));
+    if (S->product()) R.reset(new LexRank(S->C.get(), n, S->B));
   }
   int64_t rank(const int32_t *k) const {
     if (S->kind == HS_SET_LIST) return n == 0 ? 0 : S->L->pos.at(ListSet::key(k, n));
-    if (S->kind == HS_SET_HYPERBOLIC) return R->rank(k);
+    if (S->product()) return R->rank(k);
     int64_t r = 0;
     if (S->kind == HS_SET_BOX) {
       for (int i = 0; i < n; ++i) r = r * (S->K + 1) + k[i];
@@ -334,12 +346,19 @@ hs::IndexDev hs_index_s::view(const void *dev) const {
   return v;
 }
 
+// The set operations of an index handle (padded crosses keep B = product bound + w as
+// their coordinate bound, and w in deg).
+static SetOps set_ops(const hs_index_s *ix) {
+  const int64_t pb = ix->kind == HS_SET_PADDED ? ix->B - ix->deg : ix->B;
+  return SetOps(ix->kind, pb, ix->kmax, ix->deg, ix->N, ix->list.get());
+}
+
 static int32_t default_tile_dim(int32_t N) { return N <= 2 ? N : (N <= 4 ? 2 : (N <= 8 ? 3 : 4)); }
 
 static int32_t build_index(hs_index_s *ix) {
   const int N = ix->N, d = ix->d, np = ix->np;
-  const int64_t B = ix->B;
-  const SetOps S(ix->kind, B, ix->kmax, ix->deg, N, ix->list.get());
+  const int64_t B = ix->B;  // coordinates stay below B (weight tables)
+  const SetOps S = set_ops(ix);
   const int64_t total = S.count(N);
   if (total >= (INT64_C(1) << 31) - 1) return hs::fail(HS_E_OVERFLOW, "index set has 2^31 or more rows");
   const int64_t ntiles = S.count(np);
@@ -662,6 +681,39 @@ extern "C" int32_t hs_index_create_box(int32_t N, int64_t Kmax, int32_t tile_dim
   return HS_OK;
 }
 
+extern "C" int32_t hs_index_create_padded(int32_t N, int64_t B, int64_t w, int32_t tile_dim, hs_index *out) {
+  if (!out) return hs::fail(HS_E_INVALID, "hs_index_create_padded: out is NULL");
+  *out = nullptr;
+  if (N < 1 || N > HS_NMAX) return hs::fail(HS_E_INVALID, "hs_index_create_padded: N out of range 1..16");
+  if (w < 0 || w > 16) return hs::fail(HS_E_INVALID, "hs_index_create_padded: w out of range 0..16");
+  if (B < 1 || B + w > 65536) return hs::fail(HS_E_INVALID, "hs_index_create_padded: need 1 <= B and B + w <= 65536");
+  if (tile_dim < 0 || tile_dim > N) return hs::fail(HS_E_INVALID, "hs_index_create_padded: tile_dim out of range 0..N");
+  {
+    Counter C(B, N, w);
+    if (C.count(N, B) >= (INT64_C(1) << 31) - 1) return hs::fail(HS_E_OVERFLOW, "hs_index_create_padded: 2^31 or more rows");
+  }
+  hs_index_s *ix = new (std::nothrow) hs_index_s();
+  if (!ix) return hs::fail(HS_E_NOMEM, "hs_index_create_padded: out of host memory");
+  ix->N = N;
+  ix->kind = HS_SET_PADDED;
+  ix->deg = w;
+  ix->B = B + w;  // coordinates stay below B + w
+  ix->d = tile_dim ? tile_dim : default_tile_dim(N);
+  ix->np = N - ix->d;
+  int32_t st;
+  try {
+    st = build_index(ix);
+  } catch (const std::bad_alloc &) {
+    st = hs::fail(HS_E_NOMEM, "hs_index_create_padded: out of host memory");
+  }
+  if (st != HS_OK) {
+    delete ix;
+    return st;
+  }
+  *out = ix;
+  return HS_OK;
+}
+
 extern "C" int32_t hs_index_create_total_degree(int32_t N, int64_t D, int32_t tile_dim, hs_index *out) {
   if (!out) return hs::fail(HS_E_INVALID, "hs_index_create_total_degree: out is NULL");
   *out = nullptr;
@@ -755,20 +807,35 @@ extern "C" int32_t hs_index_create_from_list(int32_t N, int64_t n, const uint16_
 
 extern "C" int32_t hs_index_embed(hs_index sub, hs_index box, int32_t *map_host) {
   if (!sub || !box || !map_host) return hs::fail(HS_E_INVALID, "hs_index_embed: NULL argument");
-  if (box->kind != HS_SET_BOX) return hs::fail(HS_E_UNSUPPORTED, "hs_index_embed: the target must be a box set");
+  if (box->kind != HS_SET_BOX && box->kind != HS_SET_PADDED)
+    return hs::fail(HS_E_UNSUPPORTED, "hs_index_embed: the target must be a box set or a padded cross");
   if (sub->N != box->N) return hs::fail(HS_E_INVALID, "hs_index_embed: the sets differ in N");
   const int N = sub->N, np = box->np, d = box->d;
-  const int64_t K1 = box->kmax + 1;
-  std::vector<uint16_t> k((size_t)sub->size * N);
-  hs_index_multi_indices(sub, k.data());
-  for (int64_t r = 0; r < sub->size; ++r) {
-    const uint16_t *m = k.data() + (size_t)r * N;
-    int64_t t = 0, o = 0;
-    bool in = true;
-    for (int i = 0; i < N; ++i) in = in && m[i] <= box->kmax;
-    for (int i = 0; i < np; ++i) t = t * K1 + m[i];
-    for (int a = 0; a < d; ++a) o = o * K1 + m[np + a];
-    map_host[r] = in ? (int32_t)(box->tstart[t] + o) : -1;
+  try {
+    // row of a multi-index in the target: tile = lexicographic rank of the prefix among
+    // the target's prefixes, offset = position of the suffix in the graded suffix list
+    const SetOps S = set_ops(box);
+    const Ranker Rp(&S, np), Rs(&S, d);
+    std::vector<int64_t> off_of_lex(box->ng, -1);
+    std::vector<int32_t> m(N);
+    for (int64_t g = 0; g < box->ng; ++g) {
+      for (int a = 0; a < d; ++a) m[a] = box->gsidx[g * d + a];
+      off_of_lex[Rs.rank(m.data())] = g;
+    }
+    std::vector<uint16_t> k((size_t)sub->size * N);
+    hs_index_multi_indices(sub, k.data());
+    for (int64_t r = 0; r < sub->size; ++r) {
+      for (int i = 0; i < N; ++i) m[i] = k[(size_t)r * N + i];
+      if (!S.member(m.data(), N)) {
+        map_host[r] = -1;
+        continue;
+      }
+      const int64_t t = Rp.rank(m.data());
+      const int64_t o = off_of_lex[Rs.rank(m.data() + np)];
+      map_host[r] = (int32_t)(box->tstart[t] + o);
+    }
+  } catch (const std::bad_alloc &) {
+    return hs::fail(HS_E_NOMEM, "hs_index_embed: out of host memory");
   }
   return HS_OK;
 }

@@ -26,6 +26,7 @@ HS_OK, HS_INFO_BREAKDOWN = 0, 1
 HS_C128, HS_C64 = 0, 1
 HS_BASIS_MONO, HS_BASIS_CHEB, HS_BASIS_HERM = 0, 1, 2
 HS_FORM_PAPER, HS_FORM_SYM = 0, 1
+HS_SET_HYPERBOLIC, HS_SET_BOX, HS_SET_TOTAL_DEGREE, HS_SET_LIST, HS_SET_PADDED = 0, 1, 2, 3, 4
 BASIS = {"mono": HS_BASIS_MONO, "cheb": HS_BASIS_CHEB, "herm": HS_BASIS_HERM}
 
 _vp, _i32, _i64, _f64, _f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_float
@@ -61,6 +62,7 @@ _SIGS = {
     "hs_propagate": [_vp, _vp, _vp, _vp, _i32, _f64, _vp, _f64, _i32, _i32, _i64, _vp, _vp, _vp],
     "hs_set_small_step_rows": [_i64],
     "hs_get_small_step_rows": [_pi64],
+    "hs_index_create_padded": [_i32, _i64, _i64, _i32, C.POINTER(_vp)],
     "hs_workspace_bytes": [_vp, _vp, _i32, _i32, _pi64],
     "hs_apply_h": [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "hs_step": [_vp, _vp, _vp, _vp, _i32, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
@@ -163,12 +165,14 @@ class Index:
     """Host handle + uploaded device block of K_N(B)."""
 
     def __init__(self, N: int, B: int = 0, tile_dim: int = 0, device="cuda", upload=True, box: bool = False,
-                 total_degree: bool = False, rows=None):
+                 total_degree: bool = False, rows=None, pad: int = None):
         """The hyperbolic cross prod(1 + k_l) <= B; with box=True the box {0..B}^N; with
         total_degree=True the set |k|_1 <= B; with rows (n x N integers) that explicit
-        downward-closed set."""
+        downward-closed set; with pad=w the padded cross prod(1 + max(k_l - w, 0)) <= B."""
         h = _vp()
-        if rows is not None:
+        if pad is not None:
+            hs_index_create_padded(N, B, int(pad), tile_dim, C.byref(h))
+        elif rows is not None:
             k = np.ascontiguousarray(np.asarray(rows, dtype=np.uint16).reshape(-1, N))
             hs_index_create_from_list(N, k.shape[0], k.ctypes.data_as(_pu16), C.byref(h))
         else:

@@ -9,7 +9,7 @@ import pytest
 
 from oracle.index import BoxIndex, IndexSet
 from oracle.operators import (error_split, exact_W_separable, fast_apply_H, torsional_potential)
-from synth import complex_normal_by_index, decay_vector
+from synth import coherent_state, complex_normal_by_index, decay_vector
 from tests.hsutil import hh_workload, lib_terms, lib_to_lex, oracle_W, rel2
 
 pytestmark = pytest.mark.gpu
@@ -123,3 +123,69 @@ def test_error_split_on_the_box_itself(hs):
     torch.cuda.synchronize()
     assert float(er.abs().max()) == 0.0
     assert float(eq.abs().max()) > 0.0
+
+
+@pytest.mark.parametrize("N,B,w,d", [(2, 24, 3, 0), (3, 12, 3, 0), (3, 12, 3, 1), (4, 10, 4, 0)])
+def test_galerkin_gap_on_a_padded_cross(hs, N, B, w, d):
+    """e_red with a padded cross in place of the box: F_K v - (D + W_K) v, against the
+    oracle's fast product minus the densely assembled exact Galerkin product, and the
+    padded cross's H application against the oracle's fast algorithm on the same set."""
+    import torch
+    from oracle.index import PaddedIndex
+    from oracle.operators import dense_H
+    tt = hh_workload(N, 0.111, 0.05)
+    W = oracle_W(N, tt, 0.3)
+    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    pot.set_time(0.3)
+    sub = hs.Index(N, B)
+    P = hs.Index(N, B, d, pad=w)
+    ix = IndexSet(N, B)
+    lexpos = lib_to_lex(sub, N, B)
+    v_lex = complex_normal_by_index(ix.k, 5)
+    v = torch.from_numpy(np.ascontiguousarray(v_lex[lexpos])).to("cuda")
+    _, gap = hs.error_split(sub, P, None, pot, v)
+    torch.cuda.synchronize()
+    got = np.empty_like(v_lex)
+    got[lexpos] = gap.cpu().numpy()
+    exact = dense_H(ix.k, W) @ v_lex
+    ref = fast_apply_H(ix, W, v_lex) - exact
+    assert np.linalg.norm(ref) > 1e-6 * np.linalg.norm(exact)        # the gap is there
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(exact)
+    # H on the padded cross itself, every row
+    PO = PaddedIndex(N, B, w)
+    pos = PO.rank(P.multi_indices().astype(np.int64))
+    x = complex_normal_by_index(PO.k, 6)
+    xl = torch.from_numpy(np.ascontiguousarray(x[pos])).to("cuda")
+    yl = torch.empty_like(xl)
+    hs.apply_h(P, pot, xl, yl)
+    y = np.empty_like(x)
+    y[pos] = yl.cpu().numpy()
+    assert rel2(y, fast_apply_H(PO, W, x)) <= 1e-12
+
+
+def test_galerkin_gap_independent_of_the_widening(hs):
+    """N = 6, B = 512 (208,280 rows): widened by 3 (18.5M rows) and by 4 (43.3M rows) the
+    padded crosses give the same exact product on K, so the same gap; refusals of a cross
+    that is too narrow or of another bound."""
+    import torch
+    N, B = 6, 512
+    tt = hh_workload(N, 0.111, 0.05)
+    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    sub = hs.Index(N, B)
+    c = coherent_state(sub.multi_indices(), 1.0)
+    v = torch.from_numpy(c / np.linalg.norm(c)).to("cuda")
+    y = torch.empty_like(v)
+    hs.apply_h(sub, pot, v, y)
+    gaps = []
+    for w in (3, 4):
+        P = hs.Index(N, B, pad=w)
+        print("padded cross w", w, "rows", P.size, flush=True)
+        _, g = hs.error_split(sub, P, None, pot, v)
+        gaps.append(g.clone())
+        del P
+    torch.cuda.synchronize()
+    assert float(torch.linalg.norm(gaps[0])) > 1e-8 * float(torch.linalg.norm(y))
+    assert float(torch.linalg.norm(gaps[0] - gaps[1])) <= 1e-13 * float(torch.linalg.norm(y))
+    for bad in (hs.Index(N, B, pad=2), hs.Index(N, B + 1, pad=3)):
+        with pytest.raises(hs.HSError):
+            hs.error_split(sub, bad, None, pot, v)

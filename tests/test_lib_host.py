@@ -344,3 +344,45 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+@pytest.mark.parametrize("N,B,w,d", [(1, 10, 2, 0), (2, 24, 3, 0), (3, 12, 3, 0), (3, 12, 3, 1), (4, 10, 2, 0),
+                                     (4, 10, 1, 4)])
+def test_padded_index_matches_oracle(hs, N, B, w, d):
+    """The library's padded cross is the oracle's set, with graded tiles, and every row of
+    the hyperbolic cross embeds at the padded row holding its multi-index (as do box
+    embeddings, through the same ranking)."""
+    from oracle.index import PaddedIndex
+    P = hs.Index(N, B, d, upload=False, pad=w)
+    ref = PaddedIndex(N, B, w)
+    k = P.multi_indices().astype(np.int64)
+    assert P.size == ref.size
+    assert sorted(map(tuple, k)) == sorted(map(tuple, ref.k.astype(np.int64)))
+    dd = P.tile_dim
+    pre, suf = k[:, :N - dd], k[:, N - dd:]
+    keys = [tuple(p) for p in pre]
+    starts = [0] + [i for i in range(1, len(keys)) if keys[i] != keys[i - 1]]
+    for a, b in zip(starts, starts[1:] + [len(keys)]):
+        g = [(int(np.prod(1 + np.maximum(s - w, 0))), tuple(s)) for s in suf[a:b]]
+        assert g == sorted(g)
+    sub = hs.Index(N, B, upload=False)
+    mp = sub.embed_map(P)
+    ks = sub.multi_indices().astype(np.int64)
+    assert np.all(mp >= 0)
+    assert np.array_equal(k[mp], ks)
+    box = hs.Index(N, w + 2, upload=False, box=True)
+    mb = sub.embed_map(box)
+    inside = np.all(ks <= w + 2, axis=1)
+    assert np.array_equal(mb >= 0, inside)
+    assert np.array_equal(box.multi_indices().astype(np.int64)[mb[inside]], ks[inside])
+
+
+def test_padded_index_errors(hs):
+    h = C.c_void_p()
+    for args in ((0, 10, 2, 0), (3, 0, 2, 0), (3, 65535, 2, 0), (3, 10, -1, 0), (3, 10, 17, 0), (3, 10, 2, 4)):
+        with pytest.raises(hs.HSError):
+            hs.hs_index_create_padded(*args, C.byref(h))
+    sub = hs.Index(3, 10, upload=False)
+    tot = hs.Index(3, 5, upload=False, total_degree=True)
+    with pytest.raises(hs.HSError):
+        sub.embed_map(tot)   # a total-degree target has no embedding

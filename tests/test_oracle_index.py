@@ -113,3 +113,36 @@ def test_total_degree_index():
             m = ix.nbr_minus[l]
             assert np.array_equal(m >= 0, k[:, l] > 0)
         assert np.array_equal(ix.rank(k), np.arange(ix.size))
+
+
+@pytest.mark.parametrize("N,B,w", [(1, 10, 2), (2, 20, 3), (3, 12, 1), (3, 8, 3)])
+def test_padded_index(N, B, w):
+    """The padded cross prod(1 + max(k_l - w, 0)) <= B: w = 0 gives the hyperbolic cross;
+    it contains every k + d with k in K_N(B) and |d_l| <= w; it is downward closed; its
+    size follows the recursion in the first coordinate (values 0..w cost 1, value w + a
+    costs 1 + a); the neighbour maps are those of brute force."""
+    from oracle.index import PaddedIndex
+    P = PaddedIndex(N, B, w)
+    assert sorted(map(tuple, PaddedIndex(N, B, 0).k)) == sorted(map(tuple, enumerate_lex(N, B)))
+    members = set(map(tuple, P.k.astype(int)))
+    for k in enumerate_lex(N, B).astype(int):
+        for d in itertools.product(range(-w, w + 1), repeat=N):
+            m = tuple(int(a + b) for a, b in zip(k, d))
+            if min(m) >= 0:
+                assert m in members
+    for m in members:
+        for l in range(N):
+            if m[l] > 0:
+                assert tuple(m[i] - (i == l) for i in range(N)) in members
+
+    def cnt(n, b):
+        if b < 1:
+            return 0
+        if n == 0:
+            return 1
+        return (w + 1) * cnt(n - 1, b) + sum(cnt(n - 1, b // (1 + a)) for a in range(1, b))
+    assert P.size == cnt(N, B)
+    for l in range(N):
+        for i, m in enumerate(P.k.astype(int)):
+            up = tuple(m[j] + (j == l) for j in range(N))
+            assert (P.nbr_plus[l, i] >= 0) == (up in members)
