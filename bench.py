@@ -251,6 +251,7 @@ def main():
             forms["sym"] = sym_form(hs, idx, pot, c0, stream, args, value)
         if "diag" in want:
             forms["diag"] = diag_form(hs, stream, args)
+            forms["diag"]["galerkin_gap"] = galerkin_gap_form(hs, idx, pot, c0, stream)
         if "xop" in want:
             forms["xop"] = xop_form(hs, idx, c0, stream)
         if "small" in want:
@@ -528,6 +529,33 @@ def diag_form(hs, stream, args, reps=5):
         del sub, box, pad, vt, eq, er, maps, ws
     return {"workload": "Fig. 9, N = 4 column: torsional potential (L = 16, Chebyshev degree 8), beta = 5",
             "cases": out, "paper_seconds_at_K75": FIG9_N4_PAPER_SECONDS}
+
+
+def galerkin_gap_form(hs, idx, pot, c0, stream, w=3, reps=3):
+    """The gap between the fast algorithm and the exact Galerkin product on the main line's
+    set and packet: F_K c - (D + W_K) c, the exact product taken from the fast algorithm on
+    the hyperbolic cross widened by w = 3 (the largest per-axis degree), restricted to K."""
+    import torch
+    t0 = time.time()
+    P = hs.Index(idx.N, idx.B, pad=w)
+    build_s = time.time() - t0
+    pot.set_time(0.0025)
+    v = torch.from_numpy(c0).to("cuda")
+    y = torch.empty_like(v)
+    hs.apply_h(idx, pot, v, y)
+    maps = (torch.from_numpy(idx.embed_map(P)).to("cuda"), None)
+    gap = torch.empty_like(v)
+    nb = ctypes.c_int64()
+    hs.hs_error_split_workspace_bytes(idx.h, P.h, None, pot.h, ctypes.byref(nb))
+    ws = hs.dev_buffer(nb.value)
+    run = lambda: hs.error_split(idx, P, None, pot, v, e_red=gap, maps=maps, ws=ws)  # noqa: E731
+    run()
+    ms = event_time_ms(run, reps, stream) / reps
+    torch.cuda.synchronize()
+    rel2 = float(torch.linalg.norm(gap) / torch.linalg.norm(y))
+    relinf = float(gap.abs().max() / y.abs().max())
+    return {"workload": "N=%d B=%d packet x_d=2 at t=h/2; widened cross w=%d (%d rows)" % (idx.N, idx.B, w, P.size),
+            "rel_2norm": rel2, "rel_infnorm": relinf, "ms": round(ms, 3), "host_build_s": round(build_s, 2)}
 
 
 def n10_big_form(hs, stream, args, reps=3):
