@@ -175,3 +175,35 @@ def test_explicit_downward_closed_set(hs, N, npts, maxc, kind):
     got = np.empty_like(c0)
     got[pos] = cs.cpu().numpy()
     assert rel2(got, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("N,B,w", [(2, 30, 3), (3, 12, 2)])
+def test_steps_on_a_padded_cross(hs, N, B, w):
+    """Padded crosses (the hyperbolic cross widened by w) serve H applications and steps
+    like any tiled set: 3 steps against the oracle's propagation on the same set, on both
+    step paths."""
+    import torch
+    from oracle.index import PaddedIndex
+    tt = hh_workload(N, 0.111, 0.05)
+    P = PaddedIndex(N, B, w)
+    idx = hs.Index(N, B, pad=w)
+    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    pos = P.rank(idx.multi_indices().astype(np.int64))
+    c0 = complex_normal_by_index(P.k, 9)
+    c0 /= np.linalg.norm(c0)
+    m, h = 10, 0.01
+    ref = c0.copy()
+    for i in range(3):
+        W = oracle_W(N, tt, i * h + 0.5 * h)
+        ref, _, _, _ = lanczos_expm(lambda v: fast_apply_H(P, W, v), ref, h, m)
+    for limit in (1024, 0):
+        old = hs.set_small_step_rows(limit)
+        c = torch.from_numpy(np.ascontiguousarray(c0[pos])).to("cuda")
+        ws = hs.workspace(idx, pot, 0, m)
+        for i in range(3):
+            hs.step(idx, pot, c, i * h, h, m, ws=ws)
+        torch.cuda.synchronize()
+        hs.set_small_step_rows(old)
+        got = np.empty_like(c0)
+        got[pos] = c.cpu().numpy()
+        assert rel2(got, ref) <= 1e-12, limit
