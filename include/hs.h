@@ -23,9 +23,12 @@
  * i.e. B = K_paper + 1.  H = D + W^pol(X_K) with D = diag(sum_l (k_l + 1/2)) and W the
  * potential minus |x|^2/2 (Sec. 1.2), W^pol(X_K) the formal insertion of the coordinate
  * matrices X_K^(l) (Sec. 3.1-3.2, eq. Horner), axis N applied first, axis 1 last.
- * Besides the hyperbolic cross, index sets may be boxes, total-degree sets or any
- * downward-closed set given as a list (HS_SET_*); the operator is defined the same way
- * on each.
+ * Besides the hyperbolic cross, index sets may be boxes, total-degree sets, padded
+ * crosses or any downward-closed set given as a list (HS_SET_*); the operator is
+ * defined the same way on each.
+ *
+ * The paper's three interfaces: the fast algorithm (Fig. 3) is hs_apply_h, the direct
+ * operation (Sec. 3.1) hs_apply_x, the time propagation (Fig. 4) hs_step / hs_propagate.
  */
 #ifndef HS_H
 #define HS_H
