@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--tile-dim", type=int, default=0)
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--forms", type=int, default=1, help="also measure the FP32 and batched forms")
-    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4,sym,diag,xop,small",
+    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4,sym,diag,xop,small,sets",
                     help="comma-separated forms measured when --forms is set")
     ap.add_argument("--batch-log2-bmax", type=float, default=14.0)
     ap.add_argument("--batch-max-rows", type=int, default=1 << 23,
@@ -256,6 +256,8 @@ def main():
             forms["xop"] = xop_form(hs, idx, c0, stream)
         if "small" in want:
             forms["small"] = small_form(hs, stream)
+        if "sets" in want:
+            forms["sets"] = sets_form(hs, stream)
         if "n10_big" in want:   # opt-in: not in the default list
             forms["n10_big"] = n10_big_form(hs, stream, args)
 
@@ -371,6 +373,42 @@ def magnus4_form(hs, idx, pot, c0, stream, args, midpoint_matvec_per_s, nsteps=1
             # two fused passes: read v, write a and d; read a and d, write w (6 S per row)
             "m_alg_gbs": round(6 * 16.0 * idx.size / (us_m * 1e-6) / 1e9, 1),
             "rel_err_8_steps_vs_h_over_4": err}
+
+
+def sets_form(hs, stream, reps=20):
+    """H applications on the other index-set kinds with the main line's potential family
+    (chained Henon-Heiles + laser): the total-degree set |k|_1 <= 26 at N = 6 in the tiled
+    layout, the same rows given as an explicit list (one row per tile, generic row
+    kernels), and the box {0..40}^4.  Per kind: time per application, rows/s and
+    algorithmic GB/s (32 B per row)."""
+    import numpy as np
+    import torch
+    from synth import coherent_state, henon_heiles_chain
+
+    out = {}
+    td = hs.Index(6, 26, total_degree=True)
+    t0 = time.time()
+    lst = hs.Index(6, rows=td.multi_indices())
+    list_build_s = time.time() - t0
+    cases = [("total_degree_N6_D26", 6, td), ("list_same_rows", 6, lst),
+             ("box_N4_K40", 4, hs.Index(4, 40, box=True))]
+    for name, N, idx in cases:
+        tt = henon_heiles_chain(N, 0.111, 0.05)
+        pot = hs.Pot(N, [(x[0], x[1], x[2], x[3], x.degrees) for x in tt], subtract_harmonic=True)
+        pot.set_time(0.1)
+        c = coherent_state(idx.multi_indices(), 1.0)
+        x = torch.from_numpy(c / np.linalg.norm(c)).to("cuda")
+        y = torch.empty_like(x)
+        ws = hs.workspace(idx, pot, hs.HS_C128, 0)
+        hs.apply_h(idx, pot, x, y, hs.HS_C128, ws)
+        us = event_time_ms(lambda: hs.apply_h(idx, pot, x, y, hs.HS_C128, ws), reps, stream) * 1e3 / reps
+        out[name] = {"rows": idx.size, "us_per_h_application": round(us, 1),
+                     "row_matvec_per_s": float("%.4g" % (idx.size / (us * 1e-6))),
+                     "alg_gbs": round(32.0 * idx.size / (us * 1e-6) / 1e9, 1)}
+    out["list_build_s"] = round(list_build_s, 2)
+    out["list_vs_tiled_time"] = round(out["list_same_rows"]["us_per_h_application"]
+                                      / out["total_degree_N6_D26"]["us_per_h_application"], 2)
+    return out
 
 
 def small_form(hs, stream, nsteps=100, reps=20):
