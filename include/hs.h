@@ -118,10 +118,11 @@ int32_t hs_index_create_total_degree(int32_t N, int64_t D, int32_t tile_dim, hs_
  * order; the library keeps them in lexicographic order, see hs_index_multi_indices).
  * The paper's method needs only that k - e_l lies in the set whenever k does and
  * k_l > 0 (Sec. 1.2); the call checks this and returns HS_E_INVALID otherwise (also
- * for repeated rows).  Such sets have no common suffix structure, so the layout makes
- * every axis a prefix axis (one row per tile, neighbours through the tile table) and
- * the H application runs the generic row kernels: the same operator, without the
- * specialised gathers.  Paper's operator form only.                                 */
+ * for repeated rows).  For N >= 3 (and N = 1) the tiles are the distinct prefixes of
+ * the first N - 1 coordinates with the last coordinate as the suffix (tile dimension 1:
+ * downward closure makes every fibre {0..L-1}), and the fused H kernels serve them; for
+ * N = 2 every axis is a prefix axis (one row per tile, the generic row kernels).
+ * Paper's operator form only.                                                        */
 int32_t hs_index_create_from_list(int32_t N, int64_t n, const uint16_t *k_host, hs_index *out);
 /* Padded crosses {k : prod(1 + max(k_l - w, 0)) <= B}: the hyperbolic cross K_N(B)
  * widened by w in every axis (it contains every k + d with k in K_N(B), |d_l| <= w), in

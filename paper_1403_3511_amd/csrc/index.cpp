@@ -16,12 +16,23 @@
 
 #include "hs_internal.h"
 
-// An explicit downward-closed set (HS_SET_LIST) is laid out with every axis a prefix
-// axis: one row per tile, the empty suffix, moves through the tile neighbour table.
+// An explicit downward-closed set (HS_SET_LIST).  For N >= 3 (and N = 1) its tiles are the
+// distinct prefixes (first N - 1 coordinates) and the suffix is the last coordinate: by
+// downward closure every fibre is {0..L-1}, an initial segment of the one suffix list
+// {0..maxlen-1}, so the tiled layout and its fused kernels apply.  For N = 2 every axis
+// is a prefix axis: one row per tile, the empty suffix.
 struct ListSet {
   int N = 0;
+  int d = 0;                                       // tile dimension: 0 (one row per tile) or 1
   std::vector<uint16_t> k;                         // rows, lexicographic
   std::unordered_map<std::string, int64_t> pos;    // key -> row
+  // d = 1: the distinct prefixes (first N - 1 coordinates, lexicographic), the length of
+  // each one's fibre along the last axis (downward closure makes it {0..L-1}), and the
+  // longest fibre
+  std::vector<uint16_t> pfx;
+  std::vector<int32_t> flen;
+  std::unordered_map<std::string, int64_t> ppos;   // prefix key -> prefix index
+  int32_t maxlen = 0;
   static std::string key(const int32_t *m, int n) {
     std::string s((size_t)n * 2, '\0');
     for (int i = 0; i < n; ++i) {
@@ -221,8 +232,14 @@ struct SetOps {
   }
   bool product() const { return kind == HS_SET_HYPERBOLIC || kind == HS_SET_PADDED; }
   int64_t pad() const { return kind == HS_SET_PADDED ? D : 0; }
+  // Lists with tile dimension 1 answer prefix queries (n = N - 1) from the fibres and
+  // suffix queries (n = 1) with {0..maxlen-1}; N >= 3 there, so the two never coincide.
   int64_t count(int n) const {
-    if (kind == HS_SET_LIST) return n == 0 ? 1 : (int64_t)L->pos.size();
+    if (kind == HS_SET_LIST) {
+      if (n == 0) return 1;
+      if (n == L->N) return (int64_t)L->pos.size();
+      return n == 1 ? L->maxlen : (int64_t)L->flen.size();
+    }
     if (product()) return C->count(n, B);
     if (kind == HS_SET_TOTAL_DEGREE) return simplex_count(n, D);
     int64_t r = 1;
@@ -234,7 +251,9 @@ struct SetOps {
       if (n == 0) return true;
       for (int i = 0; i < n; ++i)
         if (k[i] < 0 || k[i] > 65535) return false;
-      return L->pos.count(ListSet::key(k, n)) > 0;
+      if (n == L->N) return L->pos.count(ListSet::key(k, n)) > 0;
+      if (n == 1) return k[0] < L->maxlen;
+      return L->ppos.count(ListSet::key(k, n)) > 0;
     }
     if (product()) return ::member(k, n, B, pad());
     int64_t sum = 0;
@@ -251,10 +270,23 @@ struct SetOps {
         f(m.data());
         return;
       }
-      const int64_t rows = (int64_t)L->pos.size();
-      for (int64_t r = 0; r < rows; ++r) {
-        for (int i = 0; i < n; ++i) m[i] = L->k[(size_t)r * n + i];
-        f(m.data());
+      if (n == L->N) {
+        const int64_t rows = (int64_t)L->pos.size();
+        for (int64_t r = 0; r < rows; ++r) {
+          for (int i = 0; i < n; ++i) m[i] = L->k[(size_t)r * n + i];
+          f(m.data());
+        }
+      } else if (n == 1) {
+        for (int32_t a = 0; a < L->maxlen; ++a) {
+          m[0] = a;
+          f(m.data());
+        }
+      } else {
+        const int64_t np = (int64_t)L->flen.size();
+        for (int64_t t = 0; t < np; ++t) {
+          for (int i = 0; i < n; ++i) m[i] = L->pfx[(size_t)t * n + i];
+          f(m.data());
+        }
       }
       return;
     }
@@ -263,15 +295,20 @@ struct SetOps {
     else enumerate(n, B, f, pad());
   }
   int64_t grade(const int32_t *s, int d) const {
-    if (kind == HS_SET_BOX || kind == HS_SET_LIST) return 0;
+    if (kind == HS_SET_LIST) return d == 1 ? s[0] : 0;  // a fibre is {0..L-1}
+    if (kind == HS_SET_BOX) return 0;
     int64_t g = product() ? 1 : 0;
     for (int a = 0; a < d; ++a) g = product() ? g * pcost(s[a], pad()) : g + s[a];
     return g;
   }
-  int64_t max_grade() const { return product() ? B : (kind == HS_SET_TOTAL_DEGREE ? D : 0); }
+  int64_t max_grade() const {
+    if (kind == HS_SET_LIST) return L->d == 1 ? L->maxlen - 1 : 0;
+    return product() ? B : (kind == HS_SET_TOTAL_DEGREE ? D : 0);
+  }
   // largest suffix grade that fits after prefix p
   int64_t budget(const int32_t *p, int np) const {
-    if (kind == HS_SET_BOX || kind == HS_SET_LIST) return 0;
+    if (kind == HS_SET_LIST) return L->d == 1 ? L->flen[L->ppos.at(ListSet::key(p, np))] - 1 : 0;
+    if (kind == HS_SET_BOX) return 0;
     if (kind == HS_SET_TOTAL_DEGREE) {
       int64_t sum = 0;
       for (int i = 0; i < np; ++i) sum += p[i];
@@ -292,7 +329,11 @@ struct Ranker {
     if (S->product()) R.reset(new LexRank(S->C.get(), n, S->B));
   }
   int64_t rank(const int32_t *k) const {
-    if (S->kind == HS_SET_LIST) return n == 0 ? 0 : S->L->pos.at(ListSet::key(k, n));
+    if (S->kind == HS_SET_LIST) {
+      if (n == 0) return 0;
+      if (n == S->L->N) return S->L->pos.at(ListSet::key(k, n));
+      return n == 1 ? k[0] : S->L->ppos.at(ListSet::key(k, n));
+    }
     if (S->product()) return R->rank(k);
     int64_t r = 0;
     if (S->kind == HS_SET_BOX) {
@@ -786,11 +827,31 @@ extern "C" int32_t hs_index_create_from_list(int32_t N, int64_t n, const uint16_
       }
     }
     if (st == HS_OK) {
+      // N >= 3 (and N = 1): tiles are the prefixes (first N - 1 coordinates) and the
+      // suffix the last coordinate, whose fibre {0..L-1} is an initial segment of the one
+      // suffix list {0..maxlen-1} for every downward-closed set.  N = 2 keeps one row per
+      // tile (its prefix and suffix sets would both be one-dimensional).
+      L->d = (N == 2) ? 0 : 1;
+      if (L->d == 1) {
+        const int np = N - 1;
+        for (int64_t r = 0; r < n; ++r) {
+          const uint16_t *row = L->k.data() + (size_t)r * N;
+          const bool fresh = r == 0 || !std::equal(row, row + np, row - N);
+          if (fresh) {
+            for (int i = 0; i < np; ++i) m[i] = row[i];
+            L->ppos.emplace(ListSet::key(m.data(), np), (int64_t)L->flen.size());
+            L->pfx.insert(L->pfx.end(), row, row + np);
+            L->flen.push_back(0);
+          }
+          L->flen.back() += 1;
+          L->maxlen = std::max(L->maxlen, L->flen.back());
+        }
+      }
       ix->N = N;
       ix->kind = HS_SET_LIST;
       ix->B = maxc + 1;  // coordinates stay below B
-      ix->d = 0;         // every axis a prefix axis: one row per tile
-      ix->np = N;
+      ix->d = L->d;
+      ix->np = N - L->d;
       ix->list = std::move(L);
       st = build_index(ix);
     }

@@ -487,10 +487,14 @@ int launch_hh_long_impl(const IndexDev &ix, const double *hh, const void *x, voi
     HS_LONG_CASE(4, 2)
     HS_LONG_CASE(4, 3)
     HS_LONG_CASE(5, 2)
+    HS_LONG_CASE(5, 4)
     HS_LONG_CASE(6, 2)
     HS_LONG_CASE(6, 3)
+    HS_LONG_CASE(6, 5)
     HS_LONG_CASE(7, 4)
+    HS_LONG_CASE(7, 6)
     HS_LONG_CASE(8, 5)
+    HS_LONG_CASE(8, 7)
     HS_LONG_CASE(9, 5)
     HS_LONG_CASE(10, 6)
     default:

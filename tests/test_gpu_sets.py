@@ -139,7 +139,8 @@ def test_degenerate_sets(hs, kind, N, n):
 
 
 @pytest.mark.parametrize("N,npts,maxc,kind", [(2, 5, 40, "hh"), (3, 8, 20, "hh"), (4, 6, 9, "hh"),
-                                             (3, 8, 20, "torsional")])
+                                             (5, 10, 6, "hh"), (6, 12, 5, "hh"), (7, 10, 3, "hh"),
+                                             (8, 10, 3, "hh"), (1, 1, 30, "hh"), (3, 8, 20, "torsional")])
 def test_explicit_downward_closed_set(hs, N, npts, maxc, kind):
     """A random downward-closed set (union of boxes below random corners) given as a list:
     H against the oracle on the same set, and a Lanczos step."""
@@ -207,3 +208,29 @@ def test_steps_on_a_padded_cross(hs, N, B, w):
         got = np.empty_like(c0)
         got[pos] = c.cpu().numpy()
         assert rel2(got, ref) <= 1e-12, limit
+
+
+@pytest.mark.parametrize("N", [3, 4, 5, 6, 7, 8])
+def test_list_with_long_fibres(hs, N):
+    """A list whose fibres along the last axis are 64 rows long ({0,1}^(N-1) x {0..63}):
+    its tiles take the fused kernel's 64-row wave path (tile dimension 1, N - 1 prefix
+    axes); H against the oracle on the same set."""
+    import itertools
+    import torch
+    from oracle.index import ListIndex
+    rows = np.array([p + (a,) for p in itertools.product(range(2), repeat=N - 1) for a in range(64)])
+    ix = ListIndex(rows)
+    tt = hh_workload(N, 0.111, 0.05)
+    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    pot.set_time(0.2)
+    idx = hs.Index(N, rows=rows)
+    assert idx.tile_dim == 1 and idx.size == len(rows)
+    pos = ix.rank(idx.multi_indices().astype(np.int64))
+    c = complex_normal_by_index(ix.k, 90 + N)
+    cl = torch.from_numpy(np.ascontiguousarray(c[pos])).to("cuda")
+    yl = torch.empty_like(cl)
+    hs.apply_h(idx, pot, cl, yl)
+    torch.cuda.synchronize()
+    y = np.empty_like(c)
+    y[pos] = yl.cpu().numpy()
+    assert rel2(y, fast_apply_H(ix, oracle_W(N, tt, 0.2), c)) <= 1e-12

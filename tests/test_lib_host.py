@@ -104,15 +104,27 @@ def test_total_degree_index_matches_oracle(hs, N, D, d):
 
 
 def test_explicit_downward_closed_sets(hs):
-    """hs_index_create_from_list: the rows come back in lexicographic order, one per tile;
-    a repeated row or a set that is not downward closed is refused."""
+    """hs_index_create_from_list: the rows come back in lexicographic order; for N >= 3 the
+    tiles are the distinct prefixes (first N - 1 coordinates) with the last axis as the
+    suffix, for N = 2 one row per tile; a repeated row or a set that is not downward
+    closed is refused."""
     from synth import random_downward_set
     k = random_downward_set(4, 6, 7, seed=3)
     rng = np.random.default_rng(0)
     shuffled = k[rng.permutation(len(k))]
     idx = hs.Index(4, rows=shuffled, upload=False)
-    assert idx.size == len(k) == idx.ntiles
+    assert idx.size == len(k)
+    assert idx.tile_dim == 1 and idx.ntiles == len({tuple(r[:3]) for r in k})
+    assert idx.nsuffix == k[:, 3].max() + 1
     assert np.array_equal(idx.multi_indices().astype(np.int64), k)
+    k2 = random_downward_set(2, 5, 9, seed=4)
+    idx2 = hs.Index(2, rows=k2, upload=False)
+    assert idx2.tile_dim == 0 and idx2.ntiles == idx2.size == len(k2)
+    assert np.array_equal(idx2.multi_indices().astype(np.int64), k2)
+    k1 = np.arange(7).reshape(-1, 1)
+    idx1 = hs.Index(1, rows=k1, upload=False)
+    assert idx1.tile_dim == 1 and idx1.ntiles == 1
+    assert np.array_equal(idx1.multi_indices().astype(np.int64), k1)
     with pytest.raises(hs.HSError) as e:
         hs.Index(4, rows=np.vstack([k, k[:1]]), upload=False)
     assert e.value.code == -1
