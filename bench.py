@@ -7,21 +7,25 @@ harmonic-oscillator coherent state displaced to x_d = 2 normalised on K, exponen
 midpoint steps of h = 0.005 with m = 10 Lanczos vectors and one Gram-Schmidt pass.
 
 One timed "step" is one full time step: coefficient update, 10 applications of H,
-the Lanczos recurrences and reductions, the small eigensolve and the combination,
+the Lanczos recurrences and reductions, the small exponential and the combination,
 replayed as one captured HIP graph.  value = H applications per second.
 
 Also measured inside this run:
   roofline      -- the H-application kernel (one launch per application) timed back to
                    back with HIP events on its own stream; algorithmic bytes 32 |K| per
-                   launch (read c, write H c, complex128) against 8 TB/s.  traffic comes
-                   from the committed counter summary, and only while the kernel sources
-                   still hash to the value recorded with it.
+                   launch (read c, write H c, complex128) against 8 TB/s, and the
+                   algorithmic flops against the FP64 vector peak.  traffic comes from the
+                   committed counter summary, and only while the kernel sources still hash
+                   to the value recorded with it.
   forms         -- the FP32 form (complex64 matvec, float64 reductions) on the same
                    workload with its error against the float64 run, the batched form
                    (256 instances, one persistent launch per H application) against the
                    same instances stepped one by one, the N = 10 FP32 form, the learned
                    coefficient path, the fourth-order two-stage Magnus step, the
-                   symmetrised operator, and the local error diagnostics of Fig. 9.
+                   symmetrised operator, the local error diagnostics of Fig. 9 and the
+                   main workload's gap to the exact Galerkin product, the direct
+                   operation alone, the small workload (N = 2, B = 64) with the
+                   one-workgroup step, and the other index-set kinds.
   cpu_baseline  -- the CPU oracle's fast algorithm on the same workload (rank 0 only).
 
 --calibrate-copy MIB runs only a device-to-device copy of that size (the reference
