@@ -47,6 +47,13 @@ namespace {
 
 constexpr int64_t kSat = INT64_C(1) << 62;
 
+// a + f * c for non-negative terms, saturating at kSat (counts of large padded crosses
+// exceed 64 bits: 17^16 rows at N = 16, w = 16)
+inline int64_t sat_fma(int64_t a, int64_t f, int64_t c) {
+  if (f != 0 && c > (kSat - a) / f) return kSat;
+  return a + f * c;
+}
+
 // Coordinate cost of the product-bound sets: 1 + k on the hyperbolic cross, and on the
 // padded cross 1 + max(k - w, 0), so that the values 0..w all cost 1.
 inline int64_t pcost(int64_t k, int64_t w) { return 1 + (k > w ? k - w : 0); }
@@ -81,12 +88,11 @@ struct Counter {
         // group the terms a with equal floor(b / a)
         for (int64_t a = 1; a <= b;) {
           int64_t v = b / a, a2 = b / v;
-          s += (a2 - a + 1) * cnt[n - 1][slot[v]];
-          if (s > kSat) s = kSat;
+          s = sat_fma(s, a2 - a + 1, cnt[n - 1][slot[v]]);
           a = a2 + 1;
         }
         // the w further values of cost 1 on the padded cross
-        if (w > 0) s = std::min<int64_t>(kSat, s + w * cnt[n - 1][slot[b]]);
+        s = sat_fma(s, w, cnt[n - 1][slot[b]]);
         cnt[n][i] = s;
       }
   }
@@ -243,7 +249,7 @@ struct SetOps {
     if (product()) return C->count(n, B);
     if (kind == HS_SET_TOTAL_DEGREE) return simplex_count(n, D);
     int64_t r = 1;
-    for (int i = 0; i < n; ++i) r = std::min<int64_t>(r * (K + 1), kSat);
+    for (int i = 0; i < n; ++i) r = sat_fma(0, r, K + 1);
     return r;
   }
   bool member(const int32_t *k, int n) const {

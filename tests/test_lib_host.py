@@ -398,3 +398,13 @@ def test_padded_index_errors(hs):
     tot = hs.Index(3, 5, upload=False, total_degree=True)
     with pytest.raises(hs.HSError):
         sub.embed_map(tot)   # a total-degree target has no embedding
+
+
+def test_padded_count_saturates(hs):
+    """The padded cross at N = 16, w = 16 has 17^16 > 2^63 members: refused as too large
+    (no wrapped count), while the same w at N = 3 builds."""
+    h = C.c_void_p()
+    with pytest.raises(hs.HSError) as e:
+        hs.hs_index_create_padded(16, 1, 16, 0, C.byref(h))
+    assert e.value.code == -2
+    assert hs.Index(3, 1, upload=False, pad=16).size == 17 ** 3
