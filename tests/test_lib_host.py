@@ -408,3 +408,19 @@ def test_padded_count_saturates(hs):
         hs.hs_index_create_padded(16, 1, 16, 0, C.byref(h))
     assert e.value.code == -2
     assert hs.Index(3, 1, upload=False, pad=16).size == 17 ** 3
+
+
+def test_bench_flop_model():
+    """The bench's algorithmic flop count per row of H (8 per distinct partial product of a
+    term, axis N first, 4 per term, 4 for the diagonal).  By hand for N = 2 (W = 0.111 x1^2 x2
+    - 0.037 x2^3): partial products X2, X2^2, X2^3, X1 X2, X1^2 X2 -> 8*5 + 4*2 + 4 = 52; the
+    chains with the laser give 276 at N = 6 and 484 at N = 10."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    from synth import henon_heiles_chain
+    for N, laser, want in ((2, 0.0, 52), (6, 0.05, 276), (10, 0.05, 484)):
+        deg = bench.w_degrees(henon_heiles_chain(N, 0.111, laser), N)
+        assert bench.alg_flops_per_row(N, deg) == want
+    # the harmonic part cancels in W: a pure oscillator costs the diagonal only
+    assert bench.w_degrees(henon_heiles_chain(3, 0.0, 0.0), 3) == []
