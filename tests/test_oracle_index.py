@@ -146,3 +146,31 @@ def test_padded_index(N, B, w):
         for i, m in enumerate(P.k.astype(int)):
             up = tuple(m[j] + (j == l) for j in range(N))
             assert (P.nbr_plus[l, i] >= 0) == (up in members)
+
+
+@pytest.mark.parametrize("N,B", [(2, 30), (3, 40), (4, 24)])
+def test_list_index(N, B):
+    """ListIndex built from the rows of a hyperbolic cross (shuffled) is that set, with the
+    same lexicographic order and neighbour maps as IndexSet; on a random downward-closed set
+    its neighbour maps and ranks agree with brute force."""
+    from oracle.index import ListIndex
+    from synth import random_downward_set
+    ref = IndexSet(N, B)
+    rows = ref.k.astype(np.int64)
+    L = ListIndex(rows[np.random.default_rng(1).permutation(len(rows))])
+    assert np.array_equal(L.k, ref.k)
+    assert np.array_equal(L.nbr_plus, ref.nbr_plus) and np.array_equal(L.nbr_minus, ref.nbr_minus)
+    assert np.array_equal(L.rank(rows), np.arange(len(rows)))
+    R = random_downward_set(N, 5, 6, seed=N)
+    L2 = ListIndex(R)
+    members = {tuple(r) for r in R.tolist()}
+    assert len(members) == L2.size
+    for i, row in enumerate(L2.k.astype(int).tolist()):
+        assert L2.rank(np.array([row]))[0] == i
+        for l in range(N):
+            up = tuple(row[j] + (j == l) for j in range(N))
+            dn = tuple(row[j] - (j == l) for j in range(N))
+            assert (L2.nbr_plus[l, i] >= 0) == (up in members)
+            assert (L2.nbr_minus[l, i] >= 0) == (row[l] > 0)
+            if row[l] > 0:
+                assert tuple(L2.k[L2.nbr_minus[l, i]].astype(int)) == dn
