@@ -207,6 +207,7 @@ int32_t hs_step(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev, in
                 double t, double *t_dev, double h, int32_t m, int32_t reorth, void *c, void *ws,
                 double *diag_dev, void *stream);
 
+
 /* Sets of at most `rows` rows (default 1024; the kernel holds one row per thread, at most
  * 1024, so larger values act as 1024) run hs_step / hs_propagate of the paper's operator
  * form with a fused-class potential as one launch of one workgroup: the whole
@@ -321,6 +322,13 @@ int32_t hs_batch_autotune_sync(hs_batch b, const void *batch_dev, const void *c,
  * eigenvalues of the Hermite Jacobi matrix); one workgroup per sample; asynchronous on
  * the stream.  HS_E_INVALID for sizes out of range.                                  */
 int32_t hs_gh_ncoef(int32_t N, int32_t D, int32_t *ncoef);
+/* hs_gh_rule: the Q-point Gauss-Hermite rule for the weight exp(-x^2) that
+ * hs_gh_project uses (paper Sec. 4.1; the nodes are the eigenvalues of the Jacobi matrix
+ * X_full of Sec. 4.2, found by Sturm-sequence bisection and one Newton step), written to
+ * the host arrays x (ascending) and w of Q doubles each.  Host only, no device call.
+ * HS_E_INVALID for Q outside 1..32 or NULL outputs; HS_E_NONFINITE if the bisection does
+ * not isolate Q distinct nodes.                                                      */
+int32_t hs_gh_rule(int32_t Q, double *x_host, double *w_host);
 int32_t hs_gh_project(int32_t N, int32_t G, int32_t D, int32_t Q, const double *geometry_host,
                       int32_t nsamp, const double *params_dev, double *coef_dev, void *stream);
 /* hs_cheb_interp: Chebyshev interpolation of the same Gaussian-well W on the cube

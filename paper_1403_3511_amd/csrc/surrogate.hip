@@ -21,72 +21,90 @@
 namespace hs {
 
 // ---------------------------------------------------------------------------------------
-// Gauss-Hermite rule (host): nodes are the eigenvalues of the Jacobi matrix with
-// off-diagonals sqrt(k/2) (Golub-Welsch, cf. paper Sec. 4.2 X_full = U^T Xi U); weights
-// from the Christoffel function w_m = 1 / sum_k psi_k(x_m)^2 with the orthonormal
-// polynomials psi_k (psi_0 = pi^-1/4, same recurrence as the Hermite functions).
+// Gauss-Hermite rule (host).  The nodes are the eigenvalues of the Jacobi matrix J with zero
+// diagonal and off-diagonals sqrt(k/2), k = 1..Q-1 (the matrix X_full of paper Sec. 4.2,
+// whose eigen-decomposition U^T Xi U gives the quadrature), i.e. the zeros of the
+// orthonormal Hermite polynomial psi_Q.  They are located by Sturm-sequence bisection
+// (Wilkinson): for a shift x, the LDL^T pivots of J - x I,
+//   q_0 = -x,  q_k = -x - (k/2) / q_{k-1},
+// have as many negative entries as J has eigenvalues below x.  Each node is bracketed by
+// the Gershgorin interval and bisected until the bracket stops shrinking, then polished by
+// one Newton step on psi_Q (psi_Q' = sqrt(2Q) psi_{Q-1}).  The weights come from the
+// Christoffel function w_m = 1 / sum_{k<Q} psi_k(x_m)^2 with psi_0 = pi^(-1/4).
 // ---------------------------------------------------------------------------------------
-static void tridiag_eigenvalues(std::vector<double> d, std::vector<double> e, std::vector<double> &out) {
-  // implicit QL with Wilkinson shifts on a symmetric tridiagonal matrix (diagonal d,
-  // off-diagonal e[0..n-2]); eigenvalues only
-  const int n = (int)d.size();
-  e.resize(n, 0.0);
-  for (int l = 0; l < n; ++l) {
-    for (int iter = 0; iter < 200; ++iter) {
-      int m = l;
-      for (; m < n - 1; ++m) {
-        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-        if (std::fabs(e[m]) <= 1e-16 * dd) break;
-      }
-      if (m == l) break;
-      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = std::hypot(g, 1.0);
-      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
-      double s = 1.0, c = 1.0, p = 0.0;
-      int i = m - 1;
-      for (; i >= l; --i) {
-        double f = s * e[i], b = c * e[i];
-        r = std::hypot(f, g);
-        e[i + 1] = r;
-        if (r == 0.0) {
-          d[i + 1] -= p;
-          e[m] = 0.0;
-          break;
-        }
-        s = f / r;
-        c = g / r;
-        g = d[i + 1] - p;
-        r = (d[i] - g) * s + 2.0 * c * b;
-        p = s * r;
-        d[i + 1] = g + p;
-        g = c * r - b;
-      }
-      if (r == 0.0 && i >= l) continue;
-      d[l] -= p;
-      e[l] = g;
-      e[m] = 0.0;
-    }
+// number of eigenvalues of J (order Q) strictly below x
+static int gh_sturm_count(int Q, double x) {
+  int neg = 0;
+  double q = -x;
+  for (int k = 1;; ++k) {
+    // a zero pivot is replaced by a tiny positive one (a shift of x by a negligible
+    // amount), used both for the count and for the next pivot
+    if (q == 0.0) q = 1e-300;
+    if (q < 0.0) ++neg;
+    if (k == Q) break;
+    q = -x - 0.5 * k / q;
   }
-  out = d;
-  std::sort(out.begin(), out.end());
+  return neg;
 }
 
-static void gh_rule(int Q, std::vector<double> &x, std::vector<double> &w) {
-  std::vector<double> d(Q, 0.0), e(Q, 0.0);
-  for (int k = 1; k < Q; ++k) e[k - 1] = std::sqrt(0.5 * k);
-  tridiag_eigenvalues(d, e, x);
+// psi_{Q-1}(x) and psi_Q(x) by the three-term recurrence
+//   sqrt((k+1)/2) psi_{k+1} = x psi_k - sqrt(k/2) psi_{k-1}
+static void gh_psi_pair(int Q, double x, double &pqm1, double &pq) {
+  double pm = 0.0, pc = std::pow(M_PI, -0.25);
+  for (int k = 0; k < Q; ++k) {
+    const double pn = (x * pc - std::sqrt(0.5 * k) * pm) / std::sqrt(0.5 * (k + 1));
+    pm = pc;
+    pc = pn;
+  }
+  pqm1 = pm;
+  pq = pc;
+}
+
+// nodes x (ascending) and weights w of the Q-point rule for the weight exp(-x^2);
+// false if the bisection did not isolate Q distinct nodes
+static bool gh_rule(int Q, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(Q, 0.0);
   w.assign(Q, 0.0);
+  // Gershgorin: every eigenvalue lies in [-g, g]
+  double g = 0.0;
+  for (int k = 0; k < Q; ++k) {
+    const double lo = k > 0 ? std::sqrt(0.5 * k) : 0.0, hi = k + 1 < Q ? std::sqrt(0.5 * (k + 1)) : 0.0;
+    g = std::max(g, lo + hi);
+  }
+  g = g * (1.0 + 1e-12) + 1e-300;
   for (int m = 0; m < Q; ++m) {
-    double p0 = std::pow(M_PI, -0.25), p1 = 0.0, s = p0 * p0;
-    double pm = 0.0, pc = p0;
+    // the (m+1)-th smallest eigenvalue: count(a) <= m < count(b)
+    double a = -g, b = g;
+    for (int it = 0; it < 2000; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (mid <= a || mid >= b) break;  // the bracket cannot shrink further
+      if (gh_sturm_count(Q, mid) <= m) a = mid; else b = mid;
+    }
+    double xm = 0.5 * (a + b);
+    double pqm1, pq;
+    gh_psi_pair(Q, xm, pqm1, pq);
+    const double dpq = std::sqrt(2.0 * Q) * pqm1;
+    if (dpq != 0.0) {
+      const double step = pq / dpq;
+      // keep the polish inside the bracket that isolates this node
+      if (std::fabs(step) <= (b - a) + 1e-15 * (1.0 + std::fabs(xm))) xm -= step;
+    }
+    x[m] = xm;
+  }
+  for (int m = 1; m < Q; ++m)
+    if (!(x[m] > x[m - 1])) return false;
+  for (int m = 0; m < Q; ++m) {
+    double pm = 0.0, pc = std::pow(M_PI, -0.25), s = pc * pc;
     for (int k = 0; k + 1 < Q; ++k) {
-      p1 = (x[m] * pc - std::sqrt(0.5 * k) * pm) / std::sqrt(0.5 * (k + 1));
+      const double pn = (x[m] * pc - std::sqrt(0.5 * k) * pm) / std::sqrt(0.5 * (k + 1));
       pm = pc;
-      pc = p1;
+      pc = pn;
       s += pc * pc;
     }
     w[m] = 1.0 / s;
+    if (!std::isfinite(w[m]) || !(w[m] > 0.0)) return false;
   }
+  return true;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -778,7 +796,8 @@ int32_t gh_launch(int32_t N, int32_t G, int32_t D, int32_t Q, const double *geom
   if (A.R < 1 || lds > hs::kGhLdsBytes || A.ncoef > hs::kGhThreads)
     return hs::fail(HS_E_UNSUPPORTED, "Gauss-Hermite projection: workspace exceeds LDS");
   std::vector<double> xi, wq;
-  hs::gh_rule(Q, xi, wq);
+  if (!hs::gh_rule(Q, xi, wq))
+    return hs::fail(HS_E_NONFINITE, "Gauss-Hermite rule: the bisection did not isolate the nodes");
   for (int m = 0; m < Q; ++m) {
     A.xi[m] = xi[m];
     // H_n(x) by the physicists' recurrence; scaled by w_m / (sqrt(pi) 2^n n!)
@@ -885,6 +904,15 @@ int32_t hs_cheb_interp(int32_t N, int32_t G, int32_t D, int32_t R, double L, con
 int32_t hs_gh_ncoef(int32_t N, int32_t D, int32_t *ncoef) {
   if (!ncoef || N < 1 || D < 0) return hs::fail(HS_E_INVALID, "hs_gh_ncoef: bad arguments");
   *ncoef = (int32_t)hs::binom(N + D, N);
+  return HS_OK;
+}
+
+int32_t hs_gh_rule(int32_t Q, double *x_host, double *w_host) {
+  if (Q < 1 || Q > hs::kGhMaxQ || !x_host || !w_host) return hs::fail(HS_E_INVALID, "hs_gh_rule: bad arguments");
+  std::vector<double> x, w;
+  if (!hs::gh_rule(Q, x, w)) return hs::fail(HS_E_NONFINITE, "hs_gh_rule: the bisection did not isolate the nodes");
+  std::memcpy(x_host, x.data(), sizeof(double) * Q);
+  std::memcpy(w_host, w.data(), sizeof(double) * Q);
   return HS_OK;
 }
 

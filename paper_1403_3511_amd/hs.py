@@ -81,6 +81,7 @@ _SIGS = {
     "hs_batch_get_launch": [_vp, _pi32, _pi32],
     "hs_batch_autotune_sync": [_vp, _vp, _vp, _vp, _vp, _vp],
     "hs_gh_ncoef": [_i32, _i32, _pi32],
+    "hs_gh_rule": [_i32, _pf64, _pf64],
     "hs_gh_project": [_i32, _i32, _i32, _i32, _pf64, _i32, _vp, _vp, _vp],
     "hs_cheb_ncoef": [_i32, _i32, _i32, _pi32],
     "hs_cheb_interp": [_i32, _i32, _i32, _i32, _f64, _pf64, _i32, _vp, _vp, _vp],
@@ -159,6 +160,105 @@ def dev_buffer(nbytes: int, device="cuda"):
 
 def ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+# ---- argument checks before a launch: the C ABI carries no buffer lengths ------------
+
+_DT_NAMES = {HS_C128: "complex128", HS_C64: "complex64"}
+
+
+def _fail(msg):
+    raise HSError(-1, msg)
+
+
+def _check_vec(name, t, n, dtype=None, tdtype=None, device=None):
+    """t must be a contiguous tensor of at least n elements of the complex type selected by
+    dtype (or of torch dtype tdtype), on device (when given)."""
+    torch = _torch()
+    if t is None:
+        _fail(f"{name}: a tensor is required")
+    if not isinstance(t, torch.Tensor):
+        _fail(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    want = tdtype
+    if dtype is not None:
+        if dtype not in _DT_NAMES:
+            _fail(f"{name}: unknown dtype code {dtype}")
+        want = torch.complex128 if dtype == HS_C128 else torch.complex64
+    if want is not None and t.dtype != want:
+        _fail(f"{name}: dtype {t.dtype} does not match {want}")
+    if not t.is_contiguous():
+        _fail(f"{name}: tensor must be contiguous")
+    if t.numel() < n:
+        _fail(f"{name}: {t.numel()} elements, {n} required")
+    if device is not None and t.device != device:
+        _fail(f"{name}: on {t.device}, expected {device}")
+
+
+def _check_ws(name, ws, nbytes, device):
+    torch = _torch()
+    if not isinstance(ws, torch.Tensor) or not ws.is_contiguous():
+        _fail(f"{name}: workspace must be a contiguous tensor")
+    have = ws.numel() * ws.element_size()
+    if have < nbytes:
+        _fail(f"{name}: workspace of {have} bytes, {nbytes} required")
+    if ws.device != device:
+        _fail(f"{name}: workspace on {ws.device}, expected {device}")
+
+
+def _dev_of(block, what):
+    if block is None:
+        _fail(f"{what} has no device block (created with upload=False)")
+    return block.device
+
+
+def _ws_bytes(idx, pot, dtype, m, magnus4=False):
+    nb = C.c_int64()
+    (hs_magnus4_workspace_bytes if magnus4 else hs_workspace_bytes)(idx.h, pot.h, dtype, m, C.byref(nb))
+    return nb.value
+
+
+def _check_step_args(name, idx, pot, dtype, m, c, ws, magnus4=False, pot_blocks=None):
+    """A step's state c is complex128 in both forms (the FP32 form keeps complex64 Krylov
+    vectors in the workspace); the workspace is sized for (dtype, m)."""
+    _check_dtype_code(name, dtype)
+    _check_h_args(name, idx, pot, HS_C128, m, [("c", c)], None, pot_blocks=pot_blocks)
+    if ws is not None:
+        _check_ws(name, ws, _ws_bytes(idx, pot, dtype, m, magnus4), c.device)
+
+
+def _check_dtype_code(name, dtype):
+    if dtype not in _DT_NAMES:
+        _fail(f"{name}: unknown dtype code {dtype}")
+
+
+def _check_distinct(name, *ts):
+    live = [t for t in ts if t is not None]
+    for i in range(len(live)):
+        for j in range(i + 1, len(live)):
+            a, b = live[i], live[j]
+            a0, a1 = a.data_ptr(), a.data_ptr() + a.numel() * a.element_size()
+            b0, b1 = b.data_ptr(), b.data_ptr() + b.numel() * b.element_size()
+            if a0 < b1 and b0 < a1:
+                _fail(f"{name}: input and output buffers overlap")
+
+
+def _check_h_args(name, idx, pot, dtype, m, vecs, ws, magnus4=False, pot_blocks=None):
+    """Shared checks of the single-instance calls: vectors (name, tensor) of idx.size
+    elements of dtype, the workspace for (dtype, m), all on the index's device."""
+    for vn, v in vecs:
+        _check_vec(f"{name}: {vn}", v, idx.size, dtype=dtype)
+    if ws is not None:
+        _check_ws(name, ws, _ws_bytes(idx, pot, dtype, m, magnus4), ws.device)
+    dev = _dev_of(idx.dev, "index")
+    blocks = pot_blocks if pot_blocks is not None else [pot.dev]
+    for b in blocks:
+        if _dev_of(b, "potential") != dev:
+            _fail(f"{name}: potential block on {b.device}, index on {dev}")
+    for vn, v in vecs:
+        if v.device != dev:
+            _fail(f"{name}: {vn} on {v.device}, index on {dev}")
+    if ws is not None and ws.device != dev:
+        _fail(f"{name}: workspace on {ws.device}, index on {dev}")
 
 
 class Index:
@@ -300,6 +400,8 @@ def workspace(idx: Index, pot: Pot, dtype: int, m: int, device="cuda"):
 
 def apply_h(idx: Index, pot: Pot, c, y, dtype: int = HS_C128, ws=None):
     """y = H c; c, y complex device tensors in library row order."""
+    _check_h_args("apply_h", idx, pot, dtype, 0, [("c", c), ("y", y)], ws)
+    _check_distinct("apply_h", c, y)
     if ws is None:
         ws = workspace(idx, pot, dtype, 0, c.device)
     hs_apply_h(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, ptr(c), ptr(y), ptr(ws), stream_ptr())
@@ -308,6 +410,9 @@ def apply_h(idx: Index, pot: Pot, c, y, dtype: int = HS_C128, ws=None):
 
 def apply_x(idx: Index, axis: int, c, y, dtype: int = HS_C128):
     """y = X^(axis) c, the direct operation along one axis (0-based); c != y."""
+    for vn, v in (("c", c), ("y", y)):
+        _check_vec(f"apply_x: {vn}", v, idx.size, dtype=dtype, device=_dev_of(idx.dev, "index"))
+    _check_distinct("apply_x", c, y)
     hs_apply_x(idx.h, ptr(idx.dev), int(axis), dtype, ptr(c), ptr(y), stream_ptr())
     return y
 
@@ -315,6 +420,7 @@ def apply_x(idx: Index, axis: int, c, y, dtype: int = HS_C128):
 def step(idx: Index, pot: Pot, c, t: float, h: float, m: int, dtype: int = HS_C128,
          reorth: bool = True, ws=None, t_dev=None, diag=None):
     """One exponential-midpoint Lanczos step in place on c (complex128 device tensor)."""
+    _check_step_args("step", idx, pot, dtype, m, c, ws)
     if ws is None:
         ws = workspace(idx, pot, dtype, m, c.device)
     hs_step(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, float(t), ptr(t_dev), float(h), int(m),
@@ -333,6 +439,7 @@ def set_small_step_rows(rows: int) -> int:
 def propagate(idx: Index, pot: Pot, c, t0: float, h: float, m: int, nsteps: int, dtype: int = HS_C128,
               reorth: bool = True, ws=None, t_dev=None):
     """nsteps exponential-midpoint Lanczos steps in place on c (complex128 device tensor)."""
+    _check_step_args("propagate", idx, pot, dtype, m, c, ws)
     if ws is None:
         ws = workspace(idx, pot, dtype, m, c.device)
     hs_propagate(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, float(t0), ptr(t_dev), float(h), int(m),
@@ -350,9 +457,12 @@ def workspace_magnus4(idx: Index, pot: Pot, dtype: int, m: int, device="cuda"):
 def apply_magnus4(idx: Index, pot: Pot, h: float, c, y, dtype: int = HS_C128, ws=None):
     """y = M c, the operator of the two-stage Gauss-Legendre Magnus scheme, with the
     coefficients currently held in the potential's two parameter blocks."""
+    d1, d2 = pot.blocks2()
+    _check_h_args("apply_magnus4", idx, pot, dtype, 0, [("c", c), ("y", y)], ws, magnus4=True,
+                  pot_blocks=[d1, d2])
+    _check_distinct("apply_magnus4", c, y)
     if ws is None:
         ws = workspace_magnus4(idx, pot, dtype, 0, c.device)
-    d1, d2 = pot.blocks2()
     hs_apply_magnus4(idx.h, ptr(idx.dev), pot.h, ptr(d1), ptr(d2), dtype, float(h), ptr(c), ptr(y),
                      ptr(ws), stream_ptr())
     return y
@@ -361,9 +471,10 @@ def apply_magnus4(idx: Index, pot: Pot, h: float, c, y, dtype: int = HS_C128, ws
 def step_magnus4(idx: Index, pot: Pot, c, t: float, h: float, m: int, dtype: int = HS_C128,
                  reorth: bool = True, ws=None, t_dev=None, diag=None):
     """One fourth-order two-stage Gauss-Legendre Magnus step in place on c."""
+    d1, d2 = pot.blocks2()
+    _check_step_args("step_magnus4", idx, pot, dtype, m, c, ws, magnus4=True, pot_blocks=[d1, d2])
     if ws is None:
         ws = workspace_magnus4(idx, pot, dtype, m, c.device)
-    d1, d2 = pot.blocks2()
     hs_step_magnus4(idx.h, ptr(idx.dev), pot.h, ptr(d1), ptr(d2), dtype, float(t), ptr(t_dev),
                     float(h), int(m), 1 if reorth else 0, ptr(c), ptr(ws), ptr(diag), stream_ptr())
     return c
@@ -374,6 +485,10 @@ def error_split(sub: Index, box: Index, pad, pot: Pot, v, e_quad=None, e_red=Non
     quadrature error against the padded box pad (None: e_quad is None) and the index-set
     reduction error against the box."""
     torch = _torch()
+    _check_vec("error_split: v", v, sub.size, dtype=HS_C128, device=_dev_of(sub.dev, "index"))
+    for vn, e in (("e_quad", e_quad), ("e_red", e_red)):
+        if e is not None:
+            _check_vec(f"error_split: {vn}", e, sub.size, dtype=HS_C128, device=v.device)
     if maps is None:
         maps = (torch.from_numpy(sub.embed_map(box)).to(v.device),
                 torch.from_numpy(sub.embed_map(pad)).to(v.device) if pad is not None else None)
@@ -418,11 +533,23 @@ class Batch:
         hs_batch_workspace_bytes(self.h, m, C.byref(nb))
         return dev_buffer(nb.value, device)
 
+    def _check(self, name, vecs, ws=None, m=0):
+        dev = self.dev.device
+        for vn, v in vecs:
+            _check_vec(f"Batch.{name}: {vn}", v, self.total, tdtype=_torch().complex128, device=dev)
+        if ws is not None:
+            nb = C.c_int64()
+            hs_batch_workspace_bytes(self.h, m, C.byref(nb))
+            _check_ws(f"Batch.{name}", ws, nb.value, dev)
+
     def apply_h(self, c, y):
+        self._check("apply_h", [("c", c), ("y", y)])
+        _check_distinct("Batch.apply_h", c, y)
         hs_batch_apply_h(self.h, ptr(self.dev), ptr(c), ptr(y), None, stream_ptr())
         return y
 
     def step(self, c, t: float, h: float, m: int, reorth: bool = True, ws=None, t_dev=None):
+        self._check("step", [("c", c)], ws, m)
         if ws is None:
             ws = self.workspace(m, c.device)
         hs_batch_step(self.h, ptr(self.dev), float(t), ptr(t_dev), float(h), int(m),
@@ -438,6 +565,8 @@ class Batch:
         return a.value, b.value
 
     def autotune(self, c, y):
+        self._check("autotune", [("c", c), ("y", y)])
+        _check_distinct("Batch.autotune", c, y)
         hs_batch_autotune_sync(self.h, ptr(self.dev), ptr(c), ptr(y), None, stream_ptr())
         return self.get_launch()
 
@@ -479,8 +608,10 @@ def gh_project(geom, params, D: int, Q: int, out=None):
     G, N = base.shape
     nc = gh_ncoef(N, D)
     ns = params.shape[0]
+    _check_vec("gh_project: params", params, ns * (4 + G), tdtype=torch.float64)
     if out is None:
         out = torch.empty((ns, nc), dtype=torch.float64, device=params.device)
+    _check_vec("gh_project: out", out, ns * nc, tdtype=torch.float64, device=params.device)
     g = geometry_array(geom)
     hs_gh_project(N, G, D, Q, g.ctypes.data_as(_pf64), ns, ptr(params), ptr(out), stream_ptr())
     return out
@@ -499,8 +630,10 @@ def cheb_interp(geom, params, D: int, R: int, L: float, out=None):
     N = geom["base"].shape[1]
     G = geom["base"].shape[0]
     n = params.shape[0]
+    _check_vec("cheb_interp: params", params, n * (4 + G), tdtype=torch.float64)
     if out is None:
         out = torch.empty((n, cheb_ncoef(N, D, R)), dtype=torch.float64, device=params.device)
+    _check_vec("cheb_interp: out", out, n * cheb_ncoef(N, D, R), tdtype=torch.float64, device=params.device)
     g = geometry_array(geom)
     hs_cheb_interp(N, G, D, R, float(L), g.ctypes.data_as(_pf64), n, ptr(params), ptr(out), stream_ptr())
     return out
@@ -556,8 +689,10 @@ class MLP:
 
     def predict(self, x, out=None):
         torch = _torch()
+        self._check_batch("predict", x)
         if out is None:
             out = torch.empty((x.shape[0], self.n_out), dtype=torch.float64, device=x.device)
+        _check_vec("MLP.predict: out", out, x.shape[0] * self.n_out, tdtype=torch.float64, device=x.device)
         hs_mlp_predict(self.h, ptr(self.dev), x.shape[0], ptr(x), ptr(out), stream_ptr())
         return out
 
@@ -566,14 +701,35 @@ class MLP:
         torch = _torch()
         base = np.asarray(geom["base"])
         G, N = base.shape
+        self._check_batch("coeffs", params)
         if out is None:
             out = torch.empty((params.shape[0], self.n_out), dtype=torch.float64, device=params.device)
+        _check_vec("MLP.coeffs: out", out, params.shape[0] * self.n_out, tdtype=torch.float64,
+                   device=params.device)
+        if used is not None:
+            _check_vec("MLP.coeffs: used", used, params.shape[0], tdtype=torch.int32, device=params.device)
         g = geometry_array(geom)
         hs_sur_coeffs(self.h, ptr(self.dev), N, G, D, Q, g.ctypes.data_as(_pf64), params.shape[0],
                       ptr(params), ptr(out), ptr(used), stream_ptr())
         return out
 
+    def _check_batch(self, name, x):
+        torch = _torch()
+        if x.dim() != 2 or x.shape[1] != self.n_in:
+            _fail(f"MLP.{name}: inputs must be (batch, {self.n_in})")
+        if x.shape[0] > self.max_batch:
+            _fail(f"MLP.{name}: batch {x.shape[0]} above max_batch {self.max_batch}")
+        _check_vec(f"MLP.{name}: x", x, x.shape[0] * self.n_in, tdtype=torch.float64, device=self.dev.device)
+
     def train_step(self, x, target, lr: float, loss=None, grads=None):
+        torch = _torch()
+        self._check_batch("train_step", x)
+        _check_vec("MLP.train_step: target", target, x.shape[0] * self.n_out, tdtype=torch.float64,
+                   device=x.device)
+        if loss is not None:
+            _check_vec("MLP.train_step: loss", loss, 1, tdtype=torch.float32, device=x.device)
+        if grads is not None:
+            _check_vec("MLP.train_step: grads", grads, self.nparam, tdtype=torch.float32, device=x.device)
         hs_mlp_train_step(self.h, ptr(self.dev), x.shape[0], ptr(x), ptr(target), float(lr),
                           ptr(loss), ptr(grads), stream_ptr())
 
