@@ -37,6 +37,15 @@ __device__ hs_v4i hs_struct_load_b128(__amdgpu_buffer_rsrc_t rsrc, int vindex, i
 __device__ hs_v2i hs_struct_load_b64(__amdgpu_buffer_rsrc_t rsrc, int vindex, int voffset, int soffset,
                                      int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
 
+// The structured loads address element i at byte i * stride, and that product is formed
+// in 32 bits: past 2^32 bytes it wraps around, silently, to the start of the vector.  The
+// kernels that use them therefore serve only vectors of at most 2^32 bytes; larger ones
+// take the kernels with 64-bit addressing.
+template <typename T>
+inline bool struct_loads_reach(int64_t n) {
+  return n * (int64_t)sizeof(typename V2<T>::t) <= (INT64_C(1) << 32);
+}
+
 // resource over n complex elements of type V2<T>
 template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const void *x, int64_t n) {
@@ -467,6 +476,7 @@ int launch_hh_long_impl(const IndexDev &ix, const double *hh, const void *x, voi
   if (ix.rstride != rec_stride(ix.np)) return 0;
   // row indices are 32-bit and kAbsent must lie beyond every row
   if (ix.size >= (int64_t)INT32_MAX) return 0;
+  if (!struct_loads_reach<T>(ix.size)) return 0;
   const bool small = ix.tile_rec != nullptr;
 #define HS_LONG_CASE(NN, PP)                                                                    \
   case NN * 32 + PP:                                                                            \

@@ -416,6 +416,7 @@ bool launch_m4_impl(const IndexDev &ix, const double *hh1, const double *hh2, co
                     bool dl) {
   if (ix.rstride != rec_stride(ix.np)) return false;
   if (ix.size >= (int64_t)INT32_MAX) return false;
+  if (!struct_loads_reach<T>(ix.size)) return false;
   if (ix.tile_rec == nullptr && ix.nsmall > 0) return false;
 #define HS_M4_CASE(NN, PP)                                                                            \
   case NN * 32 + PP:                                                                                  \

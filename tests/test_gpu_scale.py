@@ -92,10 +92,10 @@ def test_n10_float32_form_error(setup):
 
 
 def test_above_32bit_buffer_range():
-    """N = 6, product bound 65536 (247,147,586 rows): complex128 vectors exceed the 2^31
-    bytes that 32-bit buffer offsets reach, so the float64 H application takes the 64-bit
-    row kernels; complex64 stays just below and uses the buffer kernel.  Float64 checked
-    on sampled rows against the oracle, float32 against float64."""
+    """N = 6, product bound 65536 (247,147,586 rows): complex128 vectors of 3.95 GB, past
+    the 2^31 bytes of a signed 32-bit byte offset.  The fused kernels address vectors by
+    element index (times the 16-byte record stride), so both types take them.  Float64
+    checked on sampled rows against the oracle, float32 against float64."""
     import torch
     from paper_1403_3511_amd import hs
     N6, B6 = 6, 65536
@@ -132,3 +132,92 @@ def test_above_32bit_buffer_range():
     err = float(torch.linalg.norm(y32.to(torch.complex128) - y) / torch.linalg.norm(y))
     print(f"N=6 B=65536: float32 H application relative error vs float64 {err:.2e}")
     assert err < 1e-5
+
+
+def _dyadic(k):
+    """An exactly representable complex value per multi-index, (r1 - 48)/64 + i (r2 - 44)/64
+    with r1, r2 integer residues of k: numpy here and torch on the device compute the
+    same bits (no transcendental functions), in float64 and float32 alike."""
+    k = np.atleast_2d(np.asarray(k, dtype=np.int64))
+    n = k.shape[1]
+    r1 = (k @ np.arange(3, 3 + 2 * n, 2, dtype=np.int64)) % 97
+    r2 = ((k * k) @ np.arange(n, 0, -1, dtype=np.int64)) % 89
+    return (r1 - 48) / 64.0 + 1j * (r2 - 44) / 64.0
+
+
+def _dyadic_device(k_chunk, out):
+    import torch
+    kk = torch.from_numpy(k_chunk).to("cuda").to(torch.int64)
+    n = kk.shape[1]
+    w1 = torch.arange(3, 3 + 2 * n, 2, dtype=torch.int64, device="cuda")
+    w2 = torch.arange(n, 0, -1, dtype=torch.int64, device="cuda")
+    r1 = (kk * w1).sum(1) % 97
+    r2 = (kk * kk * w2).sum(1) % 89
+    out.real.copy_((r1 - 48).to(torch.float64) / 64.0)
+    out.imag.copy_((r2 - 44).to(torch.float64) / 64.0)
+
+
+def test_n10_bound_2e14_beyond_4gib():
+    """N = 10, product bound 2^14 (1,064,429,409 rows; Sec. 3.2, eq. Horner at the largest
+    single-GPU size): complex128 vectors of 17 GB and complex64 of 8.5 GB, so element
+    indices times the record stride pass 2^32 bytes.  The set is too large for per-tile
+    records everywhere, so short tiles take the row kernel.  Sampled rows against the
+    oracle's row-by-row evaluation: the first rows, random rows, rows past 4 GiB in each
+    type, rows of short tiles past 4 GiB, and the last rows; float64 to 1e-12 (2-norm and
+    largest row error), float32 to 1e-5."""
+    import torch
+    from oracle.index import count
+    from paper_1403_3511_amd import hs
+    N10, B10 = 10, 16384
+    tt = hh_workload(N10, 0.111, 0.05)
+    idx = hs.Index(N10, B10)
+    assert idx.size == 1064429409
+    pot = hs.Pot(N10, lib_terms(tt), subtract_harmonic=True)
+    pot.set_time(0.2)
+    k = idx.multi_indices()
+    print(f"N=10 B=16384: {idx.size} rows, tile dimension {idx.tile_dim}", flush=True)
+    c = torch.empty(idx.size, dtype=torch.complex128, device="cuda")
+    step = 50_000_000
+    for i in range(0, idx.size, step):
+        _dyadic_device(k[i:i + step], c[i:i + step])
+    torch.cuda.synchronize()
+    # rows: first, random, past 4 GiB of complex128 (2^28 elements) and of complex64 (2^29),
+    # in short tiles (fewer than 32 rows) past 2^29, and the last ones
+    rng = np.random.default_rng(10)
+    d = idx.tile_dim
+
+    def tile_len(j):
+        return count(d, B10 // int(np.prod(1 + j[:N10 - d].astype(np.int64))))
+
+    far = rng.integers(2 ** 29, idx.size, 4000)
+    short = [r for r in far if tile_len(k[r]) < 32][:25]
+    long_ = [r for r in far if tile_len(k[r]) >= 64][:15]
+    assert len(short) >= 10 and len(long_) >= 10
+    rows = np.concatenate([np.arange(0, 10), rng.integers(0, idx.size, 25),
+                           rng.integers(2 ** 28, 2 ** 29, 15), np.array(short), np.array(long_),
+                           np.arange(idx.size - 15, idx.size)]).astype(np.int64)
+    y_ref = fast_H_rows(N10, B10, oracle_W(N10, tt, 0.2), lambda m: _dyadic(np.array(m))[0], k[rows])
+    rsel = torch.from_numpy(rows).to("cuda")
+    y = torch.empty_like(c)
+    hs.apply_h(idx, pot, c, y)
+    y64 = y[rsel].cpu().numpy()
+    del y
+    e2 = rel2(y64, y_ref)
+    einf = float(np.max(np.abs(y64 - y_ref)) / np.max(np.abs(y_ref)))
+    parts = {"first": slice(0, 10), "random": slice(10, 35), "past 4 GiB": slice(35, 50),
+             "short tiles": slice(50, 50 + len(short)),
+             "long tiles": slice(50 + len(short), 50 + len(short) + len(long_)),
+             "last": slice(len(rows) - 15, len(rows))}
+    errs = {k: rel2(y64[v], y_ref[v]) for k, v in parts.items()}
+    print(f"float64: sampled-row relative error 2-norm {e2:.2e}, inf-norm {einf:.2e}; by kind "
+          + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()), flush=True)
+    assert e2 <= 1e-12 and einf <= 1e-12
+    assert all(v <= 1e-12 for v in errs.values())
+    c32 = c.to(torch.complex64)
+    del c
+    y32 = torch.empty_like(c32)
+    hs.apply_h(idx, pot, c32, y32, hs.HS_C64)
+    y32s = y32[rsel].cpu().numpy().astype(np.complex128)
+    e32 = rel2(y32s, y_ref)
+    print(f"float32: sampled-row relative error against the float64 oracle {e32:.2e}", flush=True)
+    assert e32 <= 1e-5
