@@ -207,6 +207,19 @@ int32_t hs_step(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev, in
                 double t, double *t_dev, double h, int32_t m, int32_t reorth, void *c, void *ws,
                 double *diag_dev, void *stream);
 
+/* hs_step_static: hs_step without a workspace argument, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses that forbid
+ * allocation).  The workspace is a fixed array of HS_STEP_STATIC_MAX_BYTES in the
+ * library's code object, one per GPU, held until the process ends; the call allocates
+ * nothing (no hipMalloc, no library allocator).  Arguments, results and the device
+ * clock t_dev as for hs_step.  HS_E_WORKSPACE when hs_workspace_bytes(idx, pot, dtype, m)
+ * exceeds the array (for complex128 and m = 10, sets up to about 190,000 rows).  All
+ * calls on one GPU share its array: calls that overlap in time on one GPU (several
+ * streams or threads) race and must be serialised by the caller.                  */
+#define HS_STEP_STATIC_MAX_BYTES (32 << 20)
+int32_t hs_step_static(hs_index idx, const void *idx_dev, hs_pot pot, void *pot_dev, int32_t dtype,
+                       double t, double *t_dev, double h, int32_t m, int32_t reorth, void *c,
+                       double *diag_dev, void *stream);
 
 /* Sets of at most `rows` rows (default 1024; the kernel holds one row per thread, at most
  * 1024, so larger values act as 1024) run hs_step / hs_propagate of the paper's operator

@@ -66,6 +66,7 @@ _SIGS = {
     "hs_workspace_bytes": [_vp, _vp, _i32, _i32, _pi64],
     "hs_apply_h": [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "hs_step": [_vp, _vp, _vp, _vp, _i32, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
+    "hs_step_static": [_vp, _vp, _vp, _vp, _i32, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp],
     "hs_magnus4_workspace_bytes": [_vp, _vp, _i32, _i32, _pi64],
     "hs_apply_magnus4": [_vp, _vp, _vp, _vp, _vp, _i32, _f64, _vp, _vp, _vp, _vp],
     "hs_step_magnus4": [_vp, _vp, _vp, _vp, _vp, _i32, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
@@ -425,6 +426,15 @@ def step(idx: Index, pot: Pot, c, t: float, h: float, m: int, dtype: int = HS_C1
         ws = workspace(idx, pot, dtype, m, c.device)
     hs_step(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, float(t), ptr(t_dev), float(h), int(m),
             1 if reorth else 0, ptr(c), ptr(ws), ptr(diag), stream_ptr())
+    return c
+
+
+def step_static(idx: Index, pot: Pot, c, t: float, h: float, m: int, dtype: int = HS_C128,
+                reorth: bool = True, t_dev=None, diag=None):
+    """hs_step with the library's fixed per-GPU workspace (no allocation anywhere)."""
+    _check_step_args("step_static", idx, pot, dtype, m, c, None)
+    hs_step_static(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, float(t), ptr(t_dev), float(h), int(m),
+                   1 if reorth else 0, ptr(c), ptr(diag), stream_ptr())
     return c
 
 
