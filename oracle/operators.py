@@ -10,6 +10,7 @@ approximation written in a per-axis three-term-recurrence basis (Sec. 1.3).
 """
 from __future__ import annotations
 
+import itertools
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -386,6 +387,44 @@ def fast_H_rows(N: int, B: int, pot: Potential, lookup, rows) -> np.ndarray:
 # ----------------------------------------------------------------------------------
 # Chebyshev interpolation of the torsional potential (Sec. 3.4, eq. TorsionalPotential)
 # ----------------------------------------------------------------------------------
+
+
+def exact_H_rows(N: int, B: int, pot: Potential, lookup, rows) -> np.ndarray:
+    """((D + W_K) c)_j, the exact Galerkin product, for the multi-indices j in rows of the
+    set K_N(B), one row at a time (the plain definition of Sec. 1.2, restricted to rows).
+
+    W_K is the Galerkin matrix (phi_j, W^pol phi_m) over K.  By tensor-product
+    orthonormality (Sec. 1.1) its entry is sum_t coef_t prod_l Q^(a_tl)[j_l, m_l] with Q^(a)
+    the exact 1-D matrix of p_a (exact_1d), which vanishes unless |j_l - m_l| <= a_l; m runs
+    over that box, and c(m) = lookup(m) for m in K, 0 outside."""
+    rows = [tuple(int(x) for x in j) for j in rows]
+    kmax = max((max(j) for j in rows), default=0) + max((max(a) for _, a in pot.terms), default=0)
+    Q = {}
+
+    def q(a):
+        if a not in Q:
+            Q[a] = exact_1d(pot.basis, pot.scale, a, kmax)
+        return Q[a]
+
+    out = np.zeros(len(rows), dtype=np.complex128)
+    for r, j in enumerate(rows):
+        acc = (sum(j) + 0.5 * N) * lookup(j)
+        for coef, a in pot.terms:
+            ranges = [range(max(0, j[l] - a[l]), j[l] + a[l] + 1) for l in range(N)]
+            tot = 0.0 + 0.0j
+            for m in itertools.product(*ranges):
+                if np.prod([1 + x for x in m]) > B:
+                    continue
+                w = 1.0
+                for l in range(N):
+                    w *= q(a[l])[j[l], m[l]]
+                    if w == 0.0:
+                        break
+                if w != 0.0:
+                    tot += w * lookup(m)
+            acc += coef * tot
+        out[r] = acc
+    return out
 
 
 def chebyshev_interpolant_1d(f, R: int) -> np.ndarray:

@@ -328,3 +328,25 @@ def test_padded_cross_gives_the_exact_galerkin_product(N, B, w):
             assert err <= 1e-13
         else:
             assert err > 1e-6
+
+
+def test_exact_rows_match_the_dense_galerkin_matrix():
+    """exact_H_rows restates the Galerkin matrix row by row; on a tiny set it must agree
+    with the dense assembly, and differ from the fast algorithm at rows that reach the
+    boundary of K (the reduced set truncates the nested products there)."""
+    import numpy as np
+    from oracle.index import IndexSet
+    from oracle.operators import Potential, dense_H, exact_H_rows, fast_H_rows
+    N, B = 3, 40
+    ix = IndexSet(N, B)
+    rng = np.random.default_rng(5)
+    v = rng.normal(size=ix.size) + 1j * rng.normal(size=ix.size)
+    pos = {tuple(int(x) for x in k): i for i, k in enumerate(ix.k)}
+    look = lambda m: v[pos[tuple(m)]]  # noqa: E731
+    for basis, scale in (("mono", 1.0), ("herm", 1.3)):
+        pot = Potential(N, basis, scale, [(0.2, (2, 1, 0)), (-0.1, (0, 0, 3)), (0.05, (1, 1, 1))])
+        ref = dense_H(ix.k, pot) @ v
+        got = exact_H_rows(N, B, pot, look, ix.k)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+        fast = fast_H_rows(N, B, pot, look, ix.k)
+        assert np.max(np.abs(fast - ref)) > 1e-6 * np.max(np.abs(ref))
