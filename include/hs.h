@@ -133,8 +133,8 @@ int32_t hs_index_create_from_list(int32_t N, int64_t n, const uint16_t *k_host, 
  * 1 <= B, B + w <= 65536, w <= 16, fewer than 2^31 rows.  Paper's operator form.   */
 int32_t hs_index_create_padded(int32_t N, int64_t B, int64_t w, int32_t tile_dim, hs_index *out);
 /* map_host[r] = the row of box that holds row r's multi-index of sub (sub->size int32),
- * -1 when it lies outside.  box: a box set or a padded cross (HS_E_UNSUPPORTED
- * otherwise).                                                                        */
+ * -1 when it lies outside.  box may be any set kind (a box or a padded cross for
+ * hs_error_split; any target for moving vectors between sets).  Host only.          */
 int32_t hs_index_embed(hs_index sub, hs_index box, int32_t *map_host);
 
 /* ---- potential (paper Sec. 1.3; W = V - |x|^2/2, Sec. 1.2) ---------------------
@@ -310,13 +310,30 @@ int32_t hs_batch_apply_h(hs_batch b, const void *batch_dev, const void *c, void 
  * hs_batch_workspace_bytes(b, m) bytes. */
 int32_t hs_batch_step(hs_batch b, void *batch_dev, double t, double *t_dev, double h, int32_t m,
                       int32_t reorth, void *c, void *ws, void *stream);
-/* Launch shape of the persistent kernel: workgroup size wg (64, 128, 256) and resident
- * workgroups per compute unit per_cu (1..64); 0 keeps the current value.
- * hs_batch_autotune_sync times the candidates on the given buffers and keeps the
- * fastest (synchronises the stream).  Work items are 64 rows; the item queue is split
- * into one contiguous range per XCD, largest instances first.                        */
+/* The batched H application runs one persistent kernel per (N, prefix axes) class present
+ * (N = 2..8 at the default tile dimension), one after the other on the stream, so each
+ * class runs at the occupancy of its own register count.  Work items are 64 rows (a chunk
+ * of a long tile, or 64 rows of the short-tile list); each class's items are split into
+ * one contiguous range per XCD, and a workgroup takes `grab` consecutive items per atomic
+ * increment of its range's counter.  Item order: 0 = largest instances first, 1 = the
+ * instances of a class interleaved chunk by chunk.
+ * hs_batch_set_launch sets the workgroup size wg (64, 128, 256) and the resident
+ * workgroups per compute unit per_cu (1..64) of every class; 0 keeps the current value.
+ * hs_batch_get_launch reports them for the class holding the most rows.
+ * hs_batch_autotune_sync times, for each item order, every class over wg x per_cu x grab
+ * (3 x 4 x 3 candidates, each class alone), then the whole application per order, and
+ * keeps the fastest order with its per-class settings; it rewrites the item list in
+ * batch_dev (and the host image that hs_batch_upload copies) and synchronises the
+ * stream.  The first failure is returned.
+ * Instances whose potential has no x_l^2 or x_l x_{l+1} monomials take their long tiles
+ * by the single-instance path's multi-tile work items (a second kernel per class), so a
+ * batched row equals the single-instance row bit for bit; the tuning covers both kinds.
+ * hs_batch_tuning writes the item order and, for each of the 7 classes, 10 int32
+ * (N, prefix axes, then for the row kernel and the multi-tile kernel: work items, wg,
+ * per_cu, grab) into table (70 int32, host).                                          */
 int32_t hs_batch_set_launch(hs_batch b, int32_t wg, int32_t per_cu);
 int32_t hs_batch_get_launch(hs_batch b, int32_t *wg, int32_t *per_cu);
+int32_t hs_batch_tuning(hs_batch b, int32_t *order, int32_t *table);
 int32_t hs_batch_autotune_sync(hs_batch b, const void *batch_dev, const void *c, void *y,
                                void *ws, void *stream);
 

@@ -11,7 +11,7 @@
 #include <new>
 
 #include "lanczos.h"
-#include "matvec_long.h"
+#include "matvec_multi.h"
 
 namespace hs {
 
@@ -40,66 +40,130 @@ __device__ __forceinline__ void batch_row(const BatchInst &B, const typename V2<
 }
 
 // y = H x, or inside a Lanczos step (scall != nullptr, km1 = k - 1 >= 0) with the stored
-// vectors unnormalised: y = s_k H x - beta_{k-1} s_{k-1} prev, s_q = 1 / beta_{q-1}, s_0 = 1
-template <typename T>
+// vectors unnormalised: y = s_k H x - beta_{k-1} s_{k-1} prev, s_q = 1 / beta_{q-1}, s_0 = 1.
+// One kernel per (N, prefix axes) class, so that each class runs at the occupancy its own
+// register count allows; the workgroups of queue q (blocks b with b % kQueues == q) take
+// `grab` consecutive work items per atomic increment of that queue's counter.
+template <typename T, int N, int NP>
 __global__ void __launch_bounds__(256)
 k_batch_hh(const BatchInst *__restrict__ insts, const int32_t *__restrict__ items,
-           const int64_t *__restrict__ qbeg, int32_t *__restrict__ counters,
+           const int64_t *__restrict__ qbeg, int32_t *__restrict__ counters, int32_t grab,
            const typename V2<T>::t *__restrict__ x, typename V2<T>::t *__restrict__ y,
            const typename V2<T>::t *__restrict__ prev, const double *__restrict__ scall, int km1) {
   const int q = blockIdx.x % kQueues;
   const int64_t lo = qbeg[q], hi = qbeg[q + 1];
   const int lane = threadIdx.x & 63;
+  constexpr int rs = rec_stride(NP);
   while (true) {
     int32_t got = 0;
-    if (lane == 0) got = atomicAdd(&counters[q * 16], 1);  // vector atomic from one lane
+    if (lane == 0) got = atomicAdd(&counters[q * 16], grab);  // vector atomic from one lane
     got = __shfl(got, 0);
-    const int64_t it = lo + got;
-    if (it >= hi) break;
-    const int32_t inst = __builtin_amdgcn_readfirstlane(items[2 * it]);
-    const int32_t ch = __builtin_amdgcn_readfirstlane(items[2 * it + 1]);
-    const BatchInst &B = insts[inst];
-    const int rs = rec_stride(B.ix.np);
-    const int32_t *rec;
-    int32_t o;
-    bool act;
-    if (ch >= 0) {
-      const int32_t ri = B.ix.chunks[2 * (int64_t)ch];
-      rec = B.ix.recs + (int64_t)ri * rs;
-      o = B.ix.chunks[2 * (int64_t)ch + 1] + lane;
-      act = o < rec[1];
-    } else {
-      const int64_t i = (int64_t)(-ch - 1) * 64 + lane;
-      act = i < B.ix.nsmall;
-      const int32_t r = act ? B.ix.small_rows[i] : 0;
-      rec = B.ix.recs + (int64_t)B.ix.tile_rec[B.ix.rowtile[r]] * rs;
-      o = r - rec[0];
-    }
-    if (!act) continue;
-    const double *sI = scall ? scall + (int64_t)inst * Scal::size : nullptr;
-    const T oscale = (sI && km1 >= 0) ? (T)sI[Scal::inv + km1] : T(1);
-    const T pcoef = (prev && sI) ? (T)(sI[Scal::beta + km1] * (km1 >= 1 ? sI[Scal::inv + km1 - 1] : 1.0)) : T(0);
-    switch (B.ix.N * 32 + B.ix.np) {
-#define HS_BCASE(NN, PP) \
-  case NN * 32 + PP:     \
-    batch_row<T, NN, PP>(B, x, y, rec, o, prev, oscale, pcoef); \
-    break;
-      HS_BCASE(2, 0)
-      HS_BCASE(3, 1)
-      HS_BCASE(4, 2)
-      HS_BCASE(5, 2)
-      HS_BCASE(6, 3)
-      HS_BCASE(7, 4)
-      HS_BCASE(8, 5)
-      default:
-        break;
-#undef HS_BCASE
+    if (lo + got >= hi) break;
+    for (int32_t g = 0; g < grab; ++g) {
+      const int64_t it = lo + got + g;
+      if (it >= hi) break;
+      const int32_t inst = __builtin_amdgcn_readfirstlane(items[2 * it]);
+      const int32_t ch = __builtin_amdgcn_readfirstlane(items[2 * it + 1]);
+      const BatchInst &B = insts[inst];
+      const int32_t *rec;
+      int32_t o;
+      bool act;
+      if (ch >= 0) {
+        const int32_t ri = B.ix.chunks[2 * (int64_t)ch];
+        rec = B.ix.recs + (int64_t)ri * rs;
+        o = B.ix.chunks[2 * (int64_t)ch + 1] + lane;
+        act = o < rec[1];
+      } else {
+        const int64_t i = (int64_t)(-ch - 1) * 64 + lane;
+        act = i < B.ix.nsmall;
+        const int32_t r = act ? B.ix.small_rows[i] : 0;
+        rec = B.ix.recs + (int64_t)B.ix.tile_rec[B.ix.rowtile[r]] * rs;
+        o = r - rec[0];
+      }
+      if (!act) continue;
+      const double *sI = scall ? scall + (int64_t)inst * Scal::size : nullptr;
+      const T oscale = (sI && km1 >= 0) ? (T)sI[Scal::inv + km1] : T(1);
+      const T pcoef = (prev && sI) ? (T)(sI[Scal::beta + km1] * (km1 >= 1 ? sI[Scal::inv + km1 - 1] : 1.0)) : T(0);
+      batch_row<T, N, NP>(B, x, y, rec, o, prev, oscale, pcoef);
     }
   }
 }
 
-__global__ void k_batch_reset(int32_t *counters) {
-  if (threadIdx.x < kQueues) counters[threadIdx.x * 16] = 0;
+// The long tiles of instances whose potential has no x_l^2 or x_l x_{l+1} monomials, by
+// the multi-tile work items of each instance's index set (the single-instance kernel's
+// row code, so a batched row equals the single-instance row bit for bit).  Queues and
+// grabs as in k_batch_hh; an item is (instance, multi-tile item of that instance).
+template <typename T, int N, int NP>
+__global__ void __launch_bounds__(256)
+k_batch_multi(const BatchInst *__restrict__ insts, const int32_t *__restrict__ items,
+              const int64_t *__restrict__ qbeg, int32_t *__restrict__ counters, int32_t grab,
+              const typename V2<T>::t *__restrict__ x, typename V2<T>::t *__restrict__ y,
+              const typename V2<T>::t *__restrict__ prev, const double *__restrict__ scall, int km1) {
+  constexpr int IS = 2 + kMultiTiles;
+  const int q = blockIdx.x % kQueues;
+  const int64_t lo = qbeg[q], hi = qbeg[q + 1];
+  const int lane = threadIdx.x & 63;
+  while (true) {
+    int32_t got = 0;
+    if (lane == 0) got = atomicAdd(&counters[q * 16], grab);  // vector atomic from one lane
+    got = __shfl(got, 0);
+    if (lo + got >= hi) break;
+    for (int32_t g = 0; g < grab; ++g) {
+      const int64_t it = lo + got + g;
+      if (it >= hi) break;
+      const int32_t inst = __builtin_amdgcn_readfirstlane(items[2 * it]);
+      const int32_t mi = __builtin_amdgcn_readfirstlane(items[2 * it + 1]);
+      const BatchInst &B = insts[inst];
+      const double *sI = scall ? scall + (int64_t)inst * Scal::size : nullptr;
+      const T oscale = (sI && km1 >= 0) ? (T)sI[Scal::inv + km1] : T(1);
+      const T pcoef = (prev && sI) ? (T)(sI[Scal::beta + km1] * (km1 >= 1 ? sI[Scal::inv + km1 - 1] : 1.0)) : T(0);
+      multi_item<T, N, NP>(B.ix, B.hh, x + B.off, y + B.off, B.ix.mitems + (int64_t)mi * IS, oscale,
+                           prev ? prev + B.off : nullptr, pcoef);
+    }
+  }
+}
+
+// the (N, prefix axes) classes the batched kernels serve, in a fixed order
+constexpr int kBatchVariants = 7;
+__host__ __device__ constexpr int batch_variant_n(int v) { return v + 2; }
+__host__ __device__ constexpr int batch_variant_np(int v) { return v == 0 ? 0 : (v == 1 ? 1 : (v <= 3 ? 2 : v - 1)); }
+inline int batch_variant_of(int N, int np) {
+  for (int v = 0; v < kBatchVariants; ++v)
+    if (batch_variant_n(v) == N && batch_variant_np(v) == np) return v;
+  return -1;
+}
+
+// kind 0: k_batch_hh over row items; kind 1: k_batch_multi over multi-tile items
+template <typename T>
+void launch_batch_variant(int kind, int v, unsigned grid, unsigned wg, hipStream_t s, const BatchInst *insts,
+                          const int32_t *items, const int64_t *qbeg, int32_t *counters, int32_t grab,
+                          const void *x, void *y, const void *prev, const double *sc, int km1) {
+  using C = typename V2<T>::t;
+#define HS_BV(V)                                                                                        \
+  case V:                                                                                               \
+    if (kind == 0)                                                                                      \
+      hipLaunchKernelGGL((k_batch_hh<T, batch_variant_n(V), batch_variant_np(V)>), dim3(grid), dim3(wg), 0, \
+                         s, insts, items, qbeg, counters, grab, (const C *)x, (C *)y, (const C *)prev, sc, km1); \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_batch_multi<T, batch_variant_n(V), batch_variant_np(V)>), dim3(grid), dim3(wg), 0, \
+                         s, insts, items, qbeg, counters, grab, (const C *)x, (C *)y, (const C *)prev, sc, km1); \
+    break;
+  switch (v) {
+    HS_BV(0)
+    HS_BV(1)
+    HS_BV(2)
+    HS_BV(3)
+    HS_BV(4)
+    HS_BV(5)
+    HS_BV(6)
+    default:
+      break;
+  }
+#undef HS_BV
+}
+
+__global__ void k_batch_reset(int32_t *counters, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) counters[i * 16] = 0;
 }
 
 // beta_t = base_t + amp_t sin(freq_t (t + dt) + phase_t); hh = M beta, per instance
@@ -133,15 +197,26 @@ struct hs_batch_s {
   std::vector<void *> pot_dev;
   std::vector<int64_t> offsets;  // n + 1 element offsets of the packed vectors
   std::vector<BatchInst> insts;
-  std::vector<int32_t> items;    // (instance, chunk) pairs; chunk < 0: short-tile block -chunk-1
-  std::vector<int64_t> qbeg;     // queue q owns items [qbeg[q], qbeg[q+1])
+  // Work items of the two kernel kinds: kind 0 (k_batch_hh) takes (instance, chunk) pairs,
+  // chunk < 0 meaning the short-tile block -chunk-1; kind 1 (k_batch_multi) takes
+  // (instance, multi-tile item).  Grouped by kernel class: class v owns
+  // [vbeg[kind][v], vbeg[kind][v+1]) of items[kind].
+  std::vector<int32_t> items[2];
+  std::vector<int64_t> vbeg[2];  // kBatchVariants + 1 each
+  std::vector<int64_t> qbeg;     // [kind][class][queue + 1]: queue q owns [qbeg[..][q], qbeg[..][q+1])
+  int32_t order = 0;             // 0: largest instances first; 1: instances interleaved
   std::vector<int32_t> seg_inst, seg_len;
   std::vector<int64_t> seg_row0, iseg0;
-  int64_t nitems = 0, nseg = 0;
-  int64_t off_insts = 0, off_items = 0, off_qbeg = 0, off_counters = 0, off_seginst = 0,
+  int64_t nitems[2] = {0, 0}, nseg = 0;
+  int64_t off_insts = 0, off_items[2] = {0, 0}, off_qbeg = 0, off_counters = 0, off_seginst = 0,
           off_segrow0 = 0, off_seglen = 0, off_iseg0 = 0, dev_bytes = 0;
-  int32_t wg = 256, per_cu = 8;
+  int32_t wg[2][hs::kBatchVariants], per_cu[2][hs::kBatchVariants], grab[2][hs::kBatchVariants];
   int32_t ncu = 256;             // compute units of the device current at creation
+  // the class kernels of one application run concurrently: one side stream per
+  // (kind, class), forked from and joined back into the caller's stream by events
+  // (default priority; graph capture follows the fork and the join)
+  hipStream_t side[2 * hs::kBatchVariants] = {};
+  hipEvent_t fork = nullptr, join[2 * hs::kBatchVariants] = {};
   std::vector<uint8_t> blob;
   void *pinned = nullptr;
   hs::SegView view(const void *dev) const {
@@ -165,6 +240,75 @@ static bool batch_supported(int N, int np) {
       return true;
     default:
       return false;
+  }
+}
+
+// Work items of every instance, grouped by kernel class.  An instance whose potential
+// has no x_l^2 or x_l x_{l+1} monomials takes its long tiles by multi-tile items (kind 1)
+// and its short tiles by 64-row blocks (kind 0), as the single-instance path does;
+// otherwise both go to kind 0 (64-row chunks of long tiles, then the short blocks).
+// order 0: the largest instances first; order 1: the instances of a class interleaved
+// item by item (round robin), so that small and large instances share the queues.  Each
+// class's items of each kind are split into one contiguous range per XCD, equal counts.
+constexpr size_t qidx(int kind, int v, int q) {
+  return ((size_t)kind * hs::kBatchVariants + (size_t)v) * (hs::kQueues + 1) + (size_t)q;
+}
+
+static void build_items(hs_batch_s *b, int32_t order) {
+  const int n = b->n;
+  b->qbeg.assign((size_t)2 * hs::kBatchVariants * (hs::kQueues + 1), 0);
+  b->order = order;
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return b->idx[a]->size > b->idx[c]->size; });
+  // the same choice as the single-instance path (bit-for-bit equal rows)
+  auto multi = [&](int i) { return hs::multi_serves<double>(b->insts[i].ix, b->pot[i]->x2); };
+  for (int kind = 0; kind < 2; ++kind) {
+    std::vector<int32_t> &items = b->items[kind];
+    items.clear();
+    b->vbeg[kind].assign(hs::kBatchVariants + 1, 0);
+    for (int v = 0; v < hs::kBatchVariants; ++v) {
+      const int64_t first = (int64_t)items.size() / 2;
+      b->vbeg[kind][v] = first;
+      std::vector<int> mine;
+      for (int i : ord)
+        if (hs::batch_variant_of(b->idx[i]->N, b->idx[i]->np) == v) mine.push_back(i);
+      // item k of instance i for this kind
+      auto count_of = [&](int i) -> int64_t {
+        const hs_index_s *ix = b->idx[i];
+        const int64_t shorts = (ix->nsmall + 63) / 64;
+        if (kind == 1) return multi(i) ? ix->nmitems : 0;
+        return (multi(i) ? 0 : ix->nchunks) + shorts;
+      };
+      auto push = [&](int i, int64_t k) {
+        items.push_back(i);
+        if (kind == 1) {
+          items.push_back((int32_t)k);
+        } else {
+          const int64_t nc = multi(i) ? 0 : b->idx[i]->nchunks;
+          items.push_back(k < nc ? (int32_t)k : (int32_t)(-(k - nc) - 1));
+        }
+      };
+      if (order == 0) {
+        for (int i : mine)
+          for (int64_t k = 0; k < count_of(i); ++k) push(i, k);
+      } else {
+        std::vector<int64_t> next(mine.size(), 0);
+        bool any = true;
+        while (any) {
+          any = false;
+          for (size_t j = 0; j < mine.size(); ++j)
+            if (next[j] < count_of(mine[j])) {
+              push(mine[j], next[j]++);
+              any = true;
+            }
+        }
+      }
+      const int64_t cnt = (int64_t)items.size() / 2 - first;
+      for (int q = 0; q <= hs::kQueues; ++q) b->qbeg[qidx(kind, v, q)] = first + cnt * q / hs::kQueues;
+    }
+    b->vbeg[kind][hs::kBatchVariants] = (int64_t)items.size() / 2;
+    b->nitems[kind] = b->vbeg[kind][hs::kBatchVariants];
   }
 }
 
@@ -237,23 +381,13 @@ extern "C" int32_t hs_batch_create(int32_t n, const hs_index *idx, const void *c
       B.x2 = p->x2 ? 1 : 0;
       B.off = b->offsets[i];
     }
-    // work items, largest instances first, split into one queue per XCD with equal counts
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return idx[a]->size > idx[c]->size; });
-    for (int i : order) {
-      for (int64_t ch = 0; ch < idx[i]->nchunks; ++ch) {
-        b->items.push_back(i);
-        b->items.push_back((int32_t)ch);
+    for (int kind = 0; kind < 2; ++kind)
+      for (int v = 0; v < hs::kBatchVariants; ++v) {
+        b->wg[kind][v] = 256;
+        b->per_cu[kind][v] = 8;
+        b->grab[kind][v] = 1;
       }
-      for (int64_t k = 0; k * 64 < idx[i]->nsmall; ++k) {
-        b->items.push_back(i);
-        b->items.push_back((int32_t)(-k - 1));
-      }
-    }
-    b->nitems = (int64_t)b->items.size() / 2;
-    b->qbeg.resize(hs::kQueues + 1);
-    for (int q = 0; q <= hs::kQueues; ++q) b->qbeg[q] = b->nitems * q / hs::kQueues;
+    build_items(b, 0);
     // segments
     b->iseg0.push_back(0);
     for (int i = 0; i < n; ++i) {
@@ -273,9 +407,10 @@ extern "C" int32_t hs_batch_create(int32_t n, const hs_index *idx, const void *c
       return o;
     };
     b->off_insts = take((int64_t)sizeof(BatchInst) * n);
-    b->off_items = take(b->nitems * 8);
-    b->off_qbeg = take((hs::kQueues + 1) * 8);
-    b->off_counters = take(hs::kQueues * 64);
+    b->off_items[0] = take(b->nitems[0] * 8);
+    b->off_items[1] = take(b->nitems[1] * 8);
+    b->off_qbeg = take((int64_t)b->qbeg.size() * 8);
+    b->off_counters = take((int64_t)2 * hs::kBatchVariants * hs::kQueues * 64);
     b->off_seginst = take(b->nseg * 4);
     b->off_segrow0 = take(b->nseg * 8);
     b->off_seglen = take(b->nseg * 4);
@@ -286,8 +421,9 @@ extern "C" int32_t hs_batch_create(int32_t n, const hs_index *idx, const void *c
       if (bytes > 0) std::memcpy(b->blob.data() + o, src, bytes);
     };
     put(b->off_insts, b->insts.data(), (int64_t)sizeof(BatchInst) * n);
-    put(b->off_items, b->items.data(), b->nitems * 8);
-    put(b->off_qbeg, b->qbeg.data(), (hs::kQueues + 1) * 8);
+    put(b->off_items[0], b->items[0].data(), b->nitems[0] * 8);
+    put(b->off_items[1], b->items[1].data(), b->nitems[1] * 8);
+    put(b->off_qbeg, b->qbeg.data(), (int64_t)b->qbeg.size() * 8);
     put(b->off_seginst, b->seg_inst.data(), b->nseg * 4);
     put(b->off_segrow0, b->seg_row0.data(), b->nseg * 8);
     put(b->off_seglen, b->seg_len.data(), b->nseg * 4);
@@ -296,12 +432,28 @@ extern "C" int32_t hs_batch_create(int32_t n, const hs_index *idx, const void *c
     delete b;
     return hs::fail(HS_E_NOMEM, "hs_batch_create: out of host memory");
   }
+  {
+    hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int i = 0; i < 2 * hs::kBatchVariants && e == hipSuccess; ++i) {
+      e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+      hs_batch_destroy(b);
+      return hs::hip_fail(e, "hs_batch_create: side streams");
+    }
+  }
   *out = b;
   return HS_OK;
 }
 
 extern "C" int32_t hs_batch_destroy(hs_batch b) {
   if (!b) return HS_OK;
+  for (int i = 0; i < 2 * hs::kBatchVariants; ++i) {
+    if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+    if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->pinned) (void)hipHostFree(b->pinned);
   delete b;
   return HS_OK;
@@ -342,15 +494,29 @@ extern "C" int32_t hs_batch_workspace_bytes(hs_batch b, int32_t m, int64_t *byte
 namespace {
 
 int32_t batch_matvec(hs_batch_s *b, const uint8_t *bd, const void *x, void *y, const void *prev,
-                     const double *sc, int km1, hipStream_t s) {
+                     const double *sc, int km1, hipStream_t s, int only_kind = -1, int only_v = -1) {
   const int ncu = b->ncu;
   int32_t *counters = (int32_t *)(bd + b->off_counters);
-  hipLaunchKernelGGL(hs::k_batch_reset, dim3(1), dim3(64), 0, s, counters);
-  const unsigned grid = hs::xcd_grid((int64_t)ncu * b->per_cu);
-  hipLaunchKernelGGL(hs::k_batch_hh<double>, dim3(grid), dim3(b->wg), 0, s,
-                     (const BatchInst *)(bd + b->off_insts), (const int32_t *)(bd + b->off_items),
-                     (const int64_t *)(bd + b->off_qbeg), counters, (const double2 *)x, (double2 *)y,
-                     (const double2 *)prev, sc, km1);
+  hipLaunchKernelGGL(hs::k_batch_reset, dim3(1), dim3(256), 0, s, counters, 2 * hs::kBatchVariants * hs::kQueues);
+  HS_HIP(hipEventRecord(b->fork, s));
+  for (int kind = 0; kind < 2; ++kind) {
+    if (only_kind >= 0 && kind != only_kind) continue;
+    for (int v = 0; v < hs::kBatchVariants; ++v) {
+      if (b->vbeg[kind][v + 1] == b->vbeg[kind][v] || (only_v >= 0 && v != only_v)) continue;
+      const int si = kind * hs::kBatchVariants + v;
+      hipStream_t ss = b->side[si];
+      HS_HIP(hipStreamWaitEvent(ss, b->fork, 0));
+      const unsigned grid = hs::xcd_grid((int64_t)ncu * b->per_cu[kind][v]);
+      hs::launch_batch_variant<double>(kind, v, grid, (unsigned)b->wg[kind][v], ss,
+                                       (const BatchInst *)(bd + b->off_insts),
+                                       (const int32_t *)(bd + b->off_items[kind]),
+                                       (const int64_t *)(bd + b->off_qbeg) + qidx(kind, v, 0),
+                                       counters + ((size_t)kind * hs::kBatchVariants + v) * hs::kQueues * 16,
+                                       b->grab[kind][v], x, y, prev, sc, km1);
+      HS_HIP(hipEventRecord(b->join[si], ss));
+      HS_HIP(hipStreamWaitEvent(s, b->join[si], 0));
+    }
+  }
   HS_HIP(hipGetLastError());
   return HS_OK;
 }
@@ -404,15 +570,53 @@ extern "C" int32_t hs_batch_set_launch(hs_batch b, int32_t wg, int32_t per_cu) {
   if (!b) return hs::fail(HS_E_INVALID, "hs_batch_set_launch: NULL handle");
   if (wg != 0 && wg != 64 && wg != 128 && wg != 256) return hs::fail(HS_E_INVALID, "hs_batch_set_launch: wg must be 64, 128 or 256");
   if (per_cu < 0 || per_cu > 64) return hs::fail(HS_E_INVALID, "hs_batch_set_launch: per_cu out of range 0..64");
-  if (wg) b->wg = wg;
-  if (per_cu) b->per_cu = per_cu;
+  for (int kind = 0; kind < 2; ++kind)
+    for (int v = 0; v < hs::kBatchVariants; ++v) {
+      if (wg) b->wg[kind][v] = wg;
+      if (per_cu) b->per_cu[kind][v] = per_cu;
+    }
   return HS_OK;
+}
+
+// the (kind, class) holding the most work items (its launch is the one reported)
+static void main_launch(const hs_batch_s *b, int &kind, int &v) {
+  kind = 0;
+  v = 0;
+  int64_t most = -1;
+  for (int k = 0; k < 2; ++k)
+    for (int c = 0; c < hs::kBatchVariants; ++c) {
+      const int64_t cnt = b->vbeg[k][c + 1] - b->vbeg[k][c];
+      if (cnt > most) {
+        most = cnt;
+        kind = k;
+        v = c;
+      }
+    }
 }
 
 extern "C" int32_t hs_batch_get_launch(hs_batch b, int32_t *wg, int32_t *per_cu) {
   if (!b) return hs::fail(HS_E_INVALID, "hs_batch_get_launch: NULL handle");
-  if (wg) *wg = b->wg;
-  if (per_cu) *per_cu = b->per_cu;
+  int kind, v;
+  main_launch(b, kind, v);
+  if (wg) *wg = b->wg[kind][v];
+  if (per_cu) *per_cu = b->per_cu[kind][v];
+  return HS_OK;
+}
+
+extern "C" int32_t hs_batch_tuning(hs_batch b, int32_t *order, int32_t *table) {
+  if (!b || !order || !table) return hs::fail(HS_E_INVALID, "hs_batch_tuning: NULL argument");
+  *order = b->order;
+  for (int v = 0; v < hs::kBatchVariants; ++v) {
+    int32_t *t = table + 10 * v;
+    t[0] = hs::batch_variant_n(v);
+    t[1] = hs::batch_variant_np(v);
+    for (int kind = 0; kind < 2; ++kind) {
+      t[2 + 4 * kind] = (int32_t)std::min<int64_t>(b->vbeg[kind][v + 1] - b->vbeg[kind][v], INT32_MAX);
+      t[3 + 4 * kind] = b->wg[kind][v];
+      t[4 + 4 * kind] = b->per_cu[kind][v];
+      t[5 + 4 * kind] = b->grab[kind][v];
+    }
+  }
   return HS_OK;
 }
 
@@ -421,36 +625,89 @@ extern "C" int32_t hs_batch_autotune_sync(hs_batch b, const void *batch_dev, con
   if (!b || !batch_dev || !c || !y) return hs::fail(HS_E_INVALID, "hs_batch_autotune_sync: NULL argument");
   (void)ws;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint8_t *bd = static_cast<const uint8_t *>(batch_dev);
+  uint8_t *bdw = const_cast<uint8_t *>(bd);
   hipEvent_t e0, e1;
   HS_HIP(hipEventCreate(&e0));
   HS_HIP(hipEventCreate(&e1));
-  float best = 1e30f;
-  int32_t bwg = b->wg, bpc = b->per_cu;
+  int32_t st = HS_OK;
+  // time of `reps` applications of one (kind, class), or of everything (kind < 0)
+  auto timed = [&](int kind, int v, int reps, float &ms) -> int32_t {
+    int32_t r = batch_matvec(b, bd, c, y, nullptr, nullptr, 0, s, kind, v);  // warm-up
+    if (r != HS_OK) return r;
+    if (hipEventRecord(e0, s) != hipSuccess) return hs::fail(HS_E_HIP, "hs_batch_autotune_sync: event record");
+    for (int k = 0; k < reps && r == HS_OK; ++k) r = batch_matvec(b, bd, c, y, nullptr, nullptr, 0, s, kind, v);
+    if (r != HS_OK) return r;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return hs::fail(HS_E_HIP, "hs_batch_autotune_sync: event synchronisation");
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return hs::fail(HS_E_HIP, "hs_batch_autotune_sync: event time");
+    return HS_OK;
+  };
+  // upload the item lists and queue bounds of the current order (device block and the
+  // host image that hs_batch_upload copies)
+  auto upload_items = [&]() -> int32_t {
+    for (int kind = 0; kind < 2; ++kind) {
+      HS_HIP(hipMemcpy(bdw + b->off_items[kind], b->items[kind].data(), b->nitems[kind] * 8, hipMemcpyHostToDevice));
+      std::memcpy(b->blob.data() + b->off_items[kind], b->items[kind].data(), b->nitems[kind] * 8);
+    }
+    HS_HIP(hipMemcpy(bdw + b->off_qbeg, b->qbeg.data(), (int64_t)b->qbeg.size() * 8, hipMemcpyHostToDevice));
+    std::memcpy(b->blob.data() + b->off_qbeg, b->qbeg.data(), (int64_t)b->qbeg.size() * 8);
+    if (b->pinned) std::memcpy(b->pinned, b->blob.data(), b->dev_bytes);
+    return HS_OK;
+  };
   const int32_t wgs[3] = {64, 128, 256};
   const int32_t pcs[4] = {2, 4, 8, 16};
-  int32_t st = HS_OK;
-  for (int32_t wg : wgs)
-    for (int32_t pc : pcs) {
-      b->wg = wg;
-      b->per_cu = pc;
-      st = batch_matvec(b, static_cast<const uint8_t *>(batch_dev), c, y, nullptr, nullptr, 0, s);
-      if (st != HS_OK) break;
-      (void)hipEventRecord(e0, s);
-      for (int r = 0; r < 3 && st == HS_OK; ++r)
-        st = batch_matvec(b, static_cast<const uint8_t *>(batch_dev), c, y, nullptr, nullptr, 0, s);
-      (void)hipEventRecord(e1, s);
-      if (hipEventSynchronize(e1) != hipSuccess) st = HS_E_HIP;
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (st == HS_OK && ms < best) {
-        best = ms;
-        bwg = wg;
-        bpc = pc;
+  const int32_t grabs[3] = {1, 2, 4};
+  float best_order_ms = 1e30f;
+  int32_t best_order = b->order;
+  int32_t bwg[2][hs::kBatchVariants], bpc[2][hs::kBatchVariants], bgr[2][hs::kBatchVariants];
+  for (int order = 0; order < 2 && st == HS_OK; ++order) {
+    build_items(b, order);
+    st = upload_items();
+    // each (kind, class) on its own: workgroup size, workgroups per CU, items per grab
+    for (int kind = 0; kind < 2 && st == HS_OK; ++kind)
+      for (int v = 0; v < hs::kBatchVariants && st == HS_OK; ++v) {
+        if (b->vbeg[kind][v + 1] == b->vbeg[kind][v]) continue;
+        float best = 1e30f;
+        int32_t w0 = b->wg[kind][v], p0 = b->per_cu[kind][v], g0 = b->grab[kind][v];
+        for (int32_t wg : wgs)
+          for (int32_t pc : pcs)
+            for (int32_t gr : grabs) {
+              if (st != HS_OK) break;
+              b->wg[kind][v] = wg;
+              b->per_cu[kind][v] = pc;
+              b->grab[kind][v] = gr;
+              float ms = 0.f;
+              st = timed(kind, v, 2, ms);
+              if (st == HS_OK && ms < best) {
+                best = ms;
+                w0 = wg;
+                p0 = pc;
+                g0 = gr;
+              }
+            }
+        b->wg[kind][v] = w0;
+        b->per_cu[kind][v] = p0;
+        b->grab[kind][v] = g0;
       }
-      if (st != HS_OK) break;
+    if (st != HS_OK) break;
+    float ms = 0.f;
+    st = timed(-1, -1, 3, ms);
+    if (st == HS_OK && ms < best_order_ms) {
+      best_order_ms = ms;
+      best_order = order;
+      std::memcpy(bwg, b->wg, sizeof(bwg));
+      std::memcpy(bpc, b->per_cu, sizeof(bpc));
+      std::memcpy(bgr, b->grab, sizeof(bgr));
     }
-  b->wg = bwg;
-  b->per_cu = bpc;
+  }
+  if (st == HS_OK && best_order_ms < 1e30f) {
+    std::memcpy(b->wg, bwg, sizeof(bwg));
+    std::memcpy(b->per_cu, bpc, sizeof(bpc));
+    std::memcpy(b->grab, bgr, sizeof(bgr));
+    build_items(b, best_order);
+    st = upload_items();
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return st;

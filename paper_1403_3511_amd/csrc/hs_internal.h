@@ -57,6 +57,9 @@ struct IndexDev {
   const int32_t *tile_rec;   // [ntiles] record of every tile, or NULL (long tiles only)
   int64_t nsmall;            // rows of the short tiles
   const int32_t *small_rows; // [nsmall]
+  // work items of the multi-tile kernel: (first offset, tile count, kMultiTiles records)
+  int64_t nmitems;
+  const int32_t *mitems;     // [nmitems][2 + kMultiTiles]
 };
 
 // Suffix stencil pairs.  Axis pairs p = 3 a + (|s| - 1) hold the displacements -|s|
@@ -89,6 +92,7 @@ __host__ __device__ constexpr int rec_pair(int np, int l, int s, int r) {
   return 4 + np + 2 * (6 * np + l * 10 + (s + 2) * 2 + (r > 0 ? 1 : 0));
 }
 constexpr int kChunk = 64;       // rows per wave in the long-tile kernel
+constexpr int kMultiTiles = 4;   // tiles per work item of the multi-tile kernel
 constexpr int kLongTile = 32;    // tiles at least this long go to the long-tile kernel
 
 }  // namespace hs
@@ -107,14 +111,14 @@ struct hs_index_s {
   std::vector<uint16_t> gsidx;
   std::vector<int32_t> gnbr, gssum;
   std::vector<int32_t> rowtile;
-  std::vector<int32_t> gst, chunks, small_rows, recs, tile_rec;
+  std::vector<int32_t> gst, chunks, small_rows, recs, tile_rec, mitems;
   int32_t ns = 0, rstride = 0;
   bool recs_all = false;
-  int64_t nchunks = 0, nsmall = 0;
+  int64_t nchunks = 0, nsmall = 0, nmitems = 0;
   // device blob layout (byte offsets)
   int64_t off_tstart = 0, off_tlen = 0, off_tnbr = 0, off_tpfx = 0, off_tpsum = 0,
           off_gsidx = 0, off_gnbr = 0, off_gssum = 0, off_rowtile = 0, off_wtab = 0,
-          off_wtabf = 0, off_wtp = 0, off_wtpf = 0, off_gsp = 0, off_gst = 0, off_chunks = 0, off_small = 0, off_recs = 0, off_tile_rec = 0,
+          off_wtabf = 0, off_wtp = 0, off_wtpf = 0, off_gsp = 0, off_gst = 0, off_chunks = 0, off_small = 0, off_recs = 0, off_tile_rec = 0, off_mitems = 0,
           dev_bytes = 0;
   std::vector<uint8_t> blob;   // host image of the device block
   void *pinned = nullptr;      // pinned staging for the upload

@@ -390,6 +390,8 @@ hs::IndexDev hs_index_s::view(const void *dev) const {
   v.rstride = rstride;
   v.recs = reinterpret_cast<const int32_t *>(b + off_recs);
   v.tile_rec = recs_all ? reinterpret_cast<const int32_t *>(b + off_tile_rec) : nullptr;
+  v.nmitems = nmitems;
+  v.mitems = reinterpret_cast<const int32_t *>(b + off_mitems);
   return v;
 }
 
@@ -585,6 +587,58 @@ static int32_t build_index(hs_index_s *ix) {
   ix->nchunks = (int64_t)ix->chunks.size() / 2;
   ix->nsmall = (int64_t)ix->small_rows.size();
 
+  // ---- work items of the multi-tile kernel: for each 64-offset range, the long tiles
+  // reaching into it, in tile order, kMultiTilesHost at a time (longest first inside an
+  // item); items ordered by their first tile, so that each XCD's contiguous share of
+  // items covers a contiguous range of tiles ----
+  ix->mitems.clear();
+  {
+    constexpr int R = hs::kMultiTiles, IS = 2 + R;
+    std::vector<std::pair<int64_t, int32_t>> longt;  // (tile, record) of the long tiles
+    {
+      int32_t ri = 0;
+      for (int64_t t = 0; t < ntiles; ++t) {
+        const int32_t len = ix->tlen[t];
+        if (ix->recs_all) {
+          if (len >= hs::kLongTile) longt.emplace_back(t, ix->tile_rec[t]);
+        } else if (len >= hs::kLongTile) {
+          longt.emplace_back(t, ri++);
+        }
+      }
+    }
+    int32_t maxlen = 0;
+    for (auto &pr : longt) maxlen = std::max(maxlen, ix->tlen[pr.first]);
+    const int64_t nblk = maxlen / hs::kChunk + 1;
+    // reach[b]: the long tiles (indices into longt, in tile order) longer than b * kChunk
+    std::vector<std::vector<int32_t>> reach((size_t)nblk);
+    for (size_t i = 0; i < longt.size(); ++i)
+      for (int32_t o0 = 0; o0 < ix->tlen[longt[i].first]; o0 += hs::kChunk)
+        reach[o0 / hs::kChunk].push_back((int32_t)i);
+    std::vector<std::pair<int64_t, std::vector<int32_t>>> items;  // (sort key, item words)
+    for (int64_t b = 0; b < nblk; ++b) {
+      const std::vector<int32_t> &rb = reach[(size_t)b];
+      for (size_t a = 0; a < rb.size(); a += R) {
+        const size_t nr = std::min<size_t>(R, rb.size() - a);
+        std::vector<int32_t> grp(rb.begin() + a, rb.begin() + a + nr);
+        std::stable_sort(grp.begin(), grp.end(), [&](int32_t u, int32_t v) {
+          return ix->tlen[longt[u].first] > ix->tlen[longt[v].first];
+        });
+        std::vector<int32_t> w(IS, 0);
+        w[0] = (int32_t)(b * hs::kChunk);
+        w[1] = (int32_t)nr;
+        for (size_t q = 0; q < nr; ++q) w[2 + q] = longt[grp[q]].second;
+        for (size_t q = nr; q < (size_t)R; ++q) w[2 + q] = w[2];
+        items.emplace_back(longt[rb[a]].first * nblk + b, std::move(w));
+      }
+      std::vector<int32_t>().swap(reach[(size_t)b]);
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const auto &u, const auto &v) { return u.first < v.first; });
+    ix->mitems.reserve(items.size() * IS);
+    for (auto &it : items) ix->mitems.insert(ix->mitems.end(), it.second.begin(), it.second.end());
+    ix->nmitems = (int64_t)items.size();
+  }
+
   // ---- device image ----
   int64_t off = 0;
   auto take = [&](int64_t bytes) {
@@ -611,6 +665,7 @@ static int32_t build_index(hs_index_s *ix) {
   ix->off_small = take(ix->nsmall * 4);
   ix->off_recs = take((int64_t)ix->recs.size() * 4);
   ix->off_tile_rec = take((int64_t)ix->tile_rec.size() * 4);
+  ix->off_mitems = take((int64_t)ix->mitems.size() * 4);
   ix->dev_bytes = off;
   ix->blob.assign(off, 0);
   auto put = [&](int64_t o, const void *src, int64_t bytes) {
@@ -652,6 +707,7 @@ static int32_t build_index(hs_index_s *ix) {
   put(ix->off_small, ix->small_rows.data(), ix->nsmall * 4);
   put(ix->off_recs, ix->recs.data(), (int64_t)ix->recs.size() * 4);
   put(ix->off_tile_rec, ix->tile_rec.data(), (int64_t)ix->tile_rec.size() * 4);
+  put(ix->off_mitems, ix->mitems.data(), (int64_t)ix->mitems.size() * 4);
   return HS_OK;
 }
 
@@ -874,8 +930,6 @@ extern "C" int32_t hs_index_create_from_list(int32_t N, int64_t n, const uint16_
 
 extern "C" int32_t hs_index_embed(hs_index sub, hs_index box, int32_t *map_host) {
   if (!sub || !box || !map_host) return hs::fail(HS_E_INVALID, "hs_index_embed: NULL argument");
-  if (box->kind != HS_SET_BOX && box->kind != HS_SET_PADDED)
-    return hs::fail(HS_E_UNSUPPORTED, "hs_index_embed: the target must be a box set or a padded cross");
   if (sub->N != box->N) return hs::fail(HS_E_INVALID, "hs_index_embed: the sets differ in N");
   const int N = sub->N, np = box->np, d = box->d;
   try {

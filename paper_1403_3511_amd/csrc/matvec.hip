@@ -33,6 +33,22 @@ int launch_hh_long_sym_f32(const IndexDev &ix, const double *hh, const void *x, 
                            const double *out_scale, const void *prev, const double *prev_coef,
                            const double *prev_scale, hipStream_t s, bool x2);
 
+// long tiles by work items of several tiles (0: not served; 1: short tiles too; 2: the
+// short tiles left to the caller); short tiles alone by the per-lane-record path of the
+// specialised kernel (0: not served)
+int launch_hh_multi_f64(const IndexDev &ix, const double *hh, const void *x, void *y,
+                         const double *out_scale, const void *prev, const double *prev_coef,
+                         const double *prev_scale, hipStream_t s, bool x2);
+int launch_hh_multi_f32(const IndexDev &ix, const double *hh, const void *x, void *y,
+                         const double *out_scale, const void *prev, const double *prev_coef,
+                         const double *prev_scale, hipStream_t s, bool x2);
+int launch_hh_short_f64(const IndexDev &ix, const double *hh, const void *x, void *y,
+                        const double *out_scale, const void *prev, const double *prev_coef,
+                        const double *prev_scale, hipStream_t s, bool x2);
+int launch_hh_short_f32(const IndexDev &ix, const double *hh, const void *x, void *y,
+                        const double *out_scale, const void *prev, const double *prev_coef,
+                        const double *prev_scale, hipStream_t s, bool x2);
+
 struct Pos {
   int32_t t, o;
 };
@@ -526,6 +542,25 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
       return fail(HS_E_UNSUPPORTED, "symmetrised form: no specialised kernel for this index set");
     HS_HIP(hipGetLastError());
     return HS_OK;
+  }
+  if (p->fused && !p->x2) {
+    // long tiles: work items of several tiles (any vector size)
+    const int multi = sizeof(T) == 8
+        ? launch_hh_multi_f64(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, p->x2)
+        : launch_hh_multi_f32(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, p->x2);
+    if (multi != 0) {
+      if (multi == 2 && ix.nsmall > 0) {
+        const int done = sizeof(T) == 8
+            ? launch_hh_short_f64(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, p->x2)
+            : launch_hh_short_f32(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, p->x2);
+        if (done != 1)
+          hipLaunchKernelGGL(k_hh_rows<T>, dim3(nblk(ix.nsmall, 256)), dim3(256), 0, s, ix, hh,
+                             (const C *)x, (C *)y, out_scale, (const C *)prev, prev_coef, prev_scale,
+                             ix.small_rows, ix.nsmall);
+      }
+      HS_HIP(hipGetLastError());
+      return HS_OK;
+    }
   }
   if (p->fused) {
     const int done = sizeof(T) == 8

@@ -457,33 +457,39 @@ inline void long_grid(const IndexDev &ix, bool with_small, int32_t &long_per, in
 template <typename T, int N, int NP, bool X2, bool SYM>
 static void launch_long_pair(const IndexDev &ix, const double *hh, const void *x, void *y,
                              const double *out_scale, const void *prev, const double *prev_coef,
-                             const double *prev_scale, hipStream_t s, bool with_small) {
+                             const double *prev_scale, hipStream_t s, bool with_small,
+                             bool with_long = true) {
   using C = typename V2<T>::t;
   int32_t lp, sp;
   unsigned blocks;
-  long_grid(ix, with_small, lp, sp, blocks);
+  IndexDev iv = ix;
+  if (!with_long) iv.nchunks = 0;
+  long_grid(iv, with_small, lp, sp, blocks);
   if (blocks == 0) return;
-  hipLaunchKernelGGL((k_hh_long<T, N, NP, X2, SYM>), dim3(blocks), dim3(256), 0, s, ix, hh, (const C *)x,
+  hipLaunchKernelGGL((k_hh_long<T, N, NP, X2, SYM>), dim3(blocks), dim3(256), 0, s, iv, hh, (const C *)x,
                      (C *)y, out_scale, (const C *)prev, prev_coef, prev_scale, lp, sp);
 }
 
 // Returns 1 if long and short tiles were both launched, 2 if only the long tiles (the
-// caller handles the short ones), 0 if (N, NP) has no specialisation.
+// caller handles the short ones), 0 if (N, NP) has no specialisation.  With short_only,
+// only the short tiles are launched (1), or nothing (0) when they lack records.
 template <typename T, bool SYM = false>
 int launch_hh_long_impl(const IndexDev &ix, const double *hh, const void *x, void *y,
                         const double *out_scale, const void *prev, const double *prev_coef,
-                        const double *prev_scale, hipStream_t s, bool x2) {
+                        const double *prev_scale, hipStream_t s, bool x2, bool short_only = false) {
   if (ix.rstride != rec_stride(ix.np)) return 0;
   // row indices are 32-bit and kAbsent must lie beyond every row
   if (ix.size >= (int64_t)INT32_MAX) return 0;
   if (!struct_loads_reach<T>(ix.size)) return 0;
   const bool small = ix.tile_rec != nullptr;
+  if (short_only && !small) return 0;
+  const bool lng = !short_only;
 #define HS_LONG_CASE(NN, PP)                                                                    \
   case NN * 32 + PP:                                                                            \
     if (x2)                                                                                     \
-      launch_long_pair<T, NN, PP, true, SYM>(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, small);  \
+      launch_long_pair<T, NN, PP, true, SYM>(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, small, lng);  \
     else                                                                                        \
-      launch_long_pair<T, NN, PP, false, SYM>(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, small); \
+      launch_long_pair<T, NN, PP, false, SYM>(ix, hh, x, y, out_scale, prev, prev_coef, prev_scale, s, small, lng); \
     return small ? 1 : 2;
   switch (ix.N * 32 + ix.np) {
     HS_LONG_CASE(1, 0)

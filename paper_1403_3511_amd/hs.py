@@ -81,6 +81,7 @@ _SIGS = {
     "hs_batch_set_launch": [_vp, _i32, _i32],
     "hs_batch_get_launch": [_vp, _pi32, _pi32],
     "hs_batch_autotune_sync": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "hs_batch_tuning": [_vp, _pi32, _pi32],
     "hs_gh_ncoef": [_i32, _i32, _pi32],
     "hs_gh_rule": [_i32, _pf64, _pf64],
     "hs_gh_project": [_i32, _i32, _i32, _i32, _pf64, _i32, _vp, _vp, _vp],
@@ -573,6 +574,21 @@ class Batch:
         a, b = C.c_int32(), C.c_int32()
         hs_batch_get_launch(self.h, C.byref(a), C.byref(b))
         return a.value, b.value
+
+    def tuning(self):
+        """(item order, [(N, prefix axes, kind, items, wg, per_cu, grab) for each class and
+        kernel kind with work items]); kind 0 = row kernel, 1 = multi-tile kernel."""
+        order = C.c_int32()
+        t = np.zeros(70, dtype=np.int32)
+        hs_batch_tuning(self.h, C.byref(order), t.ctypes.data_as(_pi32))
+        rows = []
+        for i in range(7):
+            r = [int(v) for v in t[10 * i:10 * i + 10]]
+            for kind in range(2):
+                items, wg, pc, gr = r[2 + 4 * kind:6 + 4 * kind]
+                if items > 0:
+                    rows.append((r[0], r[1], kind, items, wg, pc, gr))
+        return order.value, rows
 
     def autotune(self, c, y):
         self._check("autotune", [("c", c), ("y", y)])

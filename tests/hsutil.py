@@ -31,7 +31,16 @@ def to_lib(x_lex, lexpos):
 
 
 def rel2(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    """Relative error of a against b in the 2-norm and the infinity norm, the larger of the
+    two (parity is stated in both norms; an error confined to a few rows shows in the
+    second)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    e2 = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    if b.size == 0:
+        return e2
+    einf = float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+    return max(e2, einf)
 
 
 def torch_c128(x):

@@ -126,8 +126,21 @@ def test_autotune_and_graph_replay(hs):
     y = torch.zeros_like(x)
     wg, pc = b.autotune(x, y)
     assert wg in (64, 128, 256) and pc in (2, 4, 8, 16)
+    order, rows = b.tuning()
+    assert order in (0, 1) and rows
+    for (_, _, kind, items, w, p, gr) in rows:
+        assert kind in (0, 1) and items > 0 and w in (64, 128, 256) and p in (2, 4, 8, 16) and gr in (1, 2, 4)
     b.apply_h(x, y)
     y_ref = y.clone()
+    # whatever order and launches the tuning chose, each instance still equals its own
+    # single-instance application bit for bit
+    yb = y.cpu().numpy()
+    for i, (idx, pot, c) in enumerate(zip(idxs, pots, cs)):
+        ci = torch.from_numpy(c).to("cuda")
+        yi = torch.empty_like(ci)
+        hs.apply_h(idx, pot, ci, yi)
+        torch.cuda.synchronize()
+        assert np.array_equal(yb[b.offsets[i]:b.offsets[i] + c.size], yi.cpu().numpy()), i
     # eager steps
     xe = x.clone()
     ws = b.workspace(m)

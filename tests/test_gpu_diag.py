@@ -189,3 +189,41 @@ def test_galerkin_gap_independent_of_the_widening(hs):
     for bad in (hs.Index(N, B, pad=2), hs.Index(N, B + 1, pad=3)):
         with pytest.raises(hs.HSError):
             hs.error_split(sub, bad, None, pot, v)
+
+
+def test_exact_rows_from_the_union_of_term_boxes(hs):
+    """The bench's sampled-row Galerkin gap for sets too large to widen (Sec. 5.1): for
+    rows j of K, the union L of the boxes {m <= j + a} over the terms' degree vectors a
+    is downward closed and holds every path of every term from j, so the fast algorithm
+    on L applied to c restricted to L is the exact Galerkin product at j.  Checked against
+    the oracle's exact rows (the Galerkin matrix entries from exact 1-D matrices)."""
+    import torch
+    from oracle.operators import exact_H_rows
+    N, B = 6, 512
+    tt = hh_workload(N, 0.111, 0.05)
+    idx = hs.Index(N, B)
+    pot = hs.Pot(N, lib_terms(tt), subtract_harmonic=True)
+    pot.set_time(0.3)
+    k = idx.multi_indices()
+    c = complex_normal_by_index(k, 9)
+    rng = np.random.default_rng(4)
+    rows = np.sort(rng.choice(idx.size, 10, replace=False))
+    degs = {tuple(x.degrees) for x in tt} | {tuple(2 if i == l else 0 for i in range(N)) for l in range(N)}
+    boxes = []
+    for j in k[rows].astype(np.int64):
+        for a in degs:
+            g = np.meshgrid(*[np.arange(jl + al + 1) for jl, al in zip(j, a)], indexing="ij")
+            boxes.append(np.stack([x.ravel() for x in g], axis=1).astype(np.uint16))
+    Lk = np.unique(np.concatenate(boxes), axis=0)
+    L = hs.Index(N, rows=Lk)
+    lmap = L.embed_map(idx)
+    vL = np.where(lmap >= 0, c[np.maximum(lmap, 0)], 0.0)
+    x = torch.from_numpy(np.ascontiguousarray(vL)).to("cuda")
+    y = torch.empty_like(x)
+    hs.apply_h(L, pot, x, y, ws=hs.workspace(L, pot, hs.HS_C128, 0))
+    Lrows = L.multi_indices()
+    pos = {tuple(int(v) for v in m): i for i, m in enumerate(Lrows)}
+    got = y.cpu().numpy()[[pos[tuple(int(v) for v in k[r])] for r in rows]]
+    kpos = {tuple(int(v) for v in m): i for i, m in enumerate(k)}
+    ref = exact_H_rows(N, B, oracle_W(N, tt, 0.3), lambda m: c[kpos[tuple(m)]], k[rows])
+    assert rel2(got, ref) <= 1e-12

@@ -284,7 +284,9 @@ def test_bench_size_sampled_rows(hs):
 
 def test_constant_potential_equals_midpoint_step(hs):
     """Without time dependence A_1 = A_2: the GPU's commutator is exactly zero and the
-    fourth-order step reproduces the midpoint step bit for bit (benchmark size)."""
+    fourth-order step reproduces the midpoint step (benchmark size) to rounding: the
+    fused Magnus passes and the midpoint step's H application evaluate the same rows with
+    different row codes (operation order)."""
     import torch
     N, B, m, h = 6, 4096, 6, 0.01
     tt = hh_workload(N, 0.111, 0.0)
@@ -299,7 +301,8 @@ def test_constant_potential_equals_midpoint_step(hs):
     hs.step(idx, pot, a, 0.0, h, m, reorth=True)
     hs.step_magnus4(idx, pot, b, 0.0, h, m, reorth=True)
     torch.cuda.synchronize()
-    assert torch.equal(a, b)
+    assert float(torch.linalg.norm(a - b) / torch.linalg.norm(a)) <= 1e-14
+    assert float((a - b).abs().max() / a.abs().max()) <= 1e-14
 
 
 @pytest.mark.parametrize("case", ["m1", "h0", "zero"])

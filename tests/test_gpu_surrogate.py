@@ -171,7 +171,7 @@ def trained(hs):
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     g = torch.Generator(device="cpu").manual_seed(0)
     losses = []
-    nsteps, bs = 4000, 256
+    nsteps, bs = 12000, 256
     for it in range(nsteps):
         sel = torch.randint(0, 4096, (bs,), generator=g).to("cuda")
         lr = 2e-3 * 0.5 * (1 + math.cos(math.pi * it / nsteps)) + 1e-5
@@ -201,9 +201,10 @@ def test_surrogate_accuracy_and_gain(hs, trained):
     scale = np.linalg.norm(J, axis=1)
     e_mlp = float(np.median(np.linalg.norm(pred.cpu().numpy() - J, axis=1) / scale))
     errs = {}
-    for Q in range(4, 17):
+    for Q in range(2, 17):
         c = hs.gh_project(geom, Pv, D, Q).cpu().numpy()
         errs[Q] = float(np.median(np.linalg.norm(c - J, axis=1) / scale))
+    # the cheapest quadrature at least as accurate as the network
     q_match = min([Q for Q in errs if errs[Q] <= e_mlp] or [16])
 
     def timeit(fn, reps=20):
@@ -225,7 +226,9 @@ def test_surrogate_accuracy_and_gain(hs, trained):
           f"quadrature Q={q_match} (as accurate as the network) {t_qm*1e6:.1f} us")
     assert e_mlp < 2e-2
     assert errs[16] < 1e-6
-    assert t_mlp < t_q16
+    assert q_match > 2  # the network beats the coarsest rule
+    # the gain: the network is faster than the quadrature of the same accuracy
+    assert t_mlp < t_qm
 
 
 def test_fallback_outside_box(hs, trained):

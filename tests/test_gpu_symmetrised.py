@@ -145,8 +145,9 @@ def test_symmetry_at_bench_size(hs):
 
 
 def test_one_axis_and_no_coupling_equal_the_paper_form(hs):
-    """N = 1, and a potential without coupling terms: both forms are the same operator,
-    and the kernel returns the same values."""
+    """N = 1, and a potential without coupling terms: both forms are the same operator, and
+    the kernels return the same values to rounding (the paper's form may take the
+    multi-tile row code, the symmetrised form its own)."""
     import torch
     for N, terms in [(1, [(0.05, (3,)), (0.1, (1,)), (0.2, (2,))]),
                      (3, [(0.05, (3, 0, 0)), (-0.02, (0, 0, 3)), (0.1, (0, 1, 0))])]:
@@ -160,4 +161,4 @@ def test_one_axis_and_no_coupling_equal_the_paper_form(hs):
         pot.set_form(hs.HS_FORM_SYM)
         hs.apply_h(idx, pot, x, yb)
         torch.cuda.synchronize()
-        assert float(torch.linalg.norm(ya - yb) / torch.linalg.norm(ya)) <= 1e-15
+        assert float(torch.linalg.norm(ya - yb) / torch.linalg.norm(ya)) <= 1e-14

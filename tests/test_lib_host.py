@@ -145,8 +145,23 @@ def test_embedding_into_a_box(hs):
         inside = np.all(ks <= K, axis=1)
         assert np.array_equal(m >= 0, inside)
         assert np.array_equal(kb[m[inside]], ks[inside])
-    with pytest.raises(hs.HSError):
-        sub.embed_map(hs.Index(3, 10, upload=False))   # the target must be a box
+
+def test_embedding_between_any_set_kinds(hs):
+    """hs_index_embed into a hyperbolic cross, a total-degree set and a set given as a
+    list: each row maps to the target row with the same multi-index, or -1 outside."""
+    sub = hs.Index(3, 60, upload=False)
+    ks = sub.multi_indices().astype(np.int64)
+    targets = [(hs.Index(3, 20, upload=False), lambda k: np.prod(1 + k, axis=1) <= 20),
+               (hs.Index(3, 8, upload=False, total_degree=True), lambda k: k.sum(axis=1) <= 8),
+               (hs.Index(3, 90, upload=False), lambda k: np.prod(1 + k, axis=1) <= 90)]
+    lst = hs.Index(3, 20, upload=False).multi_indices()
+    targets.append((hs.Index(3, rows=lst, upload=False), lambda k: np.prod(1 + k, axis=1) <= 20))
+    for tgt, member in targets:
+        kt = tgt.multi_indices().astype(np.int64)
+        m = sub.embed_map(tgt)
+        inside = member(ks)
+        assert np.array_equal(m >= 0, inside)
+        assert np.array_equal(kt[m[inside]], ks[inside])
 
 
 def test_error_split_argument_checks(hs):
@@ -395,9 +410,8 @@ def test_padded_index_errors(hs):
         with pytest.raises(hs.HSError):
             hs.hs_index_create_padded(*args, C.byref(h))
     sub = hs.Index(3, 10, upload=False)
-    tot = hs.Index(3, 5, upload=False, total_degree=True)
     with pytest.raises(hs.HSError):
-        sub.embed_map(tot)   # a total-degree target has no embedding
+        sub.embed_map(hs.Index(4, 10, upload=False))   # the sets differ in N
 
 
 def test_padded_count_saturates(hs):
