@@ -49,11 +49,11 @@ HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6
 FP32_VALU_PEAK_TFLOPS = 157.3
 METRIC = "Galerkin matvecs/s + HBM GB/s (% peak), batched/FP32 vs plain FP64 at 1e-10"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hh_long_N6_B4096_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hh_multi_N6_B4096_traffic.json")
 # sources whose change invalidates the recorded counter traffic of the H kernel
-KERNEL_SOURCES = ["paper_1403_3511_amd/csrc/matvec_long.h", "paper_1403_3511_amd/csrc/matvec_long_f64.hip",
-                  "paper_1403_3511_amd/csrc/dev_common.h", "paper_1403_3511_amd/csrc/hs_internal.h",
-                  "paper_1403_3511_amd/csrc/index.cpp"]
+KERNEL_SOURCES = ["paper_1403_3511_amd/csrc/matvec_multi.h", "paper_1403_3511_amd/csrc/matvec_multi_f64.hip",
+                  "paper_1403_3511_amd/csrc/matvec_long.h", "paper_1403_3511_amd/csrc/dev_common.h",
+                  "paper_1403_3511_amd/csrc/hs_internal.h", "paper_1403_3511_amd/csrc/index.cpp"]
 
 
 def kernel_source_hash() -> str:
@@ -162,7 +162,8 @@ def main():
     ap.add_argument("--batch-max-rows", type=int, default=1 << 23,
                     help="redraw batched instances with more rows than this (0: keep every draw)")
     ap.add_argument("--n10-steps", type=int, default=20, help="steps of the N=10 FP32/FP64 comparison")
-    ap.add_argument("--train-steps", type=int, default=3000, help="Adam steps of the learned form")
+    ap.add_argument("--train-steps", type=int, default=12000, help="Adam steps of the learned form")
+    ap.add_argument("--train-draws", type=int, default=16384, help="training draws of the learned form")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -213,7 +214,7 @@ def main():
     value = args.steps * M_KRYLOV / (ms_total / 1e3)
     norm_err = abs(float(torch.linalg.norm(c).item()) - 1.0)
 
-    # ---- dominant kernel: H application (one launch), back to back on this stream ----
+    # ---- dominant kernel: the H application, back to back on this stream ----
     x = torch.from_numpy(c0).to(dev)
     y = torch.empty_like(x)
     aws = hs.workspace(idx, pot, hs.HS_C128, 0)
@@ -225,11 +226,14 @@ def main():
     alg_bytes = 32.0 * idx.size
     achieved = alg_bytes / (us_matvec * 1e-6) / 1e9
     np_axes = N_DIM - idx.tile_dim
-    kernel = f"hs::k_hh_long<double, {N_DIM}, {np_axes}, false, false>" if pot.fused else "hs::k_pass<double>"
+    # the H application: the multi-tile work items of the long tiles, then the short-tile
+    # rows by the row kernel (two launches, timed together)
+    kernel = (f"hs::k_hh_multi<double, {N_DIM}, {np_axes}> + hs::k_hh_long<double, {N_DIM}, {np_axes}, false, false>"
+              if pot.fused else "hs::k_pass<double>")
     traffic = recorded_traffic(kernel)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": kernel, "us_per_launch": round(us_matvec, 2),
+                "traffic": traffic, "kernel": kernel, "us_per_h_application": round(us_matvec, 2),
                 "alg_bytes_per_launch": int(alg_bytes)}
     fpr = alg_flops_per_row(N_DIM, w_degrees(terms, N_DIM))
     tflops = fpr * idx.size / (us_matvec * 1e-6) / 1e12
@@ -256,6 +260,7 @@ def main():
         if "diag" in want:
             forms["diag"] = diag_form(hs, stream, args)
             forms["diag"]["galerkin_gap"] = galerkin_gap_form(hs, idx, pot, c0, stream)
+            forms["diag"]["galerkin_gap_per_config"] = galerkin_gaps_other(hs, stream)
         if "xop" in want:
             forms["xop"] = xop_form(hs, idx, c0, stream)
         if "small" in want:
@@ -600,6 +605,124 @@ def galerkin_gap_form(hs, idx, pot, c0, stream, w=3, reps=3):
             "rel_2norm": rel2, "rel_infnorm": relinf, "ms": round(ms, 3), "host_build_s": round(build_s, 2)}
 
 
+def _padded_gap(hs, idx, pot, v, w):
+    """Relative 2-norm and infinity-norm gap between the fast algorithm on idx and the exact
+    Galerkin product there, the latter from the fast algorithm on the cross widened by w
+    (the largest per-axis degree), restricted to idx (Sec. 5.1 E^red with the widened set
+    in place of the box)."""
+    import torch
+    t0 = time.time()
+    P = hs.Index(idx.N, idx.B, pad=w)
+    build_s = time.time() - t0
+    y = torch.empty_like(v)
+    hs.apply_h(idx, pot, v, y, ws=hs.workspace(idx, pot, hs.HS_C128, 0))
+    maps = (torch.from_numpy(idx.embed_map(P)).to("cuda"), None)
+    gap = torch.empty_like(v)
+    nb = ctypes.c_int64()
+    hs.hs_error_split_workspace_bytes(idx.h, P.h, None, pot.h, ctypes.byref(nb))
+    ws = hs.dev_buffer(nb.value)
+    t0 = time.perf_counter()
+    hs.error_split(idx, P, None, pot, v, e_red=gap, maps=maps, ws=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    out = {"widened_rows": P.size, "w": w, "rel_2norm": float(torch.linalg.norm(gap) / torch.linalg.norm(y)),
+           "rel_infnorm": float(gap.abs().max() / y.abs().max()), "ms": round(ms, 2),
+           "host_build_s": round(build_s, 2)}
+    del P, ws, gap, maps
+    torch.cuda.empty_cache()
+    return out
+
+
+def galerkin_gaps_other(hs, stream, nrows=12):
+    """The gap to the exact Galerkin product on the other single-instance workloads.
+      small (N=2, B=64) and learned (N=4, B=8192, total-degree-6 Hermite W): the widened
+      cross as for the main line (w = 3 and 6).
+      FP32 (N=10, B=4096): the widened cross would hold more than 10^10 rows, so the exact
+      product is taken on sampled rows j.  A term with degrees a reaches from j only
+      points of the box {m <= j + a}; the union L of these boxes over the terms and the
+      sampled rows is downward closed, so the fast algorithm on L applied to c restricted
+      to L (zero outside K) loses no path from j and is exact there.  Rows are drawn
+      uniformly from K."""
+    import numpy as np
+    import torch
+    from synth import (coherent_state, complex_normal_by_index, draw_surrogate_params, henon_heiles_chain,
+                       surrogate_geometry)
+    out = {}
+    # small workload
+    tt = henon_heiles_chain(2, 0.111)
+    idx = hs.Index(2, 64)
+    pot = hs.Pot(2, [(x[0], x[1], x[2], x[3], x.degrees) for x in tt], subtract_harmonic=True)
+    v = torch.from_numpy(complex_normal_by_index(idx.multi_indices(), 0)).to("cuda")
+    out["small_N2_B64"] = {"workload": "N=2 B=64 HH lambda=0.111, complex normal seed 0", **_padded_gap(hs, idx, pot, v, 3)}
+    # learned workload: Hermite coefficients of one parameter draw by quadrature (Q = 16)
+    N, D = 4, 6
+    geom = surrogate_geometry(N, 3, seed=7)
+    prow = torch.from_numpy(draw_surrogate_params(1, seed=12)).to("cuda")
+    coef = hs.gh_project(geom, prow, D, 16)
+    idx = hs.Index(N, 8192)
+    pot = hs.Pot(N, [(0.0, a) for a in hs.total_degree_multi_indices(N, D)], basis="herm")
+    pot.set_coeffs_device(coef[0])
+    c0 = coherent_state(idx.multi_indices(), np.array([0.5, 0.0, -0.3, 0.2]))
+    v = torch.from_numpy(c0 / np.linalg.norm(c0)).to("cuda")
+    out["learned_N4_B8192"] = {"workload": "N=4 B=8192 Gaussian wells, degree-6 Hermite W (Q=16), packet (0.5,0,-0.3,0.2)",
+                               **_padded_gap(hs, idx, pot, v, D)}
+    del idx, pot, v
+    # FP32 workload, sampled rows
+    N, B = 10, 4096
+    tt = henon_heiles_chain(N, 0.111, 0.05)
+    idx = hs.Index(N, B)
+    pot = hs.Pot(N, [(x[0], x[1], x[2], x[3], x.degrees) for x in tt], subtract_harmonic=True)
+    pot.set_time(0.0025)
+    k = idx.multi_indices()
+    c0 = np.concatenate([coherent_state(k[i:i + 8_000_000], 0.5) for i in range(0, len(k), 8_000_000)])
+    v = torch.from_numpy(c0 / np.linalg.norm(c0)).to("cuda")
+    y = torch.empty_like(v)
+    hs.apply_h(idx, pot, v, y)
+    rng = np.random.default_rng(3)
+    rows = np.sort(rng.choice(idx.size, nrows, replace=False))
+    degs = {tuple(x.degrees) for x in tt} | {tuple(2 if i == l else 0 for i in range(N)) for l in range(N)}
+    t0 = time.time()
+    keys = []
+    for j in k[rows].astype(np.int64):
+        for a in degs:
+            grids = np.meshgrid(*[np.arange(jl + al + 1) for jl, al in zip(j, a)], indexing="ij")
+            keys.append(np.stack([g.ravel() for g in grids], axis=1).astype(np.uint16))
+    Lk = np.unique(np.concatenate(keys), axis=0)
+    L = hs.Index(N, rows=Lk)
+    build_s = time.time() - t0
+    lmap = torch.from_numpy(L.embed_map(idx).astype(np.int64)).to("cuda")
+    vL = torch.zeros(L.size, dtype=torch.complex128, device="cuda")
+    inK = lmap >= 0
+    vL[inK] = v[lmap[inK]]
+    yL = torch.empty_like(vL)
+    hs.apply_h(L, pot, vL, yL, ws=hs.workspace(L, pot, hs.HS_C128, 0))
+    # the sampled rows' positions in L, by mixed-radix keys of the multi-indices
+    Lrows = L.multi_indices().astype(np.int64)
+    radix = Lrows.max(axis=0) + 1
+
+    def key(m):
+        kk = np.zeros(m.shape[0], dtype=np.int64)
+        for l in range(N):
+            kk = kk * radix[l] + m[:, l]
+        return kk
+    lkeys = key(Lrows)
+    order = np.argsort(lkeys)
+    at = np.searchsorted(lkeys[order], key(k[rows].astype(np.int64)))
+    posL = torch.from_numpy(order[at]).to("cuda")
+    assert np.array_equal(Lrows[order[at]], k[rows].astype(np.int64))
+    yk = y[torch.from_numpy(rows.astype(np.int64)).to("cuda")]
+    ye = yL[posL]
+    d = yk - ye
+    out["fp32_N10_B4096"] = {"workload": "N=10 B=4096 HH lambda=0.111 + laser at t=h/2, packet x_d=0.5; "
+                                         "%d rows drawn uniformly from K, exact rows from the fast algorithm on "
+                                         "the union of the terms' boxes (%d rows)" % (len(rows), L.size),
+                             "rows": int(len(rows)), "exact_set_rows": int(L.size),
+                             "rel_2norm_sampled": float(torch.linalg.norm(d) / torch.linalg.norm(ye)),
+                             "rel_infnorm_sampled": float(d.abs().max() / ye.abs().max()),
+                             "host_build_s": round(build_s, 2)}
+    return out
+
+
 def n10_big_form(hs, stream, args, reps=3):
     """Matvec-only throughput at N = 10, product bound 2^14 (1,064,429,409 rows), chained
     Henon-Heiles + laser, complex64 and complex128: vectors of 8.5 and 17 GB, beyond the
@@ -693,7 +816,7 @@ def fp32_n10_form(hs, stream, args):
 def learned_form(hs, stream, args):
     """Learned coefficients, N = 4: Gaussian wells on circles expanded in Hermite
     polynomials of total degree <= 6 (210 coefficients).  Targets from the Gauss-Hermite
-    projection (Q = 16) of 4096 parameter draws; the 7-256-256-210 network trained with
+    projection (Q = 16) of 16384 parameter draws; the 7-256-256-210 network trained with
     Adam (batch 256); accuracy against a Q = 24 quadrature reference on 256 held-out draws; coefficient
     latency of network, quadrature and Chebyshev interpolation (degree 6 on [-4, 4]^4,
     the Chebyshev-basis potential of the same degrees); one propagation step at product
@@ -708,7 +831,8 @@ def learned_form(hs, stream, args):
     geom = surrogate_geometry(N, G, seed=7)
     lo, hi = surrogate_param_box()
     dev = "cuda"
-    P = torch.from_numpy(draw_surrogate_params(4096, seed=11)).to(dev)
+    ndraw = args.train_draws
+    P = torch.from_numpy(draw_surrogate_params(ndraw, seed=11)).to(dev)
     T = hs.gh_project(geom, P, D, Q)
     Tn = T.cpu().numpy()
     mean, sd = Tn.mean(axis=0), Tn.std(axis=0) + 1e-3 * np.abs(Tn).max()
@@ -718,7 +842,7 @@ def learned_form(hs, stream, args):
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
     gen = torch.Generator(device=dev).manual_seed(0)
     bs = 256
-    sels = torch.randint(0, 4096, (args.train_steps, bs), generator=gen, device=dev)
+    sels = torch.randint(0, ndraw, (args.train_steps, bs), generator=gen, device=dev)
     Xb = P[sels]  # all batches gathered before timing
     Yb = T[sels]
     torch.cuda.synchronize()
@@ -736,7 +860,8 @@ def learned_form(hs, stream, args):
     scale = np.linalg.norm(J, axis=1)
     err_net = float(np.median(np.linalg.norm(net.predict(Pv).cpu().numpy() - J, axis=1) / scale))
     err_q = {q: float(np.median(np.linalg.norm(hs.gh_project(geom, Pv, D, q).cpu().numpy() - J, axis=1) / scale))
-             for q in (4, 5, 6, 8, 16)}
+             for q in (2, 3, 4, 5, 6, 8, 16)}
+    # the cheapest quadrature at least as accurate as the network
     q_match = min([q for q in err_q if err_q[q] <= err_net] or [16])
 
     def lat_us(fn, reps=50):
@@ -798,12 +923,14 @@ def learned_form(hs, stream, args):
     hs.apply_h(idx, pot, x, yn, hs.HS_C128, aws)
     hc_diff = float(torch.linalg.norm(yn - yq) / torch.linalg.norm(yq))
     return {"workload": "N=4, 3 Gaussian wells on circles, total degree 6 (210 Hermite coefficients); targets "
-                        "Gauss-Hermite Q=16 on 4096 draws; network 7-256-256-210 BF16 MFMA; step at product "
-                        "bound 8192 (%d rows), h=0.002, m=10" % idx.size,
+                        "Gauss-Hermite Q=16 on %d draws; network 7-256-256-210 BF16 MFMA; step at product "
+                        "bound 8192 (%d rows), h=0.002, m=10" % (ndraw, idx.size),
             "train_steps": args.train_steps, "train_samples_per_s": round(args.train_steps * bs / train_s, 1),
             "train_tflops": round(args.train_steps * step_flops / train_s / 1e12, 3),
             "final_loss": float(loss.item()),
             "median_rel_err_network": err_net, "median_rel_err_quadrature": err_q, "quad_q_matched": q_match,
+            "gain_vs_matched_quadrature_b1": round(lat["quad_matched_b1"] / lat["network_b1"], 3),
+            "gain_vs_matched_quadrature_b256": round(lat["quad_matched_b256"] / lat["network_b256"], 3),
             "latency_us": {k: round(v, 2) for k, v in lat.items()},
             "step_ms_with_network": round(res["network"][0], 3),
             "step_ms_with_quadrature": round(res["quadrature"][0], 3),
@@ -812,18 +939,25 @@ def learned_form(hs, stream, args):
 
 
 def batched_form(hs, stream, args, nsteps=3):
+    """The batched workload's draw (below), and a draw of many small instances
+    (log2 B <= 10) beside it."""
+    out = batched_draw(hs, stream, args, args.batch_log2_bmax, args.batch_max_rows, nsteps)
+    out["small_draw"] = batched_draw(hs, stream, args, 10.0, 0, nsteps)
+    return out
+
+
+def batched_draw(hs, stream, args, log2_bmax, cap, nsteps=3):
     """256 instances (N uniform in 3..8, B = floor(2^U(8, log2_bmax)), lambda in
-    [0.05, 0.15], laser-free chained Henon-Heiles; an instance with more than max_rows
-    rows is drawn again), complex normal start vectors: one batched application of H
-    (persistent launch) and the batched step (graph replay), against the instances
-    stepped one by one with the single-instance path."""
+    [0.05, 0.15], laser-free chained Henon-Heiles; an instance with more than cap rows is
+    drawn again), complex normal start vectors: one batched application of H (the
+    per-class persistent kernels, launches autotuned) and the batched step (graph
+    replay), against the instances stepped one by one with the single-instance path."""
     import numpy as np
     import torch
     from synth import batch_instances, henon_heiles_chain
 
-    cap = args.batch_max_rows
     accept = (lambda N, B: hs.index_count(N, B) <= cap) if cap > 0 else None
-    draws = batch_instances(256, seed=0, log2_bmax=args.batch_log2_bmax, accept=accept)
+    draws = batch_instances(256, seed=0, log2_bmax=log2_bmax, accept=accept)
     t0 = time.time()
     idxs, pots = [], []
     for d in draws:
@@ -843,7 +977,10 @@ def batched_form(hs, stream, args, nsteps=3):
     # batched
     c = c_init.clone()
     y = torch.empty_like(c)
+    t0 = time.time()
     b.autotune(c, y)
+    tune_s = time.time() - t0
+    order, tuning = b.tuning()
     # one batched application of H over all instances
     b.apply_h(c, y)
     ms_apply = event_time_ms(lambda: b.apply_h(c, y), 10, stream) / 10
@@ -887,7 +1024,7 @@ def batched_form(hs, stream, args, nsteps=3):
     inst_mv = len(draws) * M_KRYLOV * nsteps
     apply_gbs = 2 * 16 * rows / (ms_apply / 1e3) / 1e9
     return {"workload": "256 instances, N in 3..8, B=floor(2^U(8,%g))%s, %d rows in total, %d steps"
-                        % (args.batch_log2_bmax,
+                        % (log2_bmax,
                            ", instances over %d rows drawn again" % cap if cap > 0 else "", rows, nsteps),
             "apply_ms": round(ms_apply, 4), "apply_row_matvec_per_s": float("%.4g" % (rows / (ms_apply / 1e3))),
             "apply_algorithmic_gbs": round(apply_gbs, 1), "apply_hbm_frac": round(apply_gbs / HBM_PEAK_GBS, 4),
@@ -896,34 +1033,79 @@ def batched_form(hs, stream, args, nsteps=3):
             "one_by_one_instance_matvec_per_s": round(inst_mv / (ms_s / 1e3), 1),
             "speedup_vs_one_by_one": round(ms_s / ms_b, 3),
             "max_rel_dev_vs_one_by_one": dev_max, "launch": list(b.get_launch()),
+            "tuning": {"order": ["largest first", "interleaved"][order],
+                       "per_class": [dict(zip(("N", "prefix_axes", "kernel", "items", "wg", "per_cu", "grab"),
+                                              (r[0], r[1], ["rows", "multi-tile"][r[2]], r[3], r[4], r[5], r[6])))
+                                     for r in tuning],
+                       "autotune_s": round(tune_s, 2)},
             "host_build_s": round(build_s, 2)}
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_threads():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(np):
-    """The CPU oracle's fast algorithm (NumPy, float64) on the same workload: a bounded
-    sample of 3 applications of H on the full set, reported as matvec/s."""
+    """The CPU oracle's fast algorithm on the same workload (N = 6, B = 4096, the same
+    potential at t = 0.1 and the packet at x_d = 2), timed on this host.  The compiled
+    oracle (oracle/fast_cpu.c: plain C, OpenMP loops over rows) runs 3 applications on all
+    host threads and 2 on one thread; the NumPy oracle's 1 application is given beside them.
+    value = the all-threads rate, the oracle as it stands."""
+    from oracle import fast_cpu
     from oracle.index import IndexSet
     from oracle.operators import Potential, fast_apply_H, subtract_harmonic
     from synth import coherent_state, henon_heiles_chain
 
-    t0 = time.time()
-    ix = IndexSet(N_DIM, B_BOUND)
-    build_s = time.time() - t0
     terms = henon_heiles_chain(N_DIM, 0.111, 0.05)
     W = subtract_harmonic(Potential(N_DIM, "mono", 1.0, [(x.coef(0.1), x.degrees) for x in terms]))
+    t0 = time.time()
+    S = fast_cpu.FastSet(N_DIM, B_BOUND)
+    build_s = time.time() - t0
+    v0 = coherent_state(S.multi_indices(), 2.0)
+    v0 /= np.linalg.norm(v0)
+    nthr = _host_threads()
+
+    def rate(threads, reps):
+        v = v0.copy()
+        S.apply_H(W, v, threads)  # warm-up
+        t = time.perf_counter()
+        for _ in range(reps):
+            v = S.apply_H(W, v, threads)
+            v /= np.linalg.norm(v)
+        return reps / (time.perf_counter() - t)
+
+    r_all = rate(nthr, 3)
+    r_one = rate(1, 2)
+    del S
+    # the NumPy oracle, one application, one thread
+    ix = IndexSet(N_DIM, B_BOUND)
     v = coherent_state(ix.k, 2.0)
     v /= np.linalg.norm(v)
-    reps = 3
     from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):  # element-wise NumPy code; any BLAS call on one thread
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            v = fast_apply_H(ix, W, v)
-            v /= np.linalg.norm(v)
-        dt = time.perf_counter() - t0
-    return {"value": round(reps / dt, 4), "unit": "matvec/s", "cores": 1, "kind": "oracle",
-            "sample": "3 applications of H by the NumPy oracle fast algorithm on the full "
-                      "N=6 B=4096 set (index build %.1f s not counted), one thread" % build_s}
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        fast_apply_H(ix, W, v)
+        r_np = 1.0 / (time.perf_counter() - t)
+    return {"value": round(r_all, 4), "unit": "matvec/s", "cores": nthr, "kind": "oracle",
+            "sample": "3 applications of H (after one warm-up) by the compiled oracle fast algorithm "
+                      "(C, OpenMP loops over rows) on the full N=6 B=4096 set on %d host threads; "
+                      "index build %.1f s not counted" % (nthr, build_s),
+            "value_1_thread": round(r_one, 4), "numpy_oracle_1_thread": round(r_np, 4),
+            "cpu_model": _cpu_model(), "host_threads": nthr}
 
 
 if __name__ == "__main__":
