@@ -50,6 +50,7 @@ extern "C" {
 #define HS_E_UNSUPPORTED -5   /* combination not implemented (e.g. basis/kernel class)  */
 #define HS_E_HIP -6           /* a HIP runtime call failed; text in hs_last_error        */
 #define HS_E_NONFINITE -7     /* non-finite coefficients                                */
+#define HS_E_IO -8            /* a checkpoint file cannot be read or written, or is corrupt */
 
 /* ---- dtypes, bases ------------------------------------------------------------ */
 #define HS_C128 0 /* complex float64 */
@@ -408,6 +409,33 @@ int32_t hs_sur_coeffs(hs_mlp mlp, void *dev, int32_t N, int32_t G, int32_t D, in
 int32_t hs_mlp_train_step(hs_mlp mlp, void *dev, int32_t batch, const double *x_dev,
                           const double *target_dev, float lr, float *loss_dev,
                           float *grads_dev, void *stream);
+
+/* ---- checkpoint and resume (an addition: the state of Fig. 4's time_propagation) ----
+ * The state of a propagation is (c^n, t_n, n) plus the configuration that produced it.
+ * hs_checkpoint_save writes bytes bytes of src (the coefficient vector, any dtype) and a
+ * caller-written header text (JSON by convention: t_n, n, the index set, the potential,
+ * seeds) to path.  The file is
+ *   "HSCKPT01" | u64 header bytes | header | u64 data bytes | u64 FNV-1a 64 of the data | data
+ * (little-endian), written to path + ".tmp" and renamed over path, so an interrupted save
+ * leaves the previous file intact.  src is device memory when src_on_device != 0 (the
+ * call waits for the work already enqueued on stream, then copies through a 64 MiB
+ * pinned buffer: it synchronises the stream), host memory otherwise.
+ * hs_checkpoint_info (host only) checks a file's framing and returns its header
+ * (NUL-terminated, truncated to cap - 1 bytes; header_out may be NULL), the header's full
+ * length and the data size.
+ * hs_checkpoint_load reads the data into dst (device when dst_on_device != 0, after the
+ * work already enqueued on stream; synchronises the stream) after verifying the checksum
+ * over the whole file, so a corrupt file leaves dst untouched.
+ * Errors: HS_E_INVALID for NULL arguments, a negative size, or a destination size that
+ * differs from the file's; HS_E_IO for files that cannot be opened, written or renamed,
+ * that are not checkpoint files, are truncated, or fail the checksum; HS_E_HIP for a
+ * failed copy.  Resuming from a checkpoint reproduces the uninterrupted run bit for bit
+ * (the step is deterministic).                                                          */
+int32_t hs_checkpoint_save(const char *path, const char *header_json, const void *src, int64_t bytes,
+                           int32_t src_on_device, void *stream);
+int32_t hs_checkpoint_info(const char *path, char *header_out, int64_t cap, int64_t *header_len,
+                           int64_t *data_bytes);
+int32_t hs_checkpoint_load(const char *path, void *dst, int64_t bytes, int32_t dst_on_device, void *stream);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libhs.so")
 SOURCES = ["api.cpp", "index.cpp", "potential.cpp", "matvec.hip", "matvec_long_f64.hip",
            "matvec_long_f32.hip", "matvec_multi_f64.hip", "matvec_multi_f32.hip", "matvec_m4_f64.hip", "matvec_m4_f32.hip", "matvec_sym_f64.hip",
            "matvec_sym_f32.hip", "lanczos.hip", "step_small_f64.hip", "step_small_f32.hip",
-           "batch.hip", "surrogate.hip", "diag.hip", "step_static.hip"]
+           "batch.hip", "surrogate.hip", "diag.hip", "step_static.hip", "checkpoint.cpp"]
 CFLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-fno-gpu-rdc", "-Wall", "-Wno-unused-function"]

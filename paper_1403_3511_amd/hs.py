@@ -20,6 +20,13 @@ LIB_PATH = os.environ.get("HS_LIBRARY") or os.path.join(_HERE, "libhs.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} not built: run __graft_entry__.build() or "
                       "python -m paper_1403_3511_amd.build")
+# PyTorch ships its own HIP runtime under the same soname as the system's.  Loading torch
+# first makes libhs.so bind to that one copy; loaded the other way round the process would
+# hold two runtimes, and the one the library calls would find no device.
+try:
+    import torch as _torch_first  # noqa: F401
+except ImportError:  # host-only use of the library (index sets, checkpoint files)
+    _torch_first = None
 _lib = C.CDLL(LIB_PATH)
 
 HS_OK, HS_INFO_BREAKDOWN = 0, 1
@@ -95,6 +102,9 @@ _SIGS = {
     "hs_mlp_predict": [_vp, _vp, _i32, _vp, _vp, _vp],
     "hs_mlp_train_step": [_vp, _vp, _i32, _vp, _vp, _f32, _vp, _vp, _vp],
     "hs_sur_coeffs": [_vp, _vp, _i32, _i32, _i32, _i32, _pf64, _i32, _vp, _vp, _vp, _vp],
+    "hs_checkpoint_save": [C.c_char_p, C.c_char_p, _vp, _i64, _i32, _vp],
+    "hs_checkpoint_info": [C.c_char_p, C.c_char_p, _i64, _pi64, _pi64],
+    "hs_checkpoint_load": [C.c_char_p, _vp, _i64, _i32, _vp],
 }
 
 EXPORTED = sorted(list(_SIGS) + ["hs_version"])
@@ -272,14 +282,21 @@ class Index:
         total_degree=True the set |k|_1 <= B; with rows (n x N integers) that explicit
         downward-closed set; with pad=w the padded cross prod(1 + max(k_l - w, 0)) <= B."""
         h = _vp()
+        self.pad, self.rows_sha256 = pad, None
         if pad is not None:
             hs_index_create_padded(N, B, int(pad), tile_dim, C.byref(h))
+            self.kind = "padded"
         elif rows is not None:
             k = np.ascontiguousarray(np.asarray(rows, dtype=np.uint16).reshape(-1, N))
             hs_index_create_from_list(N, k.shape[0], k.ctypes.data_as(_pu16), C.byref(h))
+            self.kind = "list"
+            import hashlib
+            self.rows_sha256 = hashlib.sha256(np.ascontiguousarray(np.sort(k.view(
+                np.dtype((np.void, 2 * N))).ravel())).tobytes()).hexdigest()
         else:
             make = hs_index_create_box if box else (hs_index_create_total_degree if total_degree else hs_index_create)
             make(N, B, tile_dim, C.byref(h))
+            self.kind = "box" if box else ("total_degree" if total_degree else "hyperbolic")
         self.h, self.N, self.B, self.box = h, N, B, box
         n = C.c_int64()
         hs_index_size(h, C.byref(n))
@@ -293,6 +310,16 @@ class Index:
             hs_index_device_bytes(h, C.byref(nb))
             self.dev = dev_buffer(nb.value, device)
             hs_index_upload(h, ptr(self.dev), nb.value, stream_ptr())
+
+    def describe(self) -> dict:
+        """What identifies the set and its row order (the checkpoint header's "set")."""
+        d = {"kind": self.kind, "N": self.N, "B": self.B, "tile_dim": self.tile_dim, "rows": self.size,
+             "tiles": self.ntiles, "suffixes": self.nsuffix}
+        if self.pad is not None:
+            d["pad"] = int(self.pad)
+        if self.rows_sha256 is not None:
+            d["rows_sha256"] = self.rows_sha256
+        return d
 
     def multi_indices(self) -> np.ndarray:
         out = np.empty((self.size, self.N), dtype=np.uint16)
@@ -456,6 +483,63 @@ def propagate(idx: Index, pot: Pot, c, t0: float, h: float, m: int, nsteps: int,
     hs_propagate(idx.h, ptr(idx.dev), pot.h, ptr(pot.dev), dtype, float(t0), ptr(t_dev), float(h), int(m),
                  1 if reorth else 0, int(nsteps), ptr(c), ptr(ws), stream_ptr())
     return c
+
+
+# ---- checkpoint and resume of (c^n, t_n, n) -------------------------------------------
+
+CHECKPOINT_FORMAT = "hs-checkpoint"
+
+
+def checkpoint_save(path: str, idx: Index, c, t: float, n: int, config=None, seeds=None):
+    """Write the state (c, t, n) of a propagation on idx to path (hs_checkpoint_save).
+
+    c is a contiguous complex128 or complex64 tensor on the GPU or the CPU with one entry
+    per row of idx, in library row order.  t is stored exactly (as a hexadecimal float);
+    config and seeds are JSON-serialisable descriptions kept in the header."""
+    import json
+    torch = _torch()
+    if c.dtype not in (torch.complex128, torch.complex64) or c.numel() != idx.size or not c.is_contiguous():
+        _fail(f"checkpoint_save: c must be a contiguous complex tensor of {idx.size} entries")
+    header = {"format": CHECKPOINT_FORMAT, "version": 1, "set": idx.describe(),
+              "dtype": "complex128" if c.dtype == torch.complex128 else "complex64",
+              "t": float(t), "t_hex": float(t).hex(), "n": int(n),
+              "config": config if config is not None else {}, "seeds": seeds if seeds is not None else {}}
+    on_dev = bool(c.is_cuda)
+    hs_checkpoint_save(os.fsencode(path), json.dumps(header, sort_keys=True).encode(), ptr(c),
+                       c.numel() * c.element_size(), 1 if on_dev else 0, stream_ptr() if on_dev else None)
+
+
+def checkpoint_info(path: str) -> dict:
+    """The header of a checkpoint file, after checking its framing (hs_checkpoint_info)."""
+    import json
+    hl, dl = C.c_int64(), C.c_int64()
+    hs_checkpoint_info(os.fsencode(path), None, 0, C.byref(hl), C.byref(dl))
+    buf = C.create_string_buffer(hl.value + 1)
+    hs_checkpoint_info(os.fsencode(path), buf, hl.value + 1, C.byref(hl), C.byref(dl))
+    header = json.loads(buf.raw[:hl.value].decode())
+    if header.get("format") != CHECKPOINT_FORMAT:
+        _fail(f"checkpoint_info: {path} is not an {CHECKPOINT_FORMAT} file")
+    header["data_bytes"] = dl.value
+    return header
+
+
+def checkpoint_load(path: str, idx: Index, device="cuda", out=None):
+    """Read a checkpoint written for idx: returns (c, t, n, header).  The header's index
+    set must be idx's (kind, sizes, bound, tile dimension), else HSError."""
+    torch = _torch()
+    header = checkpoint_info(path)
+    want = idx.describe()
+    if header.get("set") != want:
+        _fail(f"checkpoint_load: {path} was written for the set {header.get('set')}, not {want}")
+    tdtype = torch.complex128 if header["dtype"] == "complex128" else torch.complex64
+    if out is None:
+        out = torch.empty(idx.size, dtype=tdtype, device=device)
+    elif out.dtype != tdtype or out.numel() != idx.size or not out.is_contiguous():
+        _fail(f"checkpoint_load: out must be a contiguous {header['dtype']} tensor of {idx.size} entries")
+    on_dev = bool(out.is_cuda)
+    hs_checkpoint_load(os.fsencode(path), ptr(out), out.numel() * out.element_size(), 1 if on_dev else 0,
+                       stream_ptr() if on_dev else None)
+    return out, float.fromhex(header["t_hex"]), int(header["n"]), header
 
 
 def workspace_magnus4(idx: Index, pot: Pot, dtype: int, m: int, device="cuda"):

@@ -1,5 +1,5 @@
 """The host C++ of the library (index-set construction, potential compilation, argument
-checks) under AddressSanitizer and UndefinedBehaviorSanitizer: a build with the host code
+checks, checkpoint files) under AddressSanitizer and UndefinedBehaviorSanitizer: a build with the host code
 instrumented (device code unchanged) runs the host-only test files in a subprocess with
 the ASan runtime preloaded; any report fails it.  No GPU is touched.  Set
 HS_SANITIZED_LIB to reuse an existing sanitized build instead of compiling one (about
@@ -36,8 +36,10 @@ def test_host_code_under_asan_and_ubsan():
                    ASAN_OPTIONS="detect_leaks=0:halt_on_error=1",
                    UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
         res = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                              "-m", "not gpu",
                               os.path.join(ROOT, "tests", "test_lib_host.py"),
-                              os.path.join(ROOT, "tests", "test_binding_checks.py")],
+                              os.path.join(ROOT, "tests", "test_binding_checks.py"),
+                              os.path.join(ROOT, "tests", "test_checkpoint.py")],
                              cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
         out = res.stdout + res.stderr
         assert res.returncode == 0, out[-4000:]
