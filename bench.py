@@ -917,7 +917,17 @@ def learned_form(hs, stream, args):
     aws = hs.workspace(idx, pot, hs.HS_C128, 0)
     hs.gh_project(geom, prow, D, Q, out=coef)
     pot.set_coeffs_device(coef[0])
-    mv_ms = event_time_ms(lambda: hs.apply_h(idx, pot, x, yq, hs.HS_C128, aws), 3, stream) / 3
+    mv_ms = event_time_ms(lambda: hs.apply_h(idx, pot, x, yq, hs.HS_C128, aws), 20, stream) / 20
+    # the H application's roofline: the pass program (whole-vector recurrence and Clenshaw
+    # passes plus one per-row combination) against the FP64 vector peak, by the
+    # shared-prefix flop count of the 210-term potential
+    fpr = alg_flops_per_row(N, [tuple(int(v) for v in a) for a in degs])
+    tflops = fpr * idx.size / (mv_ms * 1e-3) / 1e12
+    gbs = 32.0 * idx.size / (mv_ms * 1e-3) / 1e9
+    roof = {"bound": "alu", "kernel": "generic pass program (k_pass, k_combine, k_diag, k_accum, k_epilogue)",
+            "alg_flops_per_row": fpr, "achieved": round(tflops, 3), "peak": FP64_VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tflops / FP64_VALU_PEAK_TFLOPS, 4),
+            "alg_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     net.predict(prow, out=coef)
     pot.set_coeffs_device(coef[0])
     hs.apply_h(idx, pot, x, yn, hs.HS_C128, aws)
@@ -935,7 +945,8 @@ def learned_form(hs, stream, args):
             "step_ms_with_network": round(res["network"][0], 3),
             "step_ms_with_quadrature": round(res["quadrature"][0], 3),
             "step_ms_with_chebyshev": round(res["chebyshev"][0], 3),
-            "h_apply_ms": round(mv_ms, 3), "hc_rel_diff_network_vs_quadrature": hc_diff}
+            "h_apply_ms": round(mv_ms, 3), "h_apply_roofline": roof,
+            "hc_rel_diff_network_vs_quadrature": hc_diff}
 
 
 def batched_form(hs, stream, args, nsteps=3):

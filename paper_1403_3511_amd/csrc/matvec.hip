@@ -475,6 +475,42 @@ k_combine(int64_t n, CombSlots cs, const typename V2<T>::t *__restrict__ x, type
   }
 }
 
+// The same combination for at most kCombRegs inputs, as a dense product: every thread
+// loads its row of all inputs into registers at once (the loads overlap), and the block
+// first gathers the table into a dense coefficient matrix M[o][i] = sum of beta over the
+// entries (o, i) in LDS, read back with one address across the wave.
+constexpr int kCombRegs = 32;
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_combine_dense(int64_t n, CombSlots cs, const typename V2<T>::t *__restrict__ x, typename V2<T>::t *__restrict__ y,
+                typename V2<T>::t *__restrict__ ws, int64_t stride, const int32_t *__restrict__ ctab,
+                const double *__restrict__ beta) {
+  using C = typename V2<T>::t;
+  __shared__ double M[kMaxComb * kCombRegs];
+  for (int k = threadIdx.x; k < cs.nout * kCombRegs; k += blockDim.x) M[k] = 0.0;
+  __syncthreads();
+  const int32_t *cptr = ctab, *cidx = ctab + cs.nout + 1, *cterm = cidx + ctab[cs.nout];
+  for (int o = threadIdx.x; o < cs.nout; o += blockDim.x)
+    for (int e = cptr[o]; e < cptr[o + 1]; ++e) M[o * kCombRegs + cidx[e]] += beta[cterm[e]];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  auto slot = [&](int k) -> C * {
+    if (k == 0) return const_cast<C *>(x);
+    if (k == 1) return y;
+    return ws + (int64_t)(k - 2) * stride;
+  };
+  C in[kCombRegs];
+#pragma unroll
+  for (int i = 0; i < kCombRegs; ++i) in[i] = i < cs.nin ? slot(cs.in[i])[r] : vz<T>();
+  for (int o = 0; o < cs.nout; ++o) {
+    C acc = vz<T>();
+#pragma unroll
+    for (int i = 0; i < kCombRegs; ++i) fma_rc<T>(acc, (T)M[o * kCombRegs + i], in[i]);
+    slot(cs.out[o])[r] = acc;
+  }
+}
+
 // y = out_scale * y - prev_coef * prev_scale * prev (epilogue of the generic program)
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -597,9 +633,15 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
       cs.nout = (int32_t)p->cout_slot.size();
       for (int i = 0; i < cs.nin; ++i) cs.in[i] = p->cin_slot[i];
       for (int i = 0; i < cs.nout; ++i) cs.out[i] = p->cout_slot[i];
-      const size_t lds = sizeof(C) * 64 * (size_t)std::max(cs.nin, 1);
-      hipLaunchKernelGGL(k_combine<T>, dim3(nblk(idx->size, 64)), dim3(64), lds, s, idx->size, cs, (const C *)x,
-                         (C *)y, (C *)ws, stride / (int64_t)sizeof(C), (const int32_t *)(pb + p->off_comb), beta);
+      if (cs.nin <= kCombRegs) {
+        hipLaunchKernelGGL(k_combine_dense<T>, dim3(g), dim3(256), 0, s, idx->size, cs, (const C *)x, (C *)y,
+                           (C *)ws, stride / (int64_t)sizeof(C), (const int32_t *)(pb + p->off_comb), beta);
+      } else {
+        const size_t lds = sizeof(C) * 64 * (size_t)std::max(cs.nin, 1);
+        hipLaunchKernelGGL(k_combine<T>, dim3(nblk(idx->size, 64)), dim3(64), lds, s, idx->size, cs,
+                           (const C *)x, (C *)y, (C *)ws, stride / (int64_t)sizeof(C),
+                           (const int32_t *)(pb + p->off_comb), beta);
+      }
     }
   }
   if (out_scale || prev)
