@@ -23,7 +23,8 @@ Also measured inside this run:
                    same instances stepped one by one, the N = 10 FP32 form, the learned
                    coefficient path, the fourth-order two-stage Magnus step, the
                    symmetrised operator, the local error diagnostics of Fig. 9 and the
-                   main workload's gap to the exact Galerkin product, the direct
+                   main workload's gap to the exact Galerkin product, the perturbed
+                   Lanczos process of Sec. 6.2 (Figs. 11 and 12), the direct
                    operation alone, the small workload (N = 2, B = 64) with the
                    one-workgroup step, and the other index-set kinds.
   cpu_baseline  -- the CPU oracle's fast algorithm on the same workload (rank 0 only).
@@ -156,7 +157,7 @@ def main():
     ap.add_argument("--tile-dim", type=int, default=0)
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--forms", type=int, default=1, help="also measure the FP32 and batched forms")
-    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4,sym,diag,xop,small,sets,n10_big",
+    ap.add_argument("--form-names", default="fp32,batched,fp32_n10,learned,magnus4,sym,diag,perturbed,xop,small,sets,n10_big",
                     help="comma-separated forms measured when --forms is set")
     ap.add_argument("--batch-log2-bmax", type=float, default=14.0)
     ap.add_argument("--batch-max-rows", type=int, default=1 << 23,
@@ -261,6 +262,8 @@ def main():
             forms["diag"] = diag_form(hs, stream, args)
             forms["diag"]["galerkin_gap"] = galerkin_gap_form(hs, idx, pot, c0, stream)
             forms["diag"]["galerkin_gap_per_config"] = galerkin_gaps_other(hs, stream)
+        if "perturbed" in want:
+            forms["perturbed"] = perturbed_form(hs, stream)
         if "xop" in want:
             forms["xop"] = xop_form(hs, idx, c0, stream)
         if "small" in want:
@@ -576,6 +579,82 @@ def diag_form(hs, stream, args, reps=5):
         del sub, box, pad, vt, eq, er, maps, ws
     return {"workload": "Fig. 9, N = 4 column: torsional potential (L = 16, Chebyshev degree 8), beta = 5",
             "cases": out, "paper_seconds_at_K75": FIG9_N4_PAPER_SECONDS}
+
+
+# Sec. 6.2 as printed: Fig. 11 (perturbation error, m = 5) by (N, K) and h, and Fig. 12
+# (h = 1/10; unperturbed Lanczos error and perturbation error) by (N, m) and K
+FIG11 = {(2, 10): (3.731e-06, 1.874e-06, 9.380e-07, 4.691e-07), (2, 20): (6.565e-07, 3.285e-07, 1.644e-07, 8.222e-08),
+         (2, 30): (2.650e-07, 1.305e-07, 6.526e-08, 3.264e-08), (2, 40): (1.464e-07, 6.956e-08, 3.468e-08, 1.734e-08),
+         (3, 40): (6.310e-07, 3.151e-07, 1.576e-07, 7.880e-08), (4, 40): (5.313e-06, 2.661e-06, 1.331e-06, 6.658e-07)}
+FIG12 = {(2, 3): ((8.196e-05, 1.077e-04, 1.270e-04, 1.427e-04), (3.878e-06, 8.279e-07, 4.181e-07, 2.779e-07)),
+         (2, 5): ((2.324e-07, 1.709e-06, 4.415e-06, 7.881e-06), (3.731e-06, 6.565e-07, 2.650e-07, 1.464e-07)),
+         (2, 7): ((2.522e-10, 9.192e-09, 5.211e-08, 2.003e-07), (3.730e-06, 6.533e-07, 2.588e-07, 1.374e-07)),
+         (2, 9): ((1.179e-13, 2.973e-11, 5.241e-10, 3.354e-09), (3.730e-06, 6.533e-07, 2.587e-07, 1.371e-07)),
+         (3, 5): ((2.796e-07, 1.612e-06, 4.062e-06, 8.531e-06), (1.363e-04, 5.035e-06, 1.405e-06, 6.310e-07)),
+         (4, 5): ((2.628e-07, 1.666e-06, 3.966e-06, 7.500e-06), (1.493e-04, 1.437e-04, 2.103e-05, 5.313e-06))}
+
+
+def perturbed_form(hs, stream):
+    """The perturbed Lanczos process of Sec. 6.2 on the GPU: from v_k = prod max(k_l, 1)^-3
+    (normalised) on K = {prod(1 + k_l) <= K + 1}, one Lanczos exponential (no
+    re-orthogonalisation) with the fast algorithm against the same with the exact Galerkin
+    operator (the fast algorithm on the box {0..K + 4}^N restricted to K), and the exact
+    operator's Lanczos error against its own m = 32 exponential.  Torsional potential
+    (L = 16, degree-8 Chebyshev series) with and without the -|x|^2/2 term of the paper's
+    equation; the printed tables alongside (A38: they are not reproduced)."""
+    import numpy as np
+    import torch
+    from synth import decay_vector, torsional_series
+
+    def pot_terms(N, harmonic):
+        terms = torsional_series(N)
+        if harmonic:  # -x^2/2 = -64 (T_0 + T_2)(x / 16)
+            terms = [(terms[0][0] - 64.0 * N, terms[0][1])] + terms[1:]
+            for l in range(N):
+                a = [0] * N
+                a[l] = 2
+                terms.append((-64.0, tuple(a)))
+        return terms
+
+    hs_ = (0.1, 0.05, 0.025, 0.0125)
+    t_all = time.perf_counter()
+    out = {"workload": "Sec. 6.2: torsional potential L = 16, degree 8, beta = 3; m = 5 "
+           "unless stated; errors in the 2-norm", "paper_fig11": {f"N{N}_K{K}": v for (N, K), v in FIG11.items()},
+           "paper_fig12_h0.1": {f"N{N}_m{m}": {"unperturbed": v[0], "perturbed": v[1]} for (N, m), v in FIG12.items()}}
+    for harmonic in (True, False):
+        pots = {N: hs.Pot(N, pot_terms(N, harmonic), basis="cheb", scale=16.0) for N in (2, 3, 4)}
+        fig11, fig12 = {}, {}
+        for N, K in sorted({(2, 10), (2, 20), (2, 30), (2, 40), (3, 10), (3, 20), (3, 30), (3, 40),
+                            (4, 10), (4, 20), (4, 30), (4, 40)}):
+            pot = pots[N]
+            sub = hs.Index(N, K + 1)
+            op = hs.ExactOperator(sub, hs.Index(N, K + 4, box=True))
+            v = decay_vector(sub.multi_indices(), 3.0)
+            v /= np.linalg.norm(v)
+            v0 = torch.from_numpy(v).to("cuda")
+
+            def fast(h, m):
+                c = v0.clone()
+                hs.step(sub, pot, c, 0.0, h, m, reorth=False)
+                return c
+
+            def exact(h, m):
+                c = v0.clone()
+                op.step(pot, c, 0.0, h, m, reorth=False)
+                return c
+            if (N, K) in FIG11:
+                fig11[f"N{N}_K{K}"] = [float(torch.linalg.norm(fast(h, 5) - exact(h, 5))) for h in hs_]
+            ref = exact(0.1, 32)
+            for m in ((3, 5, 7, 9) if N == 2 else (5,)):
+                e_ex = exact(0.1, m)
+                row = fig12.setdefault(f"N{N}_m{m}", {"unperturbed": [], "perturbed": []})
+                row["unperturbed"].append(float(torch.linalg.norm(e_ex - ref)))
+                row["perturbed"].append(float(torch.linalg.norm(fast(0.1, m) - e_ex)))
+            del sub, op, v0
+        out["with_harmonic_term" if harmonic else "without_harmonic_term"] = {"fig11": fig11, "fig12_h0.1": fig12}
+    torch.cuda.synchronize()
+    out["seconds"] = round(time.perf_counter() - t_all, 2)
+    return out
 
 
 def galerkin_gap_form(hs, idx, pot, c0, stream, w=3, reps=3):

@@ -288,6 +288,31 @@ int32_t hs_error_split(hs_index sub, const void *sub_dev, hs_index box, const vo
                        const int32_t *pad_map_dev, hs_pot pot, const void *pot_dev, const void *v,
                        void *e_quad, void *e_red, void *ws, void *stream);
 
+/* ---- the unperturbed Lanczos process (paper Sec. 6.2, eq.
+ * ErrorPerturbedLanczosAnalysis) --------------------------------------------------------
+ * The paper's perturbation analysis compares the Lanczos process on A = D_K + W_{K,pol},
+ * the exact Galerkin matrix, with the process on the fast algorithm (hs_step).  These
+ * calls apply that exact operator on the rows of sub, as the fast algorithm on pad
+ * restricted to sub: pad is a box reaching ceil(a/2) beyond every coordinate of sub (a
+ * the potential's largest per-axis degree; sub a hyperbolic cross, a box or a total-
+ * degree set), or, for a hyperbolic cross, the padded cross of the same bound widened by
+ * w >= a (hs_index_create_padded).  pad_map_dev: hs_index_embed(sub, pad), uploaded
+ * (device int32, sub->size).  complex128 vectors of sub; the paper's operator form.
+ * hs_exact_workspace_bytes(m = 0) sizes hs_apply_exact's workspace, m >= 1 that of
+ * hs_step_exact.  hs_apply_exact: y = (D + W_{K,pol}) x (x != y).  hs_step_exact: one
+ * exponential-midpoint step with m Lanczos steps on the exact operator; t, t_dev, h,
+ * reorth, diag_dev as for hs_step.  The difference of hs_step and hs_step_exact from
+ * one start vector is the perturbation error of the Lanczos process; hs_step_exact with
+ * a large m approximates exp(-i h A) c for the unperturbed Lanczos error.
+ * HS_E_INVALID for a pad that does not carry the exact operator, HS_E_UNSUPPORTED for
+ * sub given as a list or the symmetrised form.                                       */
+int32_t hs_exact_workspace_bytes(hs_index sub, hs_index pad, hs_pot pot, int32_t m, int64_t *bytes);
+int32_t hs_apply_exact(hs_index sub, hs_index pad, const void *pad_dev, const int32_t *pad_map_dev, hs_pot pot,
+                       const void *pot_dev, const void *x, void *y, void *ws, void *stream);
+int32_t hs_step_exact(hs_index sub, hs_index pad, const void *pad_dev, const int32_t *pad_map_dev, hs_pot pot,
+                      void *pot_dev, double t, double *t_dev, double h, int32_t m, int32_t reorth, void *c,
+                      void *ws, double *diag_dev, void *stream);
+
 /* ---- batched form: many (index, potential) instances in one persistent launch ----
  * Instances are described by handles plus their uploaded device blocks (which must stay
  * alive); vectors of all instances are packed back to back in one device buffer with

@@ -198,6 +198,19 @@ int32_t launch_apply(const hs_index_s *idx, const void *idx_dev, const hs_pot_s 
 int32_t launch_apply_x(const hs_index_s *idx, const void *idx_dev, int32_t axis, int32_t dtype,
                        const void *x, void *y, hipStream_t s);
 int64_t apply_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32_t dtype);
+// The exact Galerkin operator D + W_{K,pol} on the rows of sub, as the fast algorithm on a
+// padded set pad restricted to sub (complex128; map = hs_index_embed(sub, pad) on the device):
+// y = out_scale * Omega(F_pad Omega_+(x)) - prev_coef * prev_scale * prev (diag.hip)
+int64_t exact_apply_workspace_bytes(const hs_index_s *pad, const hs_pot_s *p);
+int32_t launch_exact_apply(const hs_index_s *sub, const hs_index_s *pad, const void *pad_dev, const int32_t *map,
+                           const hs_pot_s *p, const void *pot_dev, const void *x, void *y, void *ws, hipStream_t s,
+                           const double *out_scale, const void *prev, const double *prev_coef,
+                           const double *prev_scale);
+// one exponential-midpoint step with that operator (lanczos.hip)
+int32_t launch_step_exact(const hs_index_s *sub, const hs_index_s *pad, const void *pad_dev, const int32_t *map,
+                          const hs_pot_s *p, void *pot_dev, double t, double *t_dev, double h, int m, int reorth,
+                          void *c, void *ws, double *diag, hipStream_t s);
+int64_t step_exact_workspace_bytes(const hs_index_s *sub, const hs_index_s *pad, const hs_pot_s *p, int m);
 // row limit of the one-workgroup step (0: never)
 void set_small_step_rows(int64_t rows);
 int64_t small_step_rows();

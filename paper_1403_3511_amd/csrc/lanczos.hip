@@ -508,6 +508,31 @@ int32_t launch_step(const hs_index_s *idx, const void *idx_dev, const hs_pot_s *
   return run_step<float>(J, m, reorth, h, c, ws, t_dev, t_dev, diag, s);
 }
 
+// ---- the unperturbed Lanczos process (paper Sec. 6.2): the same step with the exact
+// Galerkin operator D + W_{K,pol} in place of the fast algorithm ----------------------------
+int64_t step_exact_workspace_bytes(const hs_index_s *sub, const hs_index_s *pad, const hs_pot_s *p, int m) {
+  if (m <= 0) return exact_apply_workspace_bytes(pad, p);
+  const SegView sv = single_segments(sub->size);
+  return step_layout(sub->size, sv.nseg, 1, 16, m, exact_apply_workspace_bytes(pad, p)).total;
+}
+
+int32_t launch_step_exact(const hs_index_s *sub, const hs_index_s *pad, const void *pad_dev, const int32_t *map,
+                          const hs_pot_s *p, void *pot_dev, double t, double *t_dev, double h, int m, int reorth,
+                          void *c, void *ws, double *diag, hipStream_t s) {
+  StepJob J;
+  J.rows = sub->size;
+  J.sv = single_segments(sub->size);
+  J.apply_ws = exact_apply_workspace_bytes(pad, p);
+  J.set_time = [&](hipStream_t st) { return launch_set_time(p, pot_dev, t, t_dev, 0.5 * h, st); };
+  J.matvec = [&](const void *vk, void *w, const void *vprev, int k, double *sc, void *aws, hipStream_t st) {
+    return launch_exact_apply(sub, pad, pad_dev, map, p, pot_dev, vk, w, aws, st,
+                              k > 0 ? sc + Scal::inv + (k - 1) : nullptr, vprev,
+                              vprev ? sc + Scal::beta + (k - 1) : nullptr,
+                              k > 1 ? sc + Scal::inv + (k - 2) : nullptr);
+  };
+  return run_step<double>(J, m, reorth, h, c, ws, t_dev, t_dev, diag, s);
+}
+
 // ---- two-stage Gauss-Legendre Magnus scheme (paper Sec. 2.1, eq. 2stageMagnus) ----------
 // Nodes c_{1,2} = 1/2 -+ sqrt(3)/6.  Potentials of the fused class take the two fused
 // passes of matvec_m4.h; the others (and sets without a specialised kernel) apply M with

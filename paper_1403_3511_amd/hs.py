@@ -102,6 +102,9 @@ _SIGS = {
     "hs_mlp_predict": [_vp, _vp, _i32, _vp, _vp, _vp],
     "hs_mlp_train_step": [_vp, _vp, _i32, _vp, _vp, _f32, _vp, _vp, _vp],
     "hs_sur_coeffs": [_vp, _vp, _i32, _i32, _i32, _i32, _pf64, _i32, _vp, _vp, _vp, _vp],
+    "hs_exact_workspace_bytes": [_vp, _vp, _vp, _i32, _pi64],
+    "hs_apply_exact": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "hs_step_exact": [_vp, _vp, _vp, _vp, _vp, _vp, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
     "hs_checkpoint_save": [C.c_char_p, C.c_char_p, _vp, _i64, _i32, _vp],
     "hs_checkpoint_info": [C.c_char_p, C.c_char_p, _i64, _pi64, _pi64],
     "hs_checkpoint_load": [C.c_char_p, _vp, _i64, _i32, _vp],
@@ -600,6 +603,56 @@ def error_split(sub: Index, box: Index, pad, pot: Pot, v, e_quad=None, e_red=Non
                    ptr(maps[1]) if pad is not None else None, pot.h, ptr(pot.dev), ptr(v),
                    ptr(e_quad) if pad is not None else None, ptr(e_red), ptr(ws), stream_ptr())
     return e_quad, e_red
+
+
+class ExactOperator:
+    """The exact Galerkin operator D + W_{K,pol} on the rows of sub, carried by the padded
+    set pad (a box, or the padded cross of a hyperbolic sub): hs_apply_exact and
+    hs_step_exact, the unperturbed Lanczos process of the paper's perturbation analysis."""
+
+    def __init__(self, sub: Index, pad: Index):
+        torch = _torch()
+        dev = _dev_of(sub.dev, "index")
+        if _dev_of(pad.dev, "padded index") != dev:
+            _fail("ExactOperator: sub and pad are uploaded to different devices")
+        m = sub.embed_map(pad)
+        if m.size and m.min() < 0:
+            _fail("ExactOperator: pad does not contain sub")
+        self.sub, self.pad, self.device = sub, pad, dev
+        self.map = torch.from_numpy(m).to(dev)
+
+    def workspace(self, pot: Pot, m: int = 0):
+        nb = C.c_int64()
+        hs_exact_workspace_bytes(self.sub.h, self.pad.h, pot.h, int(m), C.byref(nb))
+        return dev_buffer(nb.value, self.device)
+
+    def _ws(self, name, pot, m, ws):
+        nb = C.c_int64()
+        hs_exact_workspace_bytes(self.sub.h, self.pad.h, pot.h, int(m), C.byref(nb))
+        if ws is None:
+            return dev_buffer(nb.value, self.device)
+        _check_ws(name, ws, nb.value, self.device)
+        return ws
+
+    def apply(self, pot: Pot, x, y, ws=None):
+        """y = (D + W_{K,pol}) x on sub (complex128 device tensors, x != y)."""
+        _check_vec("ExactOperator.apply: x", x, self.sub.size, dtype=HS_C128, device=self.device)
+        _check_vec("ExactOperator.apply: y", y, self.sub.size, dtype=HS_C128, device=self.device)
+        _check_distinct("ExactOperator.apply", x, y)
+        ws = self._ws("ExactOperator.apply", pot, 0, ws)
+        hs_apply_exact(self.sub.h, self.pad.h, ptr(self.pad.dev), ptr(self.map), pot.h, ptr(pot.dev), ptr(x),
+                       ptr(y), ptr(ws), stream_ptr())
+        return y
+
+    def step(self, pot: Pot, c, t: float, h: float, m: int, reorth: bool = True, ws=None, t_dev=None,
+             diag=None):
+        """One exponential-midpoint step with m Lanczos steps on the exact operator, in
+        place on c (complex128 device tensor)."""
+        _check_vec("ExactOperator.step: c", c, self.sub.size, dtype=HS_C128, device=self.device)
+        ws = self._ws("ExactOperator.step", pot, m, ws)
+        hs_step_exact(self.sub.h, self.pad.h, ptr(self.pad.dev), ptr(self.map), pot.h, ptr(pot.dev), float(t),
+                      ptr(t_dev), float(h), int(m), 1 if reorth else 0, ptr(c), ptr(ws), ptr(diag), stream_ptr())
+        return c
 
 
 class Batch:

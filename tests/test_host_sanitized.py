@@ -35,7 +35,9 @@ def test_host_code_under_asan_and_ubsan():
         env = dict(os.environ, LD_PRELOAD=rt, HS_LIBRARY=lib,
                    ASAN_OPTIONS="detect_leaks=0:halt_on_error=1",
                    UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
-        res = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+        # -s: no output capture in the child, so a sanitizer report written just before the
+        # process aborts reaches this test's message
+        res = subprocess.run([sys.executable, "-m", "pytest", "-q", "-s", "-x", "-p", "no:cacheprovider",
                               "-m", "not gpu",
                               os.path.join(ROOT, "tests", "test_lib_host.py"),
                               os.path.join(ROOT, "tests", "test_binding_checks.py"),

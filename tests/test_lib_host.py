@@ -212,6 +212,38 @@ def test_potential_classification(hs):
     assert not hs.Pot(3, [(1.0, (1, 0, 1))], upload=False).fused
 
 
+def test_exact_operator_argument_checks(hs):
+    """hs_apply_exact / hs_step_exact refuse padded sets that do not carry the exact
+    Galerkin operator, before anything reaches a device (dummy device pointers)."""
+    from synth import henon_heiles_chain
+    tt = henon_heiles_chain(3, 0.111, 0.0)
+    pot = hs.Pot(3, [(x[0], x[1], x[2], x[3], x.degrees) for x in tt], subtract_harmonic=True, upload=False)
+    sub = hs.Index(3, 12, upload=False)
+    d = C.c_void_p(256)  # never dereferenced: every case fails its checks first
+
+    def expect(code, pad, p=pot, s=sub):
+        with pytest.raises(hs.HSError) as e:
+            hs.hs_apply_exact(s.h, pad.h, d, d, p.h, d, d, C.c_void_p(512), d, None)
+        assert e.value.code == code, hs.last_error()
+        with pytest.raises(hs.HSError) as e:
+            hs.hs_step_exact(s.h, pad.h, d, d, p.h, d, 0.0, None, 0.01, 5, 1, d, d, None, None)
+        assert e.value.code == code, hs.last_error()
+
+    expect(-1, hs.Index(3, 12, upload=False))                       # not a box or a padded cross
+    expect(-1, hs.Index(3, 11 + 1, box=True, upload=False))         # box without the margin (needs 11 + 2)
+    expect(-1, hs.Index(3, 12, pad=2, upload=False))                # padded cross narrower than degree 3
+    expect(-1, hs.Index(3, 13, pad=3, upload=False))                # padded cross of another bound
+    expect(-1, hs.Index(4, 20, box=True, upload=False))             # another dimension
+    lst = hs.Index(3, rows=sub.multi_indices(), upload=False)
+    expect(-5, hs.Index(3, 16, box=True, upload=False), s=lst)      # sets given as lists
+    nb = C.c_int64()
+    box = hs.Index(3, 13, box=True, upload=False)  # kept alive across the call
+    hs.hs_exact_workspace_bytes(sub.h, box.h, pot.h, 5, C.byref(nb))
+    assert nb.value > 0
+    with pytest.raises(hs.HSError):
+        hs.hs_exact_workspace_bytes(sub.h, sub.h, pot.h, 33, C.byref(nb))
+
+
 def test_error_paths(hs):
     h = C.c_void_p()
     codes = []
