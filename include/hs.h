@@ -435,6 +435,20 @@ int32_t hs_mlp_train_step(hs_mlp mlp, void *dev, int32_t batch, const double *x_
                           const double *target_dev, float lr, float *loss_dev,
                           float *grads_dev, void *stream);
 
+/* ---- debug build: neighbour-index checks ---------------------------------------------
+ * Built with -DHS_DEBUG_BOUNDS (libhs_debug.so, see the package's build), the H-application
+ * kernels check every tile record, work item, suffix-stencil offset and neighbour index
+ * they use against the sizes of the set and the vector; a failed check is counted in the
+ * index's device block (and the unchecked access is skipped where the hardware would not
+ * bound it), so the kernels never fault.  hs_debug_checks reports whether this library
+ * has the checks (1) or not (0; the release build, where they compile to nothing).
+ * hs_index_debug_read copies the index's two counters (number of failed checks, code of
+ * the first: 1 record, 2 work item, 3 suffix offset, 4 neighbour index, 5 tile position,
+ * 6 row) to counts_host (host uint32[2]) after the work already enqueued on stream, and
+ * zeroes them when clear != 0; it synchronises the stream.  hs_index_upload zeroes them.  */
+int32_t hs_debug_checks(int32_t *built);
+int32_t hs_index_debug_read(hs_index idx, const void *idx_dev, uint32_t *counts_host, int32_t clear, void *stream);
+
 /* ---- checkpoint and resume (an addition: the state of Fig. 4's time_propagation) ----
  * The state of a propagation is (c^n, t_n, n) plus the configuration that produced it.
  * hs_checkpoint_save writes bytes bytes of src (the coefficient vector, any dtype) and a

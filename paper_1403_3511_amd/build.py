@@ -14,6 +14,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhs.so")
+# the same library with the kernels' neighbour-index checks compiled in (HS_DEBUG_BOUNDS)
+OUT_DEBUG = os.path.join(HERE, "libhs_debug.so")
 SOURCES = ["api.cpp", "index.cpp", "potential.cpp", "matvec.hip", "matvec_long_f64.hip",
            "matvec_long_f32.hip", "matvec_multi_f64.hip", "matvec_multi_f32.hip", "matvec_m4_f64.hip", "matvec_m4_f32.hip", "matvec_sym_f64.hip",
            "matvec_sym_f32.hip", "lanczos.hip", "step_small_f64.hip", "step_small_f32.hip",
@@ -40,6 +42,11 @@ def _compile(src: str, obj: str, defines=(), extra=()) -> tuple[str, int, str]:
     msg = "\n".join(line for line in (res.stdout + res.stderr).splitlines()
                     if "packed-fp32-ops" not in line and "not a recognized feature" not in line)
     return src, res.returncode, msg
+
+
+def build_debug(verbose: bool = False) -> str:
+    """Compile libhs_debug.so: libhs.so with the neighbour-index checks of HS_DEBUG_BOUNDS."""
+    return build(verbose=verbose, out=OUT_DEBUG, defines=("HS_DEBUG_BOUNDS",))
 
 
 def build(verbose: bool = False, out: str | None = None, defines=(), sanitize: bool = False) -> str:
@@ -82,3 +89,5 @@ def _copy(src, dst):
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    if "--debug" in sys.argv:
+        print(build_debug(verbose=True))

@@ -163,6 +163,34 @@ extern "C" int32_t hs_step(hs_index idx, const void *idx_dev, hs_pot pot, void *
                          static_cast<hipStream_t>(stream));
 }
 
+extern "C" int32_t hs_debug_checks(int32_t *built) {
+  if (!built) return hs::fail(HS_E_INVALID, "hs_debug_checks: built is NULL");
+#ifdef HS_DEBUG_BOUNDS
+  *built = 1;
+#else
+  *built = 0;
+#endif
+  return HS_OK;
+}
+
+extern "C" int32_t hs_index_debug_read(hs_index idx, const void *idx_dev, uint32_t *counts_host, int32_t clear,
+                                       void *stream) {
+  if (!idx || !idx_dev || !counts_host) return hs::fail(HS_E_INVALID, "hs_index_debug_read: NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint8_t *dbg = const_cast<uint8_t *>(static_cast<const uint8_t *>(idx_dev)) + idx->off_dbg;
+  uint32_t words[2] = {0, 0};
+  HS_HIP(hipMemcpyAsync(words, dbg, sizeof(words), hipMemcpyDeviceToHost, s));
+  HS_HIP(hipStreamSynchronize(s));
+  counts_host[0] = words[0];
+  counts_host[1] = words[1];
+  if (clear) {
+    const uint32_t zero[2] = {0, 0};
+    HS_HIP(hipMemcpyAsync(dbg, zero, sizeof(zero), hipMemcpyHostToDevice, s));
+    HS_HIP(hipStreamSynchronize(s));
+  }
+  return HS_OK;
+}
+
 extern "C" int32_t hs_set_small_step_rows(int64_t rows) {
   if (rows < 0) return hs::fail(HS_E_INVALID, "hs_set_small_step_rows: negative row count");
   hs::set_small_step_rows(rows);

@@ -60,6 +60,7 @@ struct IndexDev {
   // work items of the multi-tile kernel: (first offset, tile count, kMultiTiles records)
   int64_t nmitems;
   const int32_t *mitems;     // [nmitems][2 + kMultiTiles]
+  uint32_t *dbg;             // [2] failed neighbour-index checks of the debug build, first code
 };
 
 // Suffix stencil pairs.  Axis pairs p = 3 a + (|s| - 1) hold the displacements -|s|
@@ -118,7 +119,7 @@ struct hs_index_s {
   // device blob layout (byte offsets)
   int64_t off_tstart = 0, off_tlen = 0, off_tnbr = 0, off_tpfx = 0, off_tpsum = 0,
           off_gsidx = 0, off_gnbr = 0, off_gssum = 0, off_rowtile = 0, off_wtab = 0,
-          off_wtabf = 0, off_wtp = 0, off_wtpf = 0, off_gsp = 0, off_gst = 0, off_chunks = 0, off_small = 0, off_recs = 0, off_tile_rec = 0, off_mitems = 0,
+          off_wtabf = 0, off_wtp = 0, off_wtpf = 0, off_gsp = 0, off_gst = 0, off_chunks = 0, off_small = 0, off_recs = 0, off_tile_rec = 0, off_mitems = 0, off_dbg = 0,
           dev_bytes = 0;
   std::vector<uint8_t> blob;   // host image of the device block
   void *pinned = nullptr;      // pinned staging for the upload

@@ -392,6 +392,7 @@ hs::IndexDev hs_index_s::view(const void *dev) const {
   v.tile_rec = recs_all ? reinterpret_cast<const int32_t *>(b + off_tile_rec) : nullptr;
   v.nmitems = nmitems;
   v.mitems = reinterpret_cast<const int32_t *>(b + off_mitems);
+  v.dbg = const_cast<uint32_t *>(reinterpret_cast<const uint32_t *>(b + off_dbg));
   return v;
 }
 
@@ -666,6 +667,7 @@ static int32_t build_index(hs_index_s *ix) {
   ix->off_recs = take((int64_t)ix->recs.size() * 4);
   ix->off_tile_rec = take((int64_t)ix->tile_rec.size() * 4);
   ix->off_mitems = take((int64_t)ix->mitems.size() * 4);
+  ix->off_dbg = take(8);  // the debug build's check counters, zero on upload
   ix->dev_bytes = off;
   ix->blob.assign(off, 0);
   auto put = [&](int64_t o, const void *src, int64_t bytes) {

@@ -56,6 +56,7 @@ struct Pos {
 // move one step along axis (0-based) in direction up (1: +e, 0: -e); t < 0 = absent
 __device__ __forceinline__ Pos mv(const IndexDev &ix, Pos p, int axis, int up) {
   if (p.t < 0) return p;
+  HS_DCHECK(ix, p.t < ix.ntiles && p.o >= 0 && p.o < ix.ng, kDbgPosition);
   if (axis < ix.np) {
     const int32_t t2 = ix.tnbr[(int64_t)p.t * (2 * ix.np) + 2 * axis + up];
     if (t2 < 0 || (up && p.o >= ix.tlen[t2])) return Pos{-1, 0};
@@ -76,6 +77,13 @@ template <typename T>
 __device__ __forceinline__ typename V2<T>::t ld(const typename V2<T>::t *__restrict__ c,
                                                 const IndexDev &ix, Pos p) {
   if (p.t < 0) return vz<T>();
+#ifdef HS_DEBUG_BOUNDS
+  // a position outside its tile is counted and not read
+  if (!(p.t < ix.ntiles && p.o >= 0 && p.o < ix.tlen[p.t])) {
+    debug_flag(ix.dbg, kDbgPosition);
+    return vz<T>();
+  }
+#endif
   return c[ix.tstart[p.t] + p.o];
 }
 

@@ -108,6 +108,8 @@ __device__ __forceinline__ typename V2<T>::t hh_row_value(const IndexDev &ix, co
   const __amdgpu_buffer_rsrc_t xr = vec_rsrc<T>(x, ix.size);
   const uint32_t base = (uint32_t)rec[0];
   const int32_t len = rec[1];
+  HS_DCHECK(ix, rec[0] >= 0 && len >= 0 && (int64_t)rec[0] + len <= ix.size && o >= 0 && o < len &&
+                    (int64_t)o < ix.ng, kDbgRecord);
   const T *__restrict__ wt;
   if constexpr (sizeof(T) == 8) wt = (const T *)ix.wtab; else wt = (const T *)ix.wtabf;
   const int64_t ng = ix.ng;
@@ -183,6 +185,7 @@ __device__ __forceinline__ typename V2<T>::t hh_row_value(const IndexDev &ix, co
         if (s == 0) continue;
         const int p = rec_axis(NP, l, s);
         const int32_t st = rec[p], ln = rec[p + 1];
+        HS_DCHECK(ix, ln == 0 || (st >= 0 && ln > 0 && (int64_t)st + ln <= ix.size), kDbgRecord);
         stw[3 + s] = st;
         lnw[3 + s] = ln;
         val[3 + s] = o < ln;
@@ -197,6 +200,7 @@ __device__ __forceinline__ typename V2<T>::t hh_row_value(const IndexDev &ix, co
         if (s == 3 && !need3) continue;
         const int2 pr = gst2[gst_axis_pair(a, s) * ng + o];  // (-s, +s)
         const int32_t ou = pr.y, od = pr.x;
+        HS_DCHECK(ix, (od == -1 || (od >= 0 && od < ng)) && (ou == -1 || (ou >= 0 && ou < ng)), kDbgSuffix);
         val[3 + s] = (uint32_t)ou < (uint32_t)len;
         val[3 - s] = od >= 0;
         id[3 + s] = val[3 + s] ? base + (uint32_t)ou : kAbsent;
@@ -216,6 +220,8 @@ __device__ __forceinline__ typename V2<T>::t hh_row_value(const IndexDev &ix, co
       e[s + 2] = w;
       ea3[s + 2] = w * a3;
     }
+#pragma unroll
+    for (int q = 0; q < 7; ++q) HS_DCHECK(ix, !val[q] || id[q] < (uint64_t)ix.size, kDbgNeighbour);
     C u[7];
 #pragma unroll
     for (int q = 0; q < 7; ++q) u[q] = vz<T>();
@@ -310,6 +316,7 @@ __device__ __forceinline__ typename V2<T>::t hh_row_value(const IndexDev &ix, co
                 const int32_t oq = r < 0 ? cr.x : cr.y;
                 vid = (vs_ok && (uint32_t)oq < (uint32_t)len) ? base + (uint32_t)oq : kAbsent;
               }
+              HS_DCHECK(ix, vid == kAbsent || vid < (uint64_t)ix.size, kDbgNeighbour);
               const C xv = BufLoad<T>::ld(xr, vid);
               if constexpr (SYM) {
                 if (r < 0) xs_lo[s + 2] = xv; else xs_hi[s + 2] = xv;

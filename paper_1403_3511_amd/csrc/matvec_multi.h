@@ -57,6 +57,8 @@ __device__ __forceinline__ void load_suffix_meta(const IndexDev &ix, int32_t o, 
 #pragma unroll
     for (int k = 1; k <= 3; ++k) {
       const int2 pr = gst2[gst_axis_pair(a, k) * ng + o];  // (-k, +k)
+      HS_DCHECK(ix, (pr.x == -1 || (pr.x >= 0 && pr.x < ng)) && (pr.y == -1 || (pr.y >= 0 && pr.y < ng)),
+                kDbgSuffix);
       M.off[a][kidx(-k)] = (uint32_t)pr.x;
       M.off[a][kidx(k)] = (uint32_t)pr.y;
     }
@@ -65,6 +67,8 @@ __device__ __forceinline__ void load_suffix_meta(const IndexDev &ix, int32_t o, 
       for (int q = 0; q < 2; ++q) {
         const int k = q == 0 ? -2 : 2;
         const int2 pr = gst2[gst_cross_pair(D, a, k) * ng + o];  // (r = -1, r = +1)
+        HS_DCHECK(ix, (pr.x == -1 || (pr.x >= 0 && pr.x < ng)) && (pr.y == -1 || (pr.y >= 0 && pr.y < ng)),
+                  kDbgSuffix);
         M.cr[a][2 * q] = (uint32_t)pr.x;
         M.cr[a][2 * q + 1] = (uint32_t)pr.y;
       }
@@ -178,6 +182,8 @@ __device__ __forceinline__ typename V2<T>::t multi_row(const IndexDev &ix, const
         const int p = rec_axis(NP, l, k);
         st[3 + k] = rec[p];
         ln[3 + k] = rec[p + 1];
+        HS_DCHECK(ix, ln[3 + k] == 0 || (st[3 + k] >= 0 && ln[3 + k] > 0 &&
+                                         (int64_t)st[3 + k] + ln[3 + k] <= ix.size), kDbgRecord);
       }
       E[3] = o < ln[4] ? E[3] : T(0);
       E[4] = o < ln[5] ? E[4] : T(0);
@@ -193,6 +199,9 @@ __device__ __forceinline__ typename V2<T>::t multi_row(const IndexDev &ix, const
           if constexpr (l + 1 < NP) {
             // p + k e_l -+ e_{l+1}: two prefix moves, the same offset
             const int pl = rec_pair(NP, l, k, -1), ph = rec_pair(NP, l, k, 1);
+            HS_DCHECK(ix, (rec[pl + 1] == 0 || (rec[pl] >= 0 && (int64_t)rec[pl] + rec[pl + 1] <= ix.size)) &&
+                              (rec[ph + 1] == 0 || (rec[ph] >= 0 && (int64_t)rec[ph] + rec[ph + 1] <= ix.size)),
+                      kDbgRecord);
             lo[q] = BufLoad<T>::ld(tile_rsrc<T>(x, rec[pl], rec[pl + 1]), (uint32_t)o);
             hi[q] = BufLoad<T>::ld(tile_rsrc<T>(x, rec[ph], rec[ph + 1]), (uint32_t)o);
           } else {
@@ -235,12 +244,16 @@ __device__ __forceinline__ void multi_item(const IndexDev &ix, const double *__r
   const int32_t o = o0 + (int32_t)(threadIdx.x & 63);
   // the first tile is the longest of the item: lanes past its end have no row at all
   const int32_t len0 = ix.recs[(int64_t)__builtin_amdgcn_readfirstlane(it[2]) * RS + 1];
+  HS_DCHECK(ix, o0 >= 0 && (o0 % 64) == 0 && nr >= 1 && nr <= kMultiTiles && o0 < len0, kDbgItem);
   if (o >= len0) return;
+  HS_DCHECK(ix, (int64_t)o < ix.ng, kDbgItem);
   SufMeta<T, N - NP> M;
   load_suffix_meta<T, N - NP>(ix, o, M);
   for (int32_t r = 0; r < nr; ++r) {
     const int32_t ri = __builtin_amdgcn_readfirstlane(it[2 + r]);
     const int32_t *__restrict__ rec = ix.recs + (int64_t)ri * RS;
+    HS_DCHECK(ix, rec[0] >= 0 && rec[1] >= 0 && (int64_t)rec[0] + rec[1] <= ix.size && rec[1] <= len0,
+              kDbgRecord);
     if (o >= rec[1]) continue;
     C acc = multi_row<T, N, NP>(ix, hh, x, rec, o, M);
     const int64_t row = (int64_t)rec[0] + o;

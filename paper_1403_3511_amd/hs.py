@@ -102,6 +102,8 @@ _SIGS = {
     "hs_mlp_predict": [_vp, _vp, _i32, _vp, _vp, _vp],
     "hs_mlp_train_step": [_vp, _vp, _i32, _vp, _vp, _f32, _vp, _vp, _vp],
     "hs_sur_coeffs": [_vp, _vp, _i32, _i32, _i32, _i32, _pf64, _i32, _vp, _vp, _vp, _vp],
+    "hs_debug_checks": [_pi32],
+    "hs_index_debug_read": [_vp, _vp, C.POINTER(C.c_uint32), _i32, _vp],
     "hs_exact_workspace_bytes": [_vp, _vp, _vp, _i32, _pi64],
     "hs_apply_exact": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "hs_step_exact": [_vp, _vp, _vp, _vp, _vp, _vp, _f64, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
@@ -149,6 +151,13 @@ _lib_raw = _lib
 
 def hs_version() -> str:
     return _lib.hs_version().decode()
+
+
+def debug_checks() -> bool:
+    """Whether the loaded library is the debug build with neighbour-index checks."""
+    b = C.c_int32()
+    hs_debug_checks(C.byref(b))
+    return bool(b.value)
 
 
 # ---------------------------------------------------------------------------------------
@@ -323,6 +332,13 @@ class Index:
         if self.rows_sha256 is not None:
             d["rows_sha256"] = self.rows_sha256
         return d
+
+    def debug_counts(self, clear: bool = True):
+        """(failed neighbour-index checks, code of the first) recorded on this index by the
+        debug build's kernels (always (0, 0) with the release build)."""
+        out = (C.c_uint32 * 2)()
+        hs_index_debug_read(self.h, ptr(self.dev), out, 1 if clear else 0, stream_ptr())
+        return int(out[0]), int(out[1])
 
     def multi_indices(self) -> np.ndarray:
         out = np.empty((self.size, self.N), dtype=np.uint16)

@@ -212,6 +212,20 @@ def test_potential_classification(hs):
     assert not hs.Pot(3, [(1.0, (1, 0, 1))], upload=False).fused
 
 
+def test_debug_build_is_built_with_its_checks(hs):
+    """libhs_debug.so (built by __graft_entry__.build()) exports the same ABI and reports
+    its neighbour-index checks; the release library reports none."""
+    path = os.path.join(ROOT, "paper_1403_3511_amd", "libhs_debug.so")
+    assert os.path.exists(path), "libhs_debug.so not built: run __graft_entry__.build()"
+    dbg = C.CDLL(path)
+    for name in declared_functions():
+        assert hasattr(dbg, name), name
+    built = C.c_int32(-1)
+    dbg.hs_debug_checks.argtypes = [C.POINTER(C.c_int32)]
+    assert dbg.hs_debug_checks(C.byref(built)) == 0 and built.value == 1
+    assert hs.debug_checks() is False
+
+
 def test_exact_operator_argument_checks(hs):
     """hs_apply_exact / hs_step_exact refuse padded sets that do not carry the exact
     Galerkin operator, before anything reaches a device (dummy device pointers)."""
