@@ -467,22 +467,27 @@ __device__ __forceinline__ float silu_grad_f(float z) {
   return s * (1.0f + z * (1.0f - s));
 }
 
+// C = A B (M x N, inner dimension K) with BF16 MFMA tiles 16x16x32 and FP32 accumulation.
+// One workgroup per 16x16 output tile; its four waves split the K steps (wave w takes
+// steps w, w + 4, ...), and their partial tiles are added in wave order through LDS, so
+// the result does not depend on scheduling.  A(i, k) = A[i sa0 + k sa1], B(k, j) =
+// B[k sb0 + j sb1].  Epilogues: store (plus bias), bias + SiLU (keeping Z), or the
+// product with SiLU'(Zin).
 template <int EPI>
 __global__ void __launch_bounds__(256)
 k_gemm_bf16(int M, int N, int K, const float *__restrict__ A, int64_t sa0, int64_t sa1,
             const float *__restrict__ B, int64_t sb0, int64_t sb1, float *__restrict__ C, int64_t ldc,
             const float *__restrict__ bias, float *__restrict__ Z, float *__restrict__ H,
             const float *__restrict__ Zin) {
+  __shared__ float part[4][4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tiles_n = (N + 15) / 16;
-  const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
-  const int ti = (int)(tile / tiles_n), tj = (int)(tile % tiles_n);
-  if (ti * 16 >= M) return;
+  const int ti = (int)(blockIdx.x / tiles_n), tj = (int)(blockIdx.x % tiles_n);
   const int i = ti * 16 + (lane & 15);   // A row of this lane
   const int j = tj * 16 + (lane & 15);   // B column of this lane
   const int kq = (lane >> 4) * 8;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  for (int k0 = 32 * wave; k0 < K; k0 += 128) {
     bf16x8 a, b;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -495,11 +500,18 @@ k_gemm_bf16(int M, int N, int K, const float *__restrict__ A, int64_t sa0, int64
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
   }
 #pragma unroll
+  for (int r = 0; r < 4; ++r) part[wave][r][lane] = acc[r];
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int oi = ti * 16 + (lane >> 4) * 4 + r;
     const int oj = tj * 16 + (lane & 15);
     if (oi >= M || oj >= N) continue;
-    float v = acc[r];
+    float v = part[0][r][lane];
+    v += part[1][r][lane];
+    v += part[2][r][lane];
+    v += part[3][r][lane];
     if constexpr (EPI == kEpiStore) {
       if (bias) v += bias[oj];
       C[(int64_t)oi * ldc + oj] = v;
@@ -513,14 +525,24 @@ k_gemm_bf16(int M, int N, int K, const float *__restrict__ A, int64_t sa0, int64
   }
 }
 
-// column sums of X (rows x cols) in a fixed order: out[j] = sum_i X[i][j]
+// column sums of X (rows x cols) in a fixed order: out[j] = sum_i X[i][j].  A workgroup
+// takes 16 columns; its 16 row groups (rows g, g + 16, ...) sum in parallel, then the
+// 16 partial sums of a column are added in group order.
 __global__ void __launch_bounds__(256) k_colsum(int rows, int cols, const float *__restrict__ X,
                                                 float *__restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
+  __shared__ float part[16][16];
+  const int c = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int j = blockIdx.x * 16 + c;
   float s = 0.f;
-  for (int i = 0; i < rows; ++i) s += X[(int64_t)i * cols + j];
-  out[j] = s;
+  if (j < cols)
+    for (int i = grp; i < rows; i += 16) s += X[(int64_t)i * cols + j];
+  part[grp][c] = s;
+  __syncthreads();
+  if (grp != 0 || j >= cols) return;
+  float t = 0.f;
+#pragma unroll
+  for (int g = 0; g < 16; ++g) t += part[g][c];
+  out[j] = t;
 }
 
 // tn = (target - mean) / std
@@ -532,13 +554,17 @@ __global__ void k_norm_out(int64_t n, int out, const double *__restrict__ tg, co
   tn[idx] = (float)((tg[idx] - mean[j]) / sd[j]);
 }
 
-// d = y - t; dY = 2 d / n; loss = mean d^2 (one block, fixed order)
+// d = y - t; dY = 2 d / n; loss partials: each workgroup sums d^2 over its
+// kMseRows elements in a fixed order (k_mse_fin adds the partials in workgroup order)
+constexpr int kMseRows = 2048;
 __global__ void __launch_bounds__(256) k_mse(int64_t n, const float *__restrict__ y, const float *__restrict__ t,
-                                             float *__restrict__ dy, float *__restrict__ loss) {
+                                             float *__restrict__ dy, float *__restrict__ part) {
   __shared__ float sh[256];
   float acc = 0.f;
   const float sc = 2.0f / (float)n;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+  const int64_t i0 = (int64_t)blockIdx.x * kMseRows;
+  const int64_t i1 = i0 + kMseRows < n ? i0 + kMseRows : n;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     const float d = y[i] - t[i];
     dy[i] = sc * d;
     acc += d * d;
@@ -549,7 +575,15 @@ __global__ void __launch_bounds__(256) k_mse(int64_t n, const float *__restrict_
     if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && loss) *loss = sh[0] / (float)n;
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// loss = (sum of the partials, in order) / n
+__global__ void k_mse_fin(int nparts, int64_t n, const float *__restrict__ part, float *__restrict__ loss) {
+  if (threadIdx.x != 0 || !loss) return;
+  float s = 0.f;
+  for (int b = 0; b < nparts; ++b) s += part[b];
+  *loss = s / (float)n;
 }
 
 // Adam with bias correction; the step counter *tstep is advanced by the next kernel on
@@ -691,7 +725,7 @@ struct hs_mlp_s {
   int32_t max_batch = 0;
   int64_t off_w = 0, off_m = 0, off_v = 0, off_g = 0, off_norm = 0, off_t = 0, off_loss = 0,
           off_x = 0, off_z1 = 0, off_h1 = 0, off_z2 = 0, off_h2 = 0, off_y = 0, off_tn = 0,
-          off_dy = 0, off_dz2 = 0, off_dz1 = 0, off_wb = 0, dev_bytes = 0;
+          off_dy = 0, off_dz2 = 0, off_dz1 = 0, off_wb = 0, off_lpart = 0, dev_bytes = 0;
   void layout(int32_t mb) {
     max_batch = mb;
     int64_t off = 0;
@@ -718,6 +752,7 @@ struct hs_mlp_s {
     off_dz2 = take(4 * (int64_t)mb * hid);
     off_dz1 = take(4 * (int64_t)mb * hid);
     off_wb = take(2 * ((int64_t)hid * 32 + (int64_t)hid * hid + (int64_t)outp * hid));
+    off_lpart = take(4 * (((int64_t)mb * out + hs::kMseRows - 1) / hs::kMseRows));
     dev_bytes = off;
   }
 };
@@ -731,9 +766,8 @@ void gemm(hipStream_t s, int M, int N, int K, const float *A, int64_t sa0, int64
           int64_t sb0, int64_t sb1, float *C, int64_t ldc, const float *bias = nullptr, float *Z = nullptr,
           float *H = nullptr, const float *Zin = nullptr) {
   const int64_t tiles = (int64_t)((M + 15) / 16) * ((N + 15) / 16);
-  const unsigned blocks = (unsigned)((tiles + 3) / 4);
-  hipLaunchKernelGGL((hs::k_gemm_bf16<EPI>), dim3(blocks), dim3(256), 0, s, M, N, K, A, sa0, sa1, B, sb0,
-                     sb1, C, ldc, bias, Z, H, Zin);
+  hipLaunchKernelGGL((hs::k_gemm_bf16<EPI>), dim3((unsigned)tiles), dim3(256), 0, s, M, N, K, A, sa0, sa1, B,
+                     sb0, sb1, C, ldc, bias, Z, H, Zin);
 }
 
 __bf16 *WB(void *dev, const hs_mlp_s *p, int layer) {
@@ -1028,23 +1062,26 @@ int32_t hs_mlp_train_step(hs_mlp mlp, void *dev, int32_t batch, const double *x_
                      nrm + 2 * in, nrm + 2 * in + out, F(dev, mlp->off_tn));
   // forward in one launch, keeping the normalised input and the activations
   mlp_fwd<true>(mlp, dev, batch, x_dev, nullptr, s);
-  hipLaunchKernelGGL(hs::k_mse, dim3(1), dim3(256), 0, s, ny, F(dev, mlp->off_y), F(dev, mlp->off_tn),
-                     F(dev, mlp->off_dy), loss_dev ? loss_dev : F(dev, mlp->off_loss));
+  const int nmse = (int)((ny + hs::kMseRows - 1) / hs::kMseRows);
+  hipLaunchKernelGGL(hs::k_mse, dim3(nmse), dim3(256), 0, s, ny, F(dev, mlp->off_y), F(dev, mlp->off_tn),
+                     F(dev, mlp->off_dy), F(dev, mlp->off_lpart));
+  hipLaunchKernelGGL(hs::k_mse_fin, dim3(1), dim3(64), 0, s, nmse, ny, (const float *)F(dev, mlp->off_lpart),
+                     loss_dev ? loss_dev : F(dev, mlp->off_loss));
   float *dy = F(dev, mlp->off_dy), *h2 = F(dev, mlp->off_h2), *h1 = F(dev, mlp->off_h1);
   float *dz2 = F(dev, mlp->off_dz2), *dz1 = F(dev, mlp->off_dz1), *xn = F(dev, mlp->off_x);
   // layer 3: dW3 = dY^T H2, db3 = colsum dY, dZ2 = (dY W3) * silu'(Z2)
   gemm<hs::kEpiStore>(s, out, hid, batch, dy, 1, out, h2, hid, 1, g + mlp->oW3, hid);
-  hipLaunchKernelGGL(hs::k_colsum, dim3((out + 255) / 256), dim3(256), 0, s, batch, out, dy, g + mlp->ob3);
+  hipLaunchKernelGGL(hs::k_colsum, dim3((out + 15) / 16), dim3(256), 0, s, batch, out, dy, g + mlp->ob3);
   gemm<hs::kEpiSiluGrad>(s, batch, hid, out, dy, out, 1, w + mlp->oW3, hid, 1, dz2, hid, nullptr, nullptr, nullptr,
                          F(dev, mlp->off_z2));
   // layer 2
   gemm<hs::kEpiStore>(s, hid, hid, batch, dz2, 1, hid, h1, hid, 1, g + mlp->oW2, hid);
-  hipLaunchKernelGGL(hs::k_colsum, dim3((hid + 255) / 256), dim3(256), 0, s, batch, hid, dz2, g + mlp->ob2);
+  hipLaunchKernelGGL(hs::k_colsum, dim3((hid + 15) / 16), dim3(256), 0, s, batch, hid, dz2, g + mlp->ob2);
   gemm<hs::kEpiSiluGrad>(s, batch, hid, hid, dz2, hid, 1, w + mlp->oW2, hid, 1, dz1, hid, nullptr, nullptr, nullptr,
                          F(dev, mlp->off_z1));
   // layer 1
   gemm<hs::kEpiStore>(s, hid, in, batch, dz1, 1, hid, xn, kin, 1, g + mlp->oW1, in);
-  hipLaunchKernelGGL(hs::k_colsum, dim3((hid + 255) / 256), dim3(256), 0, s, batch, hid, dz1, g + mlp->ob1);
+  hipLaunchKernelGGL(hs::k_colsum, dim3((hid + 15) / 16), dim3(256), 0, s, batch, hid, dz1, g + mlp->ob1);
   // Adam
   const unsigned ab = (unsigned)((mlp->nparam + 255) / 256);
   hipLaunchKernelGGL(hs::k_adam, dim3(ab), dim3(256), 0, s, mlp->nparam, w, (const float *)g, F(dev, mlp->off_m),
