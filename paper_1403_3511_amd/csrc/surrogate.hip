@@ -606,27 +606,38 @@ __global__ void __launch_bounds__(256) k_adam(int64_t n, float *__restrict__ w, 
 }
 
 // ---- fused forward pass ------------------------------------------------------------------
-// One workgroup (4 waves) carries 16 samples through the three layers.  Activations stay in
-// LDS as BF16, the operand precision of the products, so the result equals that of three
+// One workgroup (16 waves) carries 16 samples through the three layers.  Activations stay
+// in LDS as BF16, the operand precision of the products, so the result equals that of three
 // separate products; weights come from BF16 copies laid out as the fragments need them
-// (row j holds the inputs of output j).  Each wave owns a quarter of the output columns.
+// (row j holds the inputs of output j).  The 16-column output tiles of a layer go round-
+// robin to the waves (one tile per wave at 256 columns), so a layer costs about one
+// memory latency even for a single sample.
 constexpr int kFwdRows = 16;
 constexpr int kFwdLd0 = 40;  // LDS row stride of the input tile (32 + 8 padding), in bf16
 
 template <class Epi>
 __device__ __forceinline__ void dense_layer(const __bf16 *A, int lda, int K, const __bf16 *__restrict__ W,
                                             int ldw, int ncols, Epi &&epi) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int per = ncols >> 2;  // columns of this wave, a multiple of 16
-  const int c0 = wave * per;
+  // 16-column output tiles round-robin over the block's waves; each tile's weight loads
+  // for up to kPre K steps are issued together before its MFMAs
+  constexpr int kPre = 8;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   const int row = lane & 15, kq = (lane >> 4) * 8;
-  for (int t = 0; t < per; t += 16) {
-    const int col = c0 + t + (lane & 15);
+  for (int t = wave; t < (ncols >> 4); t += nw) {
+    const int col = t * 16 + (lane & 15);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 32) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8 *>(A + row * lda + k0 + kq);
-      const bf16x8 b = *reinterpret_cast<const bf16x8 *>(W + (int64_t)col * ldw + k0 + kq);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    for (int k0 = 0; k0 < K; k0 += 32 * kPre) {
+      bf16x8 b[kPre];
+#pragma unroll
+      for (int q = 0; q < kPre; ++q)
+        if (k0 + 32 * q < K) b[q] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)col * ldw + k0 + 32 * q + kq);
+#pragma unroll
+      for (int q = 0; q < kPre; ++q) {
+        if (k0 + 32 * q < K) {
+          const bf16x8 a = *reinterpret_cast<const bf16x8 *>(A + row * lda + k0 + 32 * q + kq);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[q], acc, 0, 0, 0);
+        }
+      }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) epi((lane >> 4) * 4 + r, col, acc[r]);
@@ -637,7 +648,7 @@ __device__ __forceinline__ void dense_layer(const __bf16 *A, int lda, int K, con
 // TRAIN = true: also writes the normalised input and the pre/post activations (float32)
 // that the backward pass reads, and the normalised output y.
 template <bool TRAIN>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_mlp_fwd(int M, int in, int hid, int out, int outp, const double *__restrict__ x, const float *__restrict__ nrm,
           const __bf16 *__restrict__ W1b, const float *__restrict__ b1, const __bf16 *__restrict__ W2b,
           const float *__restrict__ b2, const __bf16 *__restrict__ W3b, const float *__restrict__ b3,
@@ -789,7 +800,7 @@ template <bool TRAIN>
 void mlp_fwd(hs_mlp_s *p, void *dev, int batch, const double *x, double *coef, hipStream_t s) {
   const float *w = F(dev, p->off_w);
   const size_t lds = sizeof(__bf16) * ((size_t)hs::kFwdRows * hs::kFwdLd0 + 2 * (size_t)hs::kFwdRows * (p->hid + 8));
-  hipLaunchKernelGGL((hs::k_mlp_fwd<TRAIN>), dim3((batch + hs::kFwdRows - 1) / hs::kFwdRows), dim3(256), lds, s,
+  hipLaunchKernelGGL((hs::k_mlp_fwd<TRAIN>), dim3((batch + hs::kFwdRows - 1) / hs::kFwdRows), dim3(1024), lds, s,
                      batch, p->in, p->hid, p->out, p->outp, x, (const float *)F(dev, p->off_norm), WB(dev, p, 1),
                      w + p->ob1, WB(dev, p, 2), w + p->ob2, WB(dev, p, 3), w + p->ob3, coef,
                      F(dev, p->off_x), F(dev, p->off_z1), F(dev, p->off_h1), F(dev, p->off_z2), F(dev, p->off_h2),
