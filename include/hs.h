@@ -104,6 +104,15 @@ int32_t hs_index_multi_indices(hs_index idx, uint16_t *host_out);
  * the handle).  Every compute call on this index takes the same device pointer.     */
 int32_t hs_index_device_bytes(hs_index idx, int64_t *bytes);
 int32_t hs_index_upload(hs_index idx, void *dev, int64_t bytes, void *stream);
+/* Fibres of every axis for chained recurrence passes (an addition to paper Sec. 3.2,
+ * eq. Horner, whose passes apply the basis's three-term recurrence along one axis at a
+ * time): the generic program's chains of passes along one axis then run as one launch
+ * over that axis's fibres (rows differing in k_l alone) instead of one launch per pass,
+ * with results equal bit for bit.  Appends about 8 bytes per row and axis to the device
+ * block: call it before hs_index_device_bytes and hs_index_upload (a block sized or
+ * uploaded before must be sized and uploaded again).  Idempotent.  HS_E_OVERFLOW for
+ * sets of 2^31 rows or more or fibres longer than 65535 rows.                        */
+int32_t hs_index_build_fibres(hs_index idx);
 
 /* Box sets {0..Kmax}^N (the full index set K_full of paper Sec. 4.1-4.2), in the same
  * tiled layout (every tile holds the whole suffix list, in lexicographic order), for

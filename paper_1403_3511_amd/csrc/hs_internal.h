@@ -95,6 +95,12 @@ __host__ __device__ constexpr int rec_pair(int np, int l, int s, int r) {
 constexpr int kChunk = 64;       // rows per wave in the long-tile kernel
 constexpr int kMultiTiles = 4;   // tiles per work item of the multi-tile kernel
 constexpr int kLongTile = 32;    // tiles at least this long go to the long-tile kernel
+// Fibres for chained recurrence passes (hs_index_build_fibres): positions per batch (one
+// workgroup), and the longest chain, which is also the halo kept on each side of a
+// fibre segment.
+constexpr int kFibBatch = 1024;
+constexpr int kChainMax = 8;
+constexpr int kFibCore = kFibBatch - 2 * kChainMax;  // most core positions of one segment
 
 }  // namespace hs
 
@@ -123,6 +129,13 @@ struct hs_index_s {
           dev_bytes = 0;
   std::vector<uint8_t> blob;   // host image of the device block
   void *pinned = nullptr;      // pinned staging for the upload
+  // fibres along every axis (hs_index_build_fibres), appended to the device block:
+  // positions row | fibre coordinate << 32 | flags << 48, the distances of each position to
+  // its k - 1 and k + 1 positions (16 bits each), and batch starts (nb + 1 per axis)
+  bool fibres = false;
+  bool fibres_uploaded = false;             // the last upload carried them (kernels use them then)
+  int64_t off_fpos = 0, off_fdel = 0, off_fbat = 0;
+  std::vector<int64_t> fpos0, fbat0, fnb;   // per axis: first position, first batch entry, batches
   hs::IndexDev view(const void *dev) const;
 };
 
@@ -175,6 +188,11 @@ struct hs_pot_s {
   std::vector<double> M;              // nslots x nterms
   // generic program
   std::vector<hs::PassOp> prog;
+  // chains of recurrence passes along one axis (op i + 1 continues op i's recurrence):
+  // chain[i] = steps of the chain that starts at op i (1: a pass of its own, 0: inside a
+  // chain); keep[i] = whether op i's output is read after its chain
+  std::vector<int32_t> chain;
+  std::vector<uint8_t> keep;
   int32_t nslots_vec = 0;             // vector slots used by the program
   int32_t split = 0;                  // outer axes evaluated by Clenshaw sums (0: trie only)
   // combination step (split > 0): output o = sum over entries e in [cptr[o], cptr[o+1])

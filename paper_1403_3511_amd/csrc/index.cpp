@@ -997,6 +997,145 @@ extern "C" int32_t hs_index_multi_indices(hs_index idx, uint16_t *out) {
   return HS_OK;
 }
 
+// ---- fibres for chained recurrence passes ----------------------------------------------
+// A recurrence pass along axis l couples each row with its neighbours k -+ e_l only, so a
+// chain of K passes along l can run on one fibre (the rows that differ in k_l alone) at a
+// time, in fast memory.  Fibres longer than kFibCore are cut into segments; each segment
+// carries up to kChainMax positions of its fibre on either side as a halo, which a chain
+// of at most kChainMax steps needs to get the core positions right.  Segments are packed
+// whole, in the order of their fibre's first row, into batches of at most kFibBatch
+// positions (see flush below for the order inside a batch).
+
+namespace {
+
+// row of the neighbour r + e_l, or -1
+int64_t row_up(const hs_index_s *ix, int64_t r, int l) {
+  const int32_t t = ix->rowtile[r];
+  const int64_t o = r - ix->tstart[t];
+  if (l < ix->np) {
+    const int32_t u = ix->tnbr[(int64_t)t * 2 * ix->np + 2 * l + 1];
+    if (u < 0 || o >= ix->tlen[u]) return -1;
+    return ix->tstart[u] + o;
+  }
+  const int a = l - ix->np;
+  const int32_t g = ix->gnbr[o * 2 * ix->d + 2 * a + 1];
+  if (g < 0 || g >= ix->tlen[t]) return -1;
+  return ix->tstart[t] + g;
+}
+
+int coord_of(const hs_index_s *ix, int64_t r, int l) {
+  const int32_t t = ix->rowtile[r];
+  if (l < ix->np) return ix->tpfx[(int64_t)t * ix->np + l];
+  return ix->gsidx[(r - ix->tstart[t]) * ix->d + (l - ix->np)];
+}
+
+}  // namespace
+
+extern "C" int32_t hs_index_build_fibres(hs_index idx) {
+  if (!idx) return hs::fail(HS_E_INVALID, "hs_index_build_fibres: NULL handle");
+  if (idx->fibres) return HS_OK;
+  if (idx->size >= (int64_t)INT32_MAX)
+    return hs::fail(HS_E_OVERFLOW, "hs_index_build_fibres: rows must fit 31 bits");
+  const int N = idx->N;
+  std::vector<uint64_t> pos;
+  std::vector<uint32_t> del;
+  std::vector<int64_t> bat;
+  std::vector<int64_t> fpos0(N), fbat0(N), fnb(N);
+  std::vector<int64_t> fib;  // rows of the current fibre
+  // segments of the batch being filled: (first, count) into seg_rows / seg_fl
+  std::vector<std::pair<int64_t, int64_t>> segs;
+  std::vector<uint64_t> seg_pos;
+  for (int l = 0; l < N; ++l) {
+    fpos0[l] = (int64_t)pos.size();
+    fbat0[l] = (int64_t)bat.size();
+    const int64_t first = (int64_t)pos.size();
+    bat.push_back(0);  // batch starts relative to fpos0[l]
+    // Positions of a batch: along a prefix axis in k-major order (the k-th positions of
+    // all its segments, longest segment first, then the (k+1)-th ...), where neighbouring
+    // fibres of one tile column sit at consecutive rows; along a suffix axis fibre after
+    // fibre.  del holds each position's distance to its k - 1 and k + 1 positions.
+    const bool kmajor = l < idx->np;
+    auto flush = [&]() {
+      if (segs.empty()) return;
+      if (!kmajor) {
+        for (const auto &sg : segs)
+          for (int64_t t = 0; t < sg.second; ++t) {
+            pos.push_back(seg_pos[(size_t)(sg.first + t)]);
+            del.push_back(1u | (1u << 16));
+          }
+      } else {
+        std::stable_sort(segs.begin(), segs.end(),
+                         [](const auto &u, const auto &v) { return u.second > v.second; });
+        const int64_t T = segs[0].second;
+        std::vector<int64_t> cnt((size_t)T, 0);
+        for (const auto &sg : segs)
+          for (int64_t t = 0; t < sg.second; ++t) cnt[(size_t)t]++;
+        for (int64_t t = 0; t < T; ++t)
+          for (int64_t q = 0; q < cnt[(size_t)t]; ++q) {
+            pos.push_back(seg_pos[(size_t)(segs[(size_t)q].first + t)]);
+            const uint32_t lo = t > 0 ? (uint32_t)cnt[(size_t)t - 1] : 0u, hi = (uint32_t)cnt[(size_t)t];
+            del.push_back(lo | (hi << 16));
+          }
+      }
+      bat.push_back((int64_t)pos.size() - first);
+      segs.clear();
+      seg_pos.clear();
+    };
+    int64_t in_batch = 0;
+    for (int64_t r = 0; r < idx->size; ++r) {
+      if (coord_of(idx, r, l) != 0) continue;  // fibres start at k_l = 0
+      fib.clear();
+      for (int64_t q = r; q >= 0; q = row_up(idx, q, l)) fib.push_back(q);
+      const int64_t L = (int64_t)fib.size();
+      if (L > 65535) return hs::fail(HS_E_OVERFLOW, "hs_index_build_fibres: fibre longer than 65535");
+      for (int64_t c0 = 0; c0 < L; c0 += hs::kFibCore) {
+        const int64_t c1 = std::min<int64_t>(L, c0 + hs::kFibCore);
+        const int64_t h0 = std::max<int64_t>(0, c0 - hs::kChainMax), h1 = std::min<int64_t>(L, c1 + hs::kChainMax);
+        const int64_t n = h1 - h0;
+        if (in_batch + n > hs::kFibBatch) {
+          flush();
+          in_batch = 0;
+        }
+        segs.emplace_back((int64_t)seg_pos.size(), n);
+        for (int64_t k = h0; k < h1; ++k) {
+          uint64_t fl = 0;
+          if (k > h0) fl |= 1;          // k - 1 is a position of the batch
+          if (k + 1 < h1) fl |= 2;      // k + 1 is a position of the batch
+          if (k >= c0 && k < c1) fl |= 4;
+          seg_pos.push_back((uint64_t)fib[(size_t)k] | ((uint64_t)k << 32) | (fl << 48));
+        }
+        in_batch += n;
+      }
+    }
+    flush();
+    fnb[l] = (int64_t)bat.size() - fbat0[l] - 1;
+  }
+  // append to the device image
+  int64_t off = idx->dev_bytes;
+  auto take = [&](int64_t bytes) {
+    int64_t o = off;
+    off = hs::align_up(off + std::max<int64_t>(bytes, 1), 256);
+    return o;
+  };
+  idx->off_fpos = take((int64_t)pos.size() * 8);
+  idx->off_fdel = take((int64_t)del.size() * 4);
+  idx->off_fbat = take((int64_t)bat.size() * 8);
+  idx->blob.resize(off, 0);
+  std::memcpy(idx->blob.data() + idx->off_fpos, pos.data(), pos.size() * 8);
+  std::memcpy(idx->blob.data() + idx->off_fdel, del.data(), del.size() * 4);
+  std::memcpy(idx->blob.data() + idx->off_fbat, bat.data(), bat.size() * 8);
+  idx->dev_bytes = off;
+  idx->fpos0 = fpos0;
+  idx->fbat0 = fbat0;
+  idx->fnb = fnb;
+  idx->fibres = true;
+  if (idx->pinned) {  // the staging copy no longer matches the image
+    (void)hipHostFree(idx->pinned);
+    idx->pinned = nullptr;
+  }
+  return HS_OK;
+}
+
 extern "C" int32_t hs_index_device_bytes(hs_index idx, int64_t *bytes) {
   if (!idx || !bytes) return hs::fail(HS_E_INVALID, "hs_index_device_bytes: NULL argument");
   *bytes = idx->dev_bytes;
@@ -1013,5 +1152,6 @@ extern "C" int32_t hs_index_upload(hs_index idx, void *dev, int64_t bytes, void 
     std::memcpy(idx->pinned, idx->blob.data(), idx->dev_bytes);
   }
   HS_HIP(hipMemcpyAsync(dev, idx->pinned, idx->dev_bytes, hipMemcpyHostToDevice, s));
+  idx->fibres_uploaded = idx->fibres;
   return HS_OK;
 }

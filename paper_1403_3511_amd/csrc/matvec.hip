@@ -441,6 +441,117 @@ k_pass(IndexDev ix, int axis, double A, double Bc, double Cc,
   }
 }
 
+// A chain of recurrence passes along one axis (steps s = 0 .. nsteps - 1):
+//   out_s = A_s X v_s + B_s v_s - C_s v_{s-1} + plus_s,  v_{s+1} = out_s,
+// with v_0 = in0 and v_{-1} = prev0 (no term when prev0 is NULL), evaluated per fibre of
+// the axis: one workgroup per batch of fibre segments (hs_index_build_fibres), the
+// current vector in LDS (a position's fibre neighbours at the distances del gives),
+// each position's own values in registers.  Each step performs
+// the operations of k_pass in the same order, so the chain gives the passes' results
+// bit for bit.  Halo positions are computed but never stored.
+template <typename T>
+struct ChainArgs {
+  const typename V2<T>::t *in0, *prev0;
+  const typename V2<T>::t *plus[kChainMax];
+  typename V2<T>::t *out[kChainMax];  // NULL: the step's output is not kept
+  double A[kChainMax], B[kChainMax], C[kChainMax];
+  int32_t term[kChainMax];            // -1: none, >= 0: y += beta[term] out, kTermOne: y += out
+  int32_t nsteps;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_chain(const uint64_t *__restrict__ pos, const uint32_t *__restrict__ del, const int64_t *__restrict__ bat,
+        ChainArgs<T> a,
+        const T *__restrict__ wt, typename V2<T>::t *__restrict__ y, const double *__restrict__ beta) {
+  using C = typename V2<T>::t;
+  constexpr int PT = kFibBatch / 256;
+  __shared__ C cur[kFibBatch];
+  const int64_t p0 = bat[blockIdx.x];
+  const int n = (int)(bat[blockIdx.x + 1] - p0);
+  uint32_t row[PT], dl[PT];
+  int kk[PT], fl[PT];
+  C v[PT], o[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    const int i = threadIdx.x + 256 * j;
+    fl[j] = 0;
+    row[j] = 0;
+    dl[j] = 0;
+    kk[j] = 0;
+    v[j] = o[j] = vz<T>();
+    if (i < n) {
+      const uint64_t q = pos[p0 + i];
+      row[j] = (uint32_t)q;
+      kk[j] = (int)((q >> 32) & 0xFFFF);
+      fl[j] = (int)(q >> 48) | 8;  // 8: a position of this batch
+      dl[j] = del[p0 + i];
+      v[j] = a.in0[row[j]];
+      if (a.prev0) o[j] = a.prev0[row[j]];
+      cur[i] = v[j];
+    }
+  }
+  // the added vector of each step is loaded one step ahead
+  C pn[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) pn[j] = (a.plus[0] && (fl[j] & 8)) ? a.plus[0][row[j]] : vz<T>();
+  __syncthreads();
+  for (int s = 0; s < a.nsteps; ++s) {
+    const T As = (T)a.A[s], Bs = (T)a.B[s], Cs = (T)(-a.C[s]);
+    const bool has_pl = a.plus[s] != nullptr;
+    const bool use_prev = s > 0 || a.prev0 != nullptr;
+    C pc[PT];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) pc[j] = pn[j];
+    if (s + 1 < a.nsteps && a.plus[s + 1]) {
+      const C *__restrict__ nx = a.plus[s + 1];
+#pragma unroll
+      for (int j = 0; j < PT; ++j)
+        if (fl[j] & 8) pn[j] = nx[row[j]];
+    }
+    C nv[PT];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      const int i = threadIdx.x + 256 * j;
+      nv[j] = vz<T>();
+      if (fl[j] & 8) {
+        C xs = vz<T>();
+        if (kk[j] > 0 && (fl[j] & 1)) fma_rc<T>(xs, wt[kk[j]], cur[i - (int)(dl[j] & 0xFFFF)]);
+        fma_rc<T>(xs, wt[kk[j] + 1], (fl[j] & 2) ? cur[i + (int)(dl[j] >> 16)] : vz<T>());
+        C out = scal<T>(As, xs);
+        fma_rc<T>(out, Bs, v[j]);
+        if (use_prev) fma_rc<T>(out, Cs, o[j]);
+        if (has_pl) {
+          out.x += pc[j].x;
+          out.y += pc[j].y;
+        }
+        nv[j] = out;
+      }
+    }
+    __syncthreads();  // every read of cur for this step is done
+    C *__restrict__ dst = a.out[s];
+    const int term = a.term[s];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      const int i = threadIdx.x + 256 * j;
+      if (fl[j] & 8) {
+        o[j] = v[j];
+        v[j] = nv[j];
+        cur[i] = nv[j];
+        if (fl[j] & 4) {
+          if (dst) dst[row[j]] = nv[j];
+          if (term != -1) {
+            C yy = y[row[j]];
+            fma_rc<T>(yy, term >= 0 ? (T)beta[term] : T(1), nv[j]);
+            y[row[j]] = yy;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_accum(int64_t n, const typename V2<T>::t *__restrict__ src, typename V2<T>::t *__restrict__ y,
@@ -627,7 +738,38 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
     return (C *)((uint8_t *)ws + (int64_t)(k - 2) * stride);
   };
   hipLaunchKernelGGL(k_diag<T>, dim3(g), dim3(256), 0, s, ix, (const C *)x, (C *)y);
-  for (const PassOp &op : p->prog) {
+  // (fibres built after the last upload are not in the device block yet: not used)
+  const bool chains = idx->fibres && idx->fibres_uploaded && p->chain.size() == p->prog.size();
+  for (size_t pi = 0; pi < p->prog.size(); ++pi) {
+    const PassOp &op = p->prog[pi];
+    if (chains && p->chain[pi] >= 2) {
+      // a chain of passes along op.axis: one launch over the axis's fibre batches
+      const int K = p->chain[pi];
+      ChainArgs<T> ca{};
+      ca.in0 = slot(op.src);
+      ca.prev0 = op.prev >= 0 ? slot(op.prev) : nullptr;
+      ca.nsteps = K;
+      for (int q = 0; q < K; ++q) {
+        const PassOp &oq = p->prog[pi + q];
+        ca.plus[q] = oq.plus >= 0 ? slot(oq.plus) : nullptr;
+        ca.out[q] = p->keep[pi + q] ? slot(oq.dst) : nullptr;
+        ca.A[q] = oq.A;
+        ca.B[q] = oq.Bc;
+        ca.C[q] = oq.C;
+        ca.term[q] = oq.term;
+      }
+      const int l = op.axis;
+      const uint8_t *ib = static_cast<const uint8_t *>(idx_dev);
+      const uint64_t *fpos = reinterpret_cast<const uint64_t *>(ib + idx->off_fpos) + idx->fpos0[l];
+      const uint32_t *fdel = reinterpret_cast<const uint32_t *>(ib + idx->off_fdel) + idx->fpos0[l];
+      const int64_t *fbat = reinterpret_cast<const int64_t *>(ib + idx->off_fbat) + idx->fbat0[l];
+      const T *wt = sizeof(T) == 8 ? (const T *)ix.wtab : (const T *)ix.wtabf;
+      if (idx->fnb[l] > 0)
+        hipLaunchKernelGGL(k_chain<T>, dim3((unsigned)idx->fnb[l]), dim3(256), 0, s, fpos, fdel, fbat, ca, wt,
+                           (C *)y, beta);
+      pi += K - 1;
+      continue;
+    }
     if (op.kind == 0) {
       hipLaunchKernelGGL(k_pass<T>, dim3(g), dim3(256), 0, s, ix, op.axis, op.A, op.Bc, op.C,
                          (const C *)slot(op.src), op.prev >= 0 ? (const C *)slot(op.prev) : nullptr,

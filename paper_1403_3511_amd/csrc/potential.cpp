@@ -395,6 +395,73 @@ double program_cost(const std::vector<hs::PassOp> &prog, int ncomb_in, int ncomb
   return c;
 }
 
+// Chains of recurrence passes (paper Sec. 3.2: the three-term recurrence of the basis,
+// applied along one axis at a time).  Op i + 1 continues op i when both are passes along
+// the same axis, op i + 1 reads op i's output as its source and op i's source as its
+// previous vector.  A chain runs as one launch over the fibres of its axis, so its inputs
+// (first source and previous vector, the added vectors) must not be among the slots it
+// writes, nor y when it accumulates into y.  An output is kept (written) when an op after
+// the chain reads it before it is written again and no later step of the chain writes
+// the same slot.
+void analyse_chains(hs_pot_s *P) {
+  const std::vector<hs::PassOp> &pg = P->prog;
+  const int n = (int)pg.size();
+  P->chain.assign(n, 1);
+  P->keep.assign(n, 1);
+  auto reads = [&](const hs::PassOp &op, int slot) {
+    if (op.kind == 0) return op.src == slot || op.prev == slot || op.plus == slot || (op.term != -1 && slot == 1);
+    if (op.kind == 1) return op.src == slot || slot == 1;
+    for (int c : P->cin_slot) if (c == slot) return true;
+    return false;
+  };
+  auto writes = [&](const hs::PassOp &op, int slot) {
+    if (op.kind == 0) return op.dst == slot || (op.term != -1 && slot == 1);
+    if (op.kind == 1) return slot == 1;
+    for (int c : P->cout_slot) if (c == slot) return true;
+    return false;
+  };
+  auto live_after = [&](int e, int slot) {
+    if (slot == 0 || slot == 1) return true;
+    for (int m = e; m < n; ++m) {
+      if (reads(pg[m], slot)) return true;
+      if (writes(pg[m], slot)) return false;
+    }
+    return false;
+  };
+  auto ok = [&](int i, int e) {
+    std::vector<int> in{pg[i].src};
+    if (pg[i].prev >= 0) in.push_back(pg[i].prev);
+    bool term = false;
+    for (int j = i; j < e; ++j) {
+      if (pg[j].plus >= 0) in.push_back(pg[j].plus);
+      term |= pg[j].term != -1;
+    }
+    for (int j = i; j < e; ++j)
+      for (int v : in)
+        if (pg[j].dst == v || (term && v == 1)) return false;
+    return true;
+  };
+  int i = 0;
+  while (i < n) {
+    int e = i + 1;
+    if (pg[i].kind == 0)
+      while (e < n && e - i < hs::kChainMax && pg[e].kind == 0 && pg[e].axis == pg[i].axis &&
+             pg[e].src == pg[e - 1].dst && pg[e].prev == pg[e - 1].src)
+        ++e;
+    while (e > i + 1 && !ok(i, e)) --e;
+    if (e - i >= 2) {
+      P->chain[i] = e - i;
+      for (int j = i; j < e; ++j) {
+        if (j > i) P->chain[j] = 0;
+        bool later = false;
+        for (int q = j + 1; q < e; ++q) later |= pg[q].dst == pg[j].dst;
+        P->keep[j] = !later && live_after(e, pg[j].dst);
+      }
+    }
+    i = e;
+  }
+}
+
 }  // namespace
 
 namespace hs {
@@ -441,6 +508,7 @@ int32_t compile_potential(hs_pot_s *P) {
       }
     }
   }
+  analyse_chains(P);
   // device block layout
   int64_t off = 0;
   auto take = [&](int64_t bytes) {

@@ -51,6 +51,7 @@ _SIGS = {
     "hs_index_multi_indices": [_vp, _pu16],
     "hs_index_device_bytes": [_vp, _pi64],
     "hs_index_upload": [_vp, _vp, _i64, _vp],
+    "hs_index_build_fibres": [_vp],
     "hs_index_create_box": [_i32, _i64, _i32, C.POINTER(_vp)],
     "hs_index_embed": [_vp, _vp, _pi32],
     "hs_index_create_total_degree": [_i32, _i64, _i32, C.POINTER(_vp)],
@@ -289,10 +290,12 @@ class Index:
     """Host handle + uploaded device block of K_N(B)."""
 
     def __init__(self, N: int, B: int = 0, tile_dim: int = 0, device="cuda", upload=True, box: bool = False,
-                 total_degree: bool = False, rows=None, pad: int = None):
+                 total_degree: bool = False, rows=None, pad: int = None, fibres: bool = False):
         """The hyperbolic cross prod(1 + k_l) <= B; with box=True the box {0..B}^N; with
         total_degree=True the set |k|_1 <= B; with rows (n x N integers) that explicit
-        downward-closed set; with pad=w the padded cross prod(1 + max(k_l - w, 0)) <= B."""
+        downward-closed set; with pad=w the padded cross prod(1 + max(k_l - w, 0)) <= B.
+        fibres=True adds the per-axis fibres on which generic potentials run their chains
+        of recurrence passes as single launches (hs_index_build_fibres)."""
         h = _vp()
         self.pad, self.rows_sha256 = pad, None
         if pad is not None:
@@ -316,6 +319,9 @@ class Index:
         d, nt, ng = C.c_int32(), C.c_int64(), C.c_int64()
         hs_index_info(h, C.byref(d), C.byref(nt), C.byref(ng))
         self.tile_dim, self.ntiles, self.nsuffix = d.value, nt.value, ng.value
+        self.fibres = bool(fibres)
+        if fibres:
+            hs_index_build_fibres(h)
         self.dev = None
         if upload:
             nb = C.c_int64()

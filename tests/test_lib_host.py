@@ -484,3 +484,25 @@ def test_bench_flop_model():
         assert bench.alg_flops_per_row(N, deg) == want
     # the harmonic part cancels in W: a pure oscillator costs the diagonal only
     assert bench.w_degrees(henon_heiles_chain(3, 0.0, 0.0), 3) == []
+
+
+def test_fibre_lists_extend_the_device_block(hs):
+    """hs_index_build_fibres appends the per-axis fibre lists (a position word, 8 bytes, and
+    its two neighbour distances, 4 bytes, per row and axis, halos included) to the device
+    block; a second call changes nothing; NULL is refused."""
+    for N, B, kw in ((2, 4096, {}), (4, 512, {}), (3, 1500, {"tile_dim": 1}), (3, 40, {"box": True})):
+        idx = hs.Index(N, B, upload=False, **kw)
+        n0 = C.c_int64()
+        hs.hs_index_device_bytes(idx.h, C.byref(n0))
+        hs.hs_index_build_fibres(idx.h)
+        n1 = C.c_int64()
+        hs.hs_index_device_bytes(idx.h, C.byref(n1))
+        assert n1.value >= n0.value + 12 * N * idx.size
+        # halos add at most 2 * 8 positions per 1008 core positions of a fibre, plus padding
+        assert n1.value <= n0.value + 12 * N * idx.size * (1 + 16 / 1008) + 12 * N * 16 * idx.size ** 0.5 + 4096
+        hs.hs_index_build_fibres(idx.h)
+        n2 = C.c_int64()
+        hs.hs_index_device_bytes(idx.h, C.byref(n2))
+        assert n2.value == n1.value
+    with pytest.raises(hs.HSError):
+        hs.hs_index_build_fibres(None)
