@@ -892,6 +892,15 @@ def fp32_n10_form(hs, stream, args):
             "fp64_valu_frac": round(vfrac["fp64"], 4)}
 
 
+def _row_permutation(k_to, k_from):
+    """perm with k_from[perm[i]] == k_to[i]: rows of one layout in another's order."""
+    import numpy as np
+    key = lambda k: np.ascontiguousarray(k.astype(np.uint16)).view(np.dtype((np.void, 2 * k.shape[1]))).ravel()
+    a, b = key(k_to), key(k_from)
+    ob = np.argsort(b)
+    return ob[np.searchsorted(b[ob], a)]
+
+
 def learned_form(hs, stream, args):
     """Learned coefficients, N = 4: Gaussian wells on circles expanded in Hermite
     polynomials of total degree <= 6 (210 coefficients).  Targets from the Gauss-Hermite
@@ -899,7 +908,9 @@ def learned_form(hs, stream, args):
     Adam (batch 256); accuracy against a Q = 24 quadrature reference on 256 held-out draws; coefficient
     latency of network, quadrature and Chebyshev interpolation (degree 6 on [-4, 4]^4,
     the Chebyshev-basis potential of the same degrees); one propagation step at product
-    bound 8192 with each coefficient source."""
+    bound 8192 with each coefficient source, on the set in tile dimension 1 with its
+    fibres (chains of passes as single launches); the H application's time there and with
+    one launch per pass on the default layout."""
     import math
     import numpy as np
     import torch
@@ -962,9 +973,11 @@ def learned_form(hs, stream, args):
     ch256 = torch.empty((256, ncheb), dtype=torch.float64, device=dev)
     lat["cheb_r6_l4_b1"] = lat_us(lambda: hs.cheb_interp(geom, Pv[:1], D, D, 4.0, out=ch1))
     lat["cheb_r6_l4_b256"] = lat_us(lambda: hs.cheb_interp(geom, Pv, D, D, 4.0, out=ch256))
-    # one step at product bound 8192 with each coefficient source
+    # one step at product bound 8192 with each coefficient source; the set in tile
+    # dimension 1 with its fibres, so that the program's chains of passes along one axis
+    # each run as one launch (fibres of the last axis are whole tiles)
     degs = hs.total_degree_multi_indices(N, D)
-    idx = hs.Index(N, 8192)
+    idx = hs.Index(N, 8192, tile_dim=1, fibres=True)
     pot = hs.Pot(N, [(0.0, a) for a in degs], basis="herm")
     c0 = coherent_state(idx.multi_indices(), np.array([0.5, 0.0, -0.3, 0.2]))
     c0 /= np.linalg.norm(c0)
@@ -997,13 +1010,22 @@ def learned_form(hs, stream, args):
     hs.gh_project(geom, prow, D, Q, out=coef)
     pot.set_coeffs_device(coef[0])
     mv_ms = event_time_ms(lambda: hs.apply_h(idx, pot, x, yq, hs.HS_C128, aws), 20, stream) / 20
+    # the same product as one launch per pass (the default layout, no fibres): same result
+    plain = hs.Index(N, 8192)
+    perm = torch.from_numpy(np.ascontiguousarray(
+        _row_permutation(plain.multi_indices(), idx.multi_indices()))).to(dev)
+    xp, yp = x[perm], torch.empty_like(x)
+    mv_passes_ms = event_time_ms(lambda: hs.apply_h(plain, pot, xp, yp, hs.HS_C128, aws), 20, stream) / 20
+    passes_diff = float(torch.linalg.norm(yp - yq[perm]) / torch.linalg.norm(yq))
+    del plain, xp, yp
     # the H application's roofline: the pass program (whole-vector recurrence and Clenshaw
     # passes plus one per-row combination) against the FP64 vector peak, by the
     # shared-prefix flop count of the 210-term potential
     fpr = alg_flops_per_row(N, [tuple(int(v) for v in a) for a in degs])
     tflops = fpr * idx.size / (mv_ms * 1e-3) / 1e12
     gbs = 32.0 * idx.size / (mv_ms * 1e-3) / 1e9
-    roof = {"bound": "alu", "kernel": "generic pass program (k_pass, k_combine, k_diag, k_accum, k_epilogue)",
+    roof = {"bound": "alu", "kernel": "generic program: chains of passes per fibre (k_chain), k_pass, "
+                                      "k_combine_dense, k_diag",
             "alg_flops_per_row": fpr, "achieved": round(tflops, 3), "peak": FP64_VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(tflops / FP64_VALU_PEAK_TFLOPS, 4),
             "alg_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
@@ -1025,6 +1047,8 @@ def learned_form(hs, stream, args):
             "step_ms_with_quadrature": round(res["quadrature"][0], 3),
             "step_ms_with_chebyshev": round(res["chebyshev"][0], 3),
             "h_apply_ms": round(mv_ms, 3), "h_apply_roofline": roof,
+            "h_apply_ms_one_launch_per_pass": round(mv_passes_ms, 3),
+            "h_apply_rel_diff_chains_vs_passes": passes_diff,
             "hc_rel_diff_network_vs_quadrature": hc_diff}
 
 
