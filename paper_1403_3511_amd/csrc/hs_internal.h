@@ -96,11 +96,12 @@ constexpr int kChunk = 64;       // rows per wave in the long-tile kernel
 constexpr int kMultiTiles = 4;   // tiles per work item of the multi-tile kernel
 constexpr int kLongTile = 32;    // tiles at least this long go to the long-tile kernel
 // Fibres for chained recurrence passes (hs_index_build_fibres): positions per batch (one
-// workgroup), and the longest chain, which is also the halo kept on each side of a
-// fibre segment.
-constexpr int kFibBatch = 1024;
+// workgroup of kFibBatch threads, one position each), and the longest chain, which is
+// also the halo kept on each side of a fibre segment.
+constexpr int kFibBatch = 256;
 constexpr int kChainMax = 8;
 constexpr int kFibCore = kFibBatch - 2 * kChainMax;  // most core positions of one segment
+constexpr int kCombChains = 8;  // most chains fused with a combination
 
 }  // namespace hs
 
@@ -170,6 +171,7 @@ struct PassOp {
   int32_t plus;      // kind 0: slot added to the result (-1 none)
 };
 constexpr int kMaxComb = 64;  // inputs / outputs of the combination step
+constexpr int kCombRegs = 32; // most inputs of the combination held in registers per row
 
 }  // namespace hs
 
@@ -193,6 +195,11 @@ struct hs_pot_s {
   // chain); keep[i] = whether op i's output is read after its chain
   std::vector<int32_t> chain;
   std::vector<uint8_t> keep;
+  // the split program's combination fused with the chains that follow it along one axis
+  // (ops [cg_op, cg_end), on sets with fibres): combination outputs whose value is read
+  // after those chains are written through (cg_wt, combination output indices)
+  int32_t cg_op = -1, cg_end = -1;
+  std::vector<int32_t> cg_wt;
   int32_t nslots_vec = 0;             // vector slots used by the program
   int32_t split = 0;                  // outer axes evaluated by Clenshaw sums (0: trie only)
   // combination step (split > 0): output o = sum over entries e in [cptr[o], cptr[o+1])

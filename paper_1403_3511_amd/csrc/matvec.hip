@@ -552,6 +552,116 @@ k_chain(const uint64_t *__restrict__ pos, const uint32_t *__restrict__ del, cons
   }
 }
 
+// The split program's combination fused with the chains that follow it along one axis
+// (hs_pot_s cg_op .. cg_end): one workgroup per fibre batch, one position per thread.
+// Each position loads the combination's inputs once and forms any combination output a
+// chain needs on the spot, with the operations of k_combine_dense in the same order; the
+// chains then run as in k_chain.  Source codes: o >= 0 a combination output, -1 none,
+// -2 - i the memory input mem[i].
+template <typename T>
+struct CombChainArgs {
+  const typename V2<T>::t *in[kCombRegs];
+  const typename V2<T>::t *mem[kCombChains];
+  typename V2<T>::t *wtp[kCombChains];  // combination outputs written through ...
+  int32_t wt[kCombChains];               // ... and their indices
+  int32_t nin, nout, nchains, nwt;
+  int32_t nsteps[kCombChains], src0[kCombChains], prev0[kCombChains];
+  int32_t plus[kCombChains][kChainMax], term[kCombChains][kChainMax];
+  double A[kCombChains][kChainMax], B[kCombChains][kChainMax], C[kCombChains][kChainMax];
+  typename V2<T>::t *out[kCombChains][kChainMax];
+};
+
+// The dense coefficient matrix M[o][i] of the combination, summed from the (input, term)
+// table as k_combine_dense sums it, once per H application (one workgroup).
+__global__ void __launch_bounds__(256)
+k_comb_matrix(int nout, const int32_t *__restrict__ ctab, const double *__restrict__ beta, double *__restrict__ M) {
+  for (int k = threadIdx.x; k < nout * kCombRegs; k += blockDim.x) M[k] = 0.0;
+  __syncthreads();
+  const int32_t *cptr = ctab, *cidx = ctab + nout + 1, *cterm = cidx + ctab[nout];
+  for (int o = threadIdx.x; o < nout; o += blockDim.x)
+    for (int e = cptr[o]; e < cptr[o + 1]; ++e) M[o * kCombRegs + cidx[e]] += beta[cterm[e]];
+}
+
+// M is read with addresses uniform across the workgroup (scalar loads, no LDS)
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_comb_chains(const uint64_t *__restrict__ pos, const uint32_t *__restrict__ del, const int64_t *__restrict__ bat,
+              CombChainArgs<T> a, const double *__restrict__ M, const double *__restrict__ beta,
+              const T *__restrict__ wt, typename V2<T>::t *__restrict__ y) {
+  using C = typename V2<T>::t;
+  __shared__ C cur[kFibBatch];
+  const int64_t p0 = bat[blockIdx.x];
+  const int n = (int)(bat[blockIdx.x + 1] - p0);
+  const int i = threadIdx.x;
+  const bool valid = i < n;
+  uint32_t row = 0, dl = 0;
+  int kk = 0, fl = 0;
+  if (valid) {
+    const uint64_t q = pos[p0 + i];
+    row = (uint32_t)q;
+    kk = (int)((q >> 32) & 0xFFFF);
+    fl = (int)(q >> 48);
+    dl = del[p0 + i];
+  }
+  C in[kCombRegs];
+#pragma unroll
+  for (int r = 0; r < kCombRegs; ++r) in[r] = (valid && r < a.nin) ? a.in[r][row] : vz<T>();
+  auto comb = [&](int o) {
+    C acc = vz<T>();
+#pragma unroll
+    for (int r = 0; r < kCombRegs; ++r) fma_rc<T>(acc, (T)M[o * kCombRegs + r], in[r]);
+    return acc;
+  };
+  auto source = [&](int code) -> C {
+    if (code >= 0) return comb(code);
+    if (code == -1 || !valid) return vz<T>();
+    return a.mem[-2 - code][row];
+  };
+  if (valid && (fl & 4))
+    for (int w = 0; w < a.nwt; ++w) a.wtp[w][row] = comb(a.wt[w]);
+  for (int g = 0; g < a.nchains; ++g) {
+    C v = source(a.src0[g]);
+    const bool has_prev0 = a.prev0[g] != -1;
+    C o = has_prev0 ? source(a.prev0[g]) : vz<T>();
+    if (valid) cur[i] = v;
+    __syncthreads();
+    for (int s = 0; s < a.nsteps[g]; ++s) {
+      const bool has_pl = a.plus[g][s] != -1;
+      const C pc = has_pl ? source(a.plus[g][s]) : vz<T>();
+      C nv = vz<T>();
+      if (valid) {
+        C xs = vz<T>();
+        if (kk > 0 && (fl & 1)) fma_rc<T>(xs, wt[kk], cur[i - (int)(dl & 0xFFFF)]);
+        fma_rc<T>(xs, wt[kk + 1], (fl & 2) ? cur[i + (int)(dl >> 16)] : vz<T>());
+        C out = scal<T>((T)a.A[g][s], xs);
+        fma_rc<T>(out, (T)a.B[g][s], v);
+        if (s > 0 || has_prev0) fma_rc<T>(out, (T)(-a.C[g][s]), o);
+        if (has_pl) {
+          out.x += pc.x;
+          out.y += pc.y;
+        }
+        nv = out;
+      }
+      __syncthreads();  // every read of cur for this step is done
+      if (valid) {
+        o = v;
+        v = nv;
+        cur[i] = nv;
+        if (fl & 4) {
+          if (a.out[g][s]) a.out[g][s][row] = nv;
+          const int term = a.term[g][s];
+          if (term != -1) {
+            C yy = y[row];
+            fma_rc<T>(yy, term >= 0 ? (T)beta[term] : T(1), nv);
+            y[row] = yy;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_accum(int64_t n, const typename V2<T>::t *__restrict__ src, typename V2<T>::t *__restrict__ y,
@@ -598,7 +708,6 @@ k_combine(int64_t n, CombSlots cs, const typename V2<T>::t *__restrict__ x, type
 // loads its row of all inputs into registers at once (the loads overlap), and the block
 // first gathers the table into a dense coefficient matrix M[o][i] = sum of beta over the
 // entries (o, i) in LDS, read back with one address across the wave.
-constexpr int kCombRegs = 32;
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_combine_dense(int64_t n, CombSlots cs, const typename V2<T>::t *__restrict__ x, typename V2<T>::t *__restrict__ y,
@@ -670,8 +779,10 @@ int32_t launch_copy_coeffs(const hs_pot_s *p, void *pot_dev, const double *coef,
 int64_t apply_workspace_bytes(const hs_index_s *idx, const hs_pot_s *p, int32_t dtype) {
   if (p->fused) return 0;
   const int64_t es = dtype == HS_C64 ? 8 : 16;
-  // slots 0 (input) and 1 (output) are the caller's vectors
-  return align_up(idx->size * es, 256) * std::max(0, p->nslots_vec - 2);
+  // slots 0 (input) and 1 (output) are the caller's vectors; then the dense coefficient
+  // matrix of a combination fused with its chains
+  return align_up(idx->size * es, 256) * std::max(0, p->nslots_vec - 2) +
+         (p->cg_op >= 0 ? (int64_t)sizeof(double) * kMaxComb * kCombRegs : 0);
 }
 
 template <typename T>
@@ -740,8 +851,63 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
   hipLaunchKernelGGL(k_diag<T>, dim3(g), dim3(256), 0, s, ix, (const C *)x, (C *)y);
   // (fibres built after the last upload are not in the device block yet: not used)
   const bool chains = idx->fibres && idx->fibres_uploaded && p->chain.size() == p->prog.size();
+  const uint8_t *ib = static_cast<const uint8_t *>(idx_dev);
+  const T *wtab = sizeof(T) == 8 ? (const T *)ix.wtab : (const T *)ix.wtabf;
   for (size_t pi = 0; pi < p->prog.size(); ++pi) {
     const PassOp &op = p->prog[pi];
+    if (chains && (int)pi == p->cg_op && (int)p->cg_wt.size() <= kCombChains) {
+      // the combination and the chains after it along one axis: one launch
+      CombChainArgs<T> ca{};
+      ca.nin = (int32_t)p->cin_slot.size();
+      ca.nout = (int32_t)p->cout_slot.size();
+      for (int r = 0; r < ca.nin; ++r) ca.in[r] = slot(p->cin_slot[r]);
+      ca.nwt = (int32_t)p->cg_wt.size();
+      for (int w = 0; w < ca.nwt; ++w) {
+        ca.wt[w] = p->cg_wt[w];
+        ca.wtp[w] = slot(p->cout_slot[p->cg_wt[w]]);
+      }
+      int nmem = 0;
+      auto code = [&](int sl) -> int32_t {
+        if (sl < 0) return -1;
+        for (int o = 0; o < ca.nout; ++o)
+          if (p->cout_slot[o] == sl) return o;
+        for (int m = 0; m < nmem; ++m)
+          if (ca.mem[m] == slot(sl)) return -2 - m;
+        ca.mem[nmem] = slot(sl);
+        return -2 - nmem++;
+      };
+      int g = 0;
+      for (int j = p->cg_op + 1; j < p->cg_end; j += p->chain[j], ++g) {
+        const int K = p->chain[j];
+        ca.nsteps[g] = K;
+        ca.src0[g] = code(p->prog[j].src);
+        ca.prev0[g] = code(p->prog[j].prev);
+        for (int q = 0; q < K; ++q) {
+          const PassOp &oq = p->prog[j + q];
+          ca.plus[g][q] = code(oq.plus);
+          ca.term[g][q] = oq.term;
+          ca.A[g][q] = oq.A;
+          ca.B[g][q] = oq.Bc;
+          ca.C[g][q] = oq.C;
+          ca.out[g][q] = p->keep[j + q] ? slot(oq.dst) : nullptr;
+        }
+      }
+      ca.nchains = g;
+      const int l = p->prog[p->cg_op + 1].axis;
+      const uint64_t *fpos = reinterpret_cast<const uint64_t *>(ib + idx->off_fpos) + idx->fpos0[l];
+      const uint32_t *fdel = reinterpret_cast<const uint32_t *>(ib + idx->off_fdel) + idx->fpos0[l];
+      const int64_t *fbat = reinterpret_cast<const int64_t *>(ib + idx->off_fbat) + idx->fbat0[l];
+      double *Mg = reinterpret_cast<double *>(static_cast<uint8_t *>(ws) +
+                                              align_up(idx->size * (int64_t)sizeof(C), 256) *
+                                                  std::max(0, p->nslots_vec - 2));
+      hipLaunchKernelGGL(k_comb_matrix, dim3(1), dim3(256), 0, s, ca.nout, (const int32_t *)(pb + p->off_comb), beta,
+                         Mg);
+      if (idx->fnb[l] > 0)
+        hipLaunchKernelGGL(k_comb_chains<T>, dim3((unsigned)idx->fnb[l]), dim3(256), 0, s, fpos, fdel, fbat, ca,
+                           (const double *)Mg, beta, wtab, (C *)y);
+      pi = (size_t)p->cg_end - 1;
+      continue;
+    }
     if (chains && p->chain[pi] >= 2) {
       // a chain of passes along op.axis: one launch over the axis's fibre batches
       const int K = p->chain[pi];
@@ -759,13 +925,11 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
         ca.term[q] = oq.term;
       }
       const int l = op.axis;
-      const uint8_t *ib = static_cast<const uint8_t *>(idx_dev);
       const uint64_t *fpos = reinterpret_cast<const uint64_t *>(ib + idx->off_fpos) + idx->fpos0[l];
       const uint32_t *fdel = reinterpret_cast<const uint32_t *>(ib + idx->off_fdel) + idx->fpos0[l];
       const int64_t *fbat = reinterpret_cast<const int64_t *>(ib + idx->off_fbat) + idx->fbat0[l];
-      const T *wt = sizeof(T) == 8 ? (const T *)ix.wtab : (const T *)ix.wtabf;
       if (idx->fnb[l] > 0)
-        hipLaunchKernelGGL(k_chain<T>, dim3((unsigned)idx->fnb[l]), dim3(256), 0, s, fpos, fdel, fbat, ca, wt,
+        hipLaunchKernelGGL(k_chain<T>, dim3((unsigned)idx->fnb[l]), dim3(256), 0, s, fpos, fdel, fbat, ca, wtab,
                            (C *)y, beta);
       pi += K - 1;
       continue;

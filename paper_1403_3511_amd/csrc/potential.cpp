@@ -462,6 +462,122 @@ void analyse_chains(hs_pot_s *P) {
   }
 }
 
+// The split program's combination and the chains right after it along one axis (the
+// Clenshaw sums of the first outer axis) can run as one launch per fibre batch: each
+// position holds the combination's inputs and forms every combination output the chains
+// add on the spot, so the combination outputs never pass through memory.  That needs, in
+// the program's order:
+//  - every chain input that is a combination output still holds that output when read
+//    (no earlier chain of the group wrote its slot); other inputs are slots no chain of
+//    the group writes;
+//  - the slots the group writes are none of the combination's inputs and none of the
+//    group's inputs read from memory (such an output is moved to a new slot first, with
+//    the reads that follow renamed);
+//  - combination outputs read after the group, still holding their value, are written.
+// Returns the number of outputs moved to new slots (analyse_chains must run again then),
+// or -1 when the group does not qualify.
+int comb_group(hs_pot_s *P, bool rename) {
+  std::vector<hs::PassOp> &pg = P->prog;
+  const int n = (int)pg.size();
+  P->cg_op = P->cg_end = -1;
+  P->cg_wt.clear();
+  int c = -1;
+  for (int i = 0; i < n; ++i)
+    if (pg[i].kind == 2) {
+      c = i;
+      break;
+    }
+  if (c < 0 || (int)P->cin_slot.size() > hs::kCombRegs || (int)P->cout_slot.size() > hs::kMaxComb) return -1;
+  for (int s : P->cin_slot)
+    if (s == 1) return -1;
+  for (int i = c + 1; i < n; ++i)
+    if (pg[i].kind == 2) return -1;  // one combination per program
+  if (c + 1 >= n || pg[c + 1].kind != 0 || P->chain[c + 1] < 1) return -1;
+  const int axis = pg[c + 1].axis;
+  int e = c + 1, nch = 0;
+  while (e < n && pg[e].kind == 0 && pg[e].axis == axis && P->chain[e] >= 1 && nch < hs::kCombChains) {
+    e += P->chain[e];
+    ++nch;
+  }
+  std::map<int, int> comb_out;  // slot -> combination output index
+  for (int o = 0; o < (int)P->cout_slot.size(); ++o) comb_out[P->cout_slot[o]] = o;
+  // 0: unchanged since the combination, 1: written by the group
+  std::map<int, int> state;
+  std::vector<int> mem_reads;
+  auto read = [&](int slot) {
+    if (slot < 0) return true;
+    if (state.count(slot) && state[slot] == 1) return false;
+    if (!comb_out.count(slot)) mem_reads.push_back(slot);
+    return true;
+  };
+  bool term = false;
+  for (int j = c + 1; j < e;) {
+    const int K = P->chain[j];
+    if (!read(pg[j].src) || !read(pg[j].prev)) return -1;
+    for (int q = j; q < j + K; ++q) {
+      if (!read(pg[q].plus)) return -1;
+      term |= pg[q].term != -1;
+    }
+    for (int q = j; q < j + K; ++q) state[pg[q].dst] = 1;
+    j += K;
+  }
+  if ((int)mem_reads.size() > hs::kCombChains) return -1;
+  for (int v : mem_reads)
+    if ((state.count(v) && state[v] == 1) || (term && v == 1)) return -1;
+  // written outputs (kept) that the combination or the group's memory reads use
+  std::vector<int> moved;
+  for (int j = c + 1; j < e; ++j) {
+    if (!P->keep[j]) continue;
+    const int d = pg[j].dst;
+    bool clash = false;
+    for (int v : P->cin_slot) clash |= v == d;
+    for (int v : mem_reads) clash |= v == d;
+    if (clash) moved.push_back(j);
+  }
+  if (!moved.empty()) {
+    if (!rename) return -1;
+    for (int j : moved) {
+      const int old = pg[j].dst, fresh = P->nslots_vec++;
+      pg[j].dst = fresh;
+      for (int m = j + 1; m < n; ++m) {
+        hs::PassOp &op = pg[m];
+        if (op.kind == 0) {
+          if (op.src == old) op.src = fresh;
+          if (op.prev == old) op.prev = fresh;
+          if (op.plus == old) op.plus = fresh;
+          if (op.dst == old) break;
+        } else if (op.kind == 1) {
+          if (op.src == old) op.src = fresh;
+        } else {
+          return -1;  // a second combination: not expected after the first
+        }
+      }
+    }
+    return (int)moved.size();
+  }
+  // combination outputs read after the group while they still hold their value
+  for (const auto &kv : comb_out) {
+    const int slot = kv.first;
+    if (state.count(slot) && state[slot] == 1) continue;
+    bool used = false;
+    for (int m = e; m < n && !used; ++m) {
+      const hs::PassOp &op = pg[m];
+      if (op.kind == 0) {
+        used = op.src == slot || op.prev == slot || op.plus == slot;
+        if (op.dst == slot) break;
+      } else if (op.kind == 1) {
+        used = op.src == slot;
+      } else {
+        used = true;
+      }
+    }
+    if (used) P->cg_wt.push_back(kv.second);
+  }
+  P->cg_op = c;
+  P->cg_end = e;
+  return 0;
+}
+
 }  // namespace
 
 namespace hs {
@@ -509,6 +625,10 @@ int32_t compile_potential(hs_pot_s *P) {
     }
   }
   analyse_chains(P);
+  if (!P->fused && comb_group(P, true) > 0) {
+    analyse_chains(P);
+    comb_group(P, false);
+  }
   // device block layout
   int64_t off = 0;
   auto take = [&](int64_t bytes) {

@@ -498,8 +498,9 @@ def test_fibre_lists_extend_the_device_block(hs):
         n1 = C.c_int64()
         hs.hs_index_device_bytes(idx.h, C.byref(n1))
         assert n1.value >= n0.value + 12 * N * idx.size
-        # halos add at most 2 * 8 positions per 1008 core positions of a fibre, plus padding
-        assert n1.value <= n0.value + 12 * N * idx.size * (1 + 16 / 1008) + 12 * N * 16 * idx.size ** 0.5 + 4096
+        # halos add at most 2 * 8 positions per 240 core positions of a fibre; batch starts
+        # (one per 256 positions) and padding
+        assert n1.value <= n0.value + 12 * N * idx.size * (1 + 16 / 240) + 8 * N * (idx.size / 64 + 2) + 4096
         hs.hs_index_build_fibres(idx.h)
         n2 = C.c_int64()
         hs.hs_index_device_bytes(idx.h, C.byref(n2))
