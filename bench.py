@@ -1024,8 +1024,9 @@ def learned_form(hs, stream, args):
     fpr = alg_flops_per_row(N, [tuple(int(v) for v in a) for a in degs])
     tflops = fpr * idx.size / (mv_ms * 1e-3) / 1e12
     gbs = 32.0 * idx.size / (mv_ms * 1e-3) / 1e9
-    roof = {"bound": "alu", "kernel": "generic program: chains of passes per fibre (k_chain), k_pass, "
-                                      "k_combine_dense, k_diag",
+    roof = {"bound": "alu", "kernel": "generic program: chains of passes per fibre (k_chain), the combination "
+                                      "fused with the first outer axis's chains (k_comb_matrix, k_comb_chains), "
+                                      "k_pass, k_diag",
             "alg_flops_per_row": fpr, "achieved": round(tflops, 3), "peak": FP64_VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(tflops / FP64_VALU_PEAK_TFLOPS, 4),
             "alg_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
