@@ -111,7 +111,8 @@ int32_t hs_index_upload(hs_index idx, void *dev, int64_t bytes, void *stream);
  * with results equal bit for bit.  Appends about 8 bytes per row and axis to the device
  * block: call it before hs_index_device_bytes and hs_index_upload (a block sized or
  * uploaded before must be sized and uploaded again).  Idempotent.  HS_E_OVERFLOW for
- * sets of 2^31 rows or more or fibres longer than 65535 rows.                        */
+ * sets of 2^31 rows or more, fibres longer than 65535 rows, or lists beyond 16 GiB;
+ * HS_E_NOMEM when host memory runs out (the handle is then unchanged).             */
 int32_t hs_index_build_fibres(hs_index idx);
 
 /* Box sets {0..Kmax}^N (the full index set K_full of paper Sec. 4.1-4.2), in the same

@@ -1031,11 +1031,7 @@ int coord_of(const hs_index_s *ix, int64_t r, int l) {
 
 }  // namespace
 
-extern "C" int32_t hs_index_build_fibres(hs_index idx) {
-  if (!idx) return hs::fail(HS_E_INVALID, "hs_index_build_fibres: NULL handle");
-  if (idx->fibres) return HS_OK;
-  if (idx->size >= (int64_t)INT32_MAX)
-    return hs::fail(HS_E_OVERFLOW, "hs_index_build_fibres: rows must fit 31 bits");
+static int32_t build_fibres(hs_index idx) {
   const int N = idx->N;
   std::vector<uint64_t> pos;
   std::vector<uint32_t> del;
@@ -1134,6 +1130,23 @@ extern "C" int32_t hs_index_build_fibres(hs_index idx) {
     idx->pinned = nullptr;
   }
   return HS_OK;
+}
+
+// the lists take 12 bytes per row and axis (plus halos); more than this is refused
+static const int64_t kFibreBytesMax = int64_t(16) << 30;
+
+extern "C" int32_t hs_index_build_fibres(hs_index idx) {
+  if (!idx) return hs::fail(HS_E_INVALID, "hs_index_build_fibres: NULL handle");
+  if (idx->fibres) return HS_OK;
+  if (idx->size >= (int64_t)INT32_MAX)
+    return hs::fail(HS_E_OVERFLOW, "hs_index_build_fibres: rows must fit 31 bits");
+  if ((double)idx->size * idx->N * 12.0 * (1.0 + 16.0 / hs::kFibCore) > (double)kFibreBytesMax)
+    return hs::fail(HS_E_OVERFLOW, "hs_index_build_fibres: the fibre lists would exceed 16 GiB");
+  try {
+    return build_fibres(idx);
+  } catch (const std::bad_alloc &) {
+    return hs::fail(HS_E_NOMEM, "hs_index_build_fibres: out of host memory");
+  }
 }
 
 extern "C" int32_t hs_index_device_bytes(hs_index idx, int64_t *bytes) {

@@ -130,3 +130,63 @@ def test_fibres_built_after_upload_are_not_used(hs):
     hs.apply_h(idx, pot, c, y1)          # new block: chains
     torch.cuda.synchronize()
     assert torch.equal(y0, y1)
+
+
+def test_fibre_step_graph_replays_equal_eager(hs):
+    """A step on a set with fibres (chains, the fused combination) captured once and
+    replayed, with eager work between replays, gives the eager steps bit for bit."""
+    import torch
+    N, B, m, h = 4, 1024, 8, 0.002
+    pot = hs.Pot(N, total_degree_terms(N, 6, 17), basis="herm")
+    idx = hs.Index(N, B, tile_dim=1, fibres=True)
+    rng = np.random.default_rng(23)
+    c0 = rng.standard_normal(idx.size) + 1j * rng.standard_normal(idx.size)
+    c0 /= np.linalg.norm(c0)
+    ce = torch.from_numpy(c0.copy()).to("cuda")
+    wse = hs.workspace(idx, pot, 0, m)
+    te = torch.zeros(1, dtype=torch.float64, device="cuda")
+    eager = []
+    for _ in range(3):
+        hs.step(idx, pot, ce, 0.0, h, m, ws=wse, t_dev=te)
+        eager.append(ce.cpu().numpy().copy())
+    cg = torch.from_numpy(c0.copy()).to("cuda")
+    wsg = hs.workspace(idx, pot, 0, m)
+    tg = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    snapshot = cg.clone()
+    with torch.cuda.stream(s2):
+        with torch.cuda.graph(g, stream=s2):
+            hs.step(idx, pot, cg, 0.0, h, m, ws=wsg, t_dev=tg)
+    torch.cuda.synchronize()
+    cg.copy_(snapshot)
+    tg.zero_()
+    torch.cuda.synchronize()
+    junk = torch.randn(1000, device="cuda")
+    for i in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        junk = junk * 1.0001 + 1.0
+        torch.cuda.synchronize()
+        assert np.array_equal(cg.cpu().numpy(), eager[i]), f"replay {i} differs from eager"
+
+
+def test_fibre_magnus4_step_equals_the_passes(hs):
+    """The fourth-order step applies H four times per Krylov vector through the generic
+    program: with fibres it is the same bit for bit."""
+    import torch
+    N, B, m, h = 3, 600, 6, 0.005
+    pot = hs.Pot(N, total_degree_terms(N, 5, 29), basis="herm")
+    plain = hs.Index(N, B)
+    fib = hs.Index(N, B, fibres=True)
+    rng = np.random.default_rng(5)
+    c0 = rng.standard_normal(plain.size) + 1j * rng.standard_normal(plain.size)
+    c0 /= np.linalg.norm(c0)
+    a = torch.from_numpy(c0.copy()).to("cuda")
+    b = a.clone()
+    hs.step_magnus4(plain, pot, a, 0.0, h, m)
+    hs.step_magnus4(fib, pot, b, 0.0, h, m)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
