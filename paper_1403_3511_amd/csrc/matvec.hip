@@ -446,9 +446,9 @@ k_pass(IndexDev ix, int axis, double A, double Bc, double Cc,
 // with v_0 = in0 and v_{-1} = prev0 (no term when prev0 is NULL), evaluated per fibre of
 // the axis: one workgroup per batch of fibre segments (hs_index_build_fibres), the
 // current vector in LDS (a position's fibre neighbours at the distances del gives),
-// each position's own values in registers.  Each step performs
-// the operations of k_pass in the same order, so the chain gives the passes' results
-// bit for bit.  Halo positions are computed but never stored.
+// each position's own values in registers.  Each step performs the operations of k_pass
+// in the same order, so the chain gives the passes' results bit for bit.  Halo positions
+// are computed but never stored.
 template <typename T>
 struct ChainArgs {
   const typename V2<T>::t *in0, *prev0;
@@ -462,8 +462,8 @@ struct ChainArgs {
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_chain(const uint64_t *__restrict__ pos, const uint32_t *__restrict__ del, const int64_t *__restrict__ bat,
-        ChainArgs<T> a,
-        const T *__restrict__ wt, typename V2<T>::t *__restrict__ y, const double *__restrict__ beta) {
+        ChainArgs<T> a, const T *__restrict__ wt, typename V2<T>::t *__restrict__ y,
+        const double *__restrict__ beta) {
   using C = typename V2<T>::t;
   constexpr int PT = kFibBatch / 256;
   __shared__ C cur[kFibBatch];
