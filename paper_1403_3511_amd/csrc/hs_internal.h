@@ -200,6 +200,9 @@ struct hs_pot_s {
   // after those chains are written through (cg_wt, combination output indices)
   int32_t cg_op = -1, cg_end = -1;
   std::vector<int32_t> cg_wt;
+  // consecutive independent chains along one axis run as one launch: mc_end[i] = the end
+  // of the group that starts at op i (0: none)
+  std::vector<int32_t> mc_end;
   int32_t nslots_vec = 0;             // vector slots used by the program
   int32_t split = 0;                  // outer axes evaluated by Clenshaw sums (0: trie only)
   // combination step (split > 0): output o = sum over entries e in [cptr[o], cptr[o+1])

@@ -582,8 +582,10 @@ k_comb_matrix(int nout, const int32_t *__restrict__ ctab, const double *__restri
     for (int e = cptr[o]; e < cptr[o + 1]; ++e) M[o * kCombRegs + cidx[e]] += beta[cterm[e]];
 }
 
-// M is read with addresses uniform across the workgroup (scalar loads, no LDS)
-template <typename T>
+// M is read with addresses uniform across the workgroup (scalar loads, no LDS).  With
+// COMB = false the same kernel runs a group of independent chains along one axis whose
+// inputs all come from memory (no combination), one after the other on each batch.
+template <typename T, bool COMB>
 __global__ void __launch_bounds__(256)
 k_comb_chains(const uint64_t *__restrict__ pos, const uint32_t *__restrict__ del, const int64_t *__restrict__ bat,
               CombChainArgs<T> a, const double *__restrict__ M, const double *__restrict__ beta,
@@ -603,21 +605,22 @@ k_comb_chains(const uint64_t *__restrict__ pos, const uint32_t *__restrict__ del
     fl = (int)(q >> 48);
     dl = del[p0 + i];
   }
-  C in[kCombRegs];
+  constexpr int NI = COMB ? kCombRegs : 1;
+  C in[NI];
 #pragma unroll
-  for (int r = 0; r < kCombRegs; ++r) in[r] = (valid && r < a.nin) ? a.in[r][row] : vz<T>();
+  for (int r = 0; r < NI; ++r) in[r] = (COMB && valid && r < a.nin) ? a.in[r][row] : vz<T>();
   auto comb = [&](int o) {
     C acc = vz<T>();
 #pragma unroll
-    for (int r = 0; r < kCombRegs; ++r) fma_rc<T>(acc, (T)M[o * kCombRegs + r], in[r]);
+    for (int r = 0; r < NI; ++r) fma_rc<T>(acc, (T)M[o * kCombRegs + r], in[r]);
     return acc;
   };
   auto source = [&](int code) -> C {
-    if (code >= 0) return comb(code);
-    if (code == -1 || !valid) return vz<T>();
-    return a.mem[-2 - code][row];
+    if (COMB && code >= 0) return comb(code);
+    if (code < -1 && valid) return a.mem[-2 - code][row];
+    return vz<T>();
   };
-  if (valid && (fl & 4))
+  if (COMB && valid && (fl & 4))
     for (int w = 0; w < a.nwt; ++w) a.wtp[w][row] = comb(a.wt[w]);
   for (int g = 0; g < a.nchains; ++g) {
     C v = source(a.src0[g]);
@@ -903,9 +906,47 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
       hipLaunchKernelGGL(k_comb_matrix, dim3(1), dim3(256), 0, s, ca.nout, (const int32_t *)(pb + p->off_comb), beta,
                          Mg);
       if (idx->fnb[l] > 0)
-        hipLaunchKernelGGL(k_comb_chains<T>, dim3((unsigned)idx->fnb[l]), dim3(256), 0, s, fpos, fdel, fbat, ca,
-                           (const double *)Mg, beta, wtab, (C *)y);
+        hipLaunchKernelGGL((k_comb_chains<T, true>), dim3((unsigned)idx->fnb[l]), dim3(256), 0, s, fpos, fdel, fbat,
+                           ca, (const double *)Mg, beta, wtab, (C *)y);
       pi = (size_t)p->cg_end - 1;
+      continue;
+    }
+    if (chains && pi < p->mc_end.size() && p->mc_end[pi] > 0) {
+      // independent chains along one axis, reading memory only: one launch
+      CombChainArgs<T> ca{};
+      int nmem = 0;
+      auto code = [&](int sl) -> int32_t {
+        if (sl < 0) return -1;
+        for (int m = 0; m < nmem; ++m)
+          if (ca.mem[m] == slot(sl)) return -2 - m;
+        ca.mem[nmem] = slot(sl);
+        return -2 - nmem++;
+      };
+      int g = 0;
+      for (int j = (int)pi; j < p->mc_end[pi]; j += p->chain[j], ++g) {
+        const int K = p->chain[j];
+        ca.nsteps[g] = K;
+        ca.src0[g] = code(p->prog[j].src);
+        ca.prev0[g] = code(p->prog[j].prev);
+        for (int q = 0; q < K; ++q) {
+          const PassOp &oq = p->prog[j + q];
+          ca.plus[g][q] = code(oq.plus);
+          ca.term[g][q] = oq.term;
+          ca.A[g][q] = oq.A;
+          ca.B[g][q] = oq.Bc;
+          ca.C[g][q] = oq.C;
+          ca.out[g][q] = p->keep[j + q] ? slot(oq.dst) : nullptr;
+        }
+      }
+      ca.nchains = g;
+      const int l = op.axis;
+      const uint64_t *fpos = reinterpret_cast<const uint64_t *>(ib + idx->off_fpos) + idx->fpos0[l];
+      const uint32_t *fdel = reinterpret_cast<const uint32_t *>(ib + idx->off_fdel) + idx->fpos0[l];
+      const int64_t *fbat = reinterpret_cast<const int64_t *>(ib + idx->off_fbat) + idx->fbat0[l];
+      if (idx->fnb[l] > 0)
+        hipLaunchKernelGGL((k_comb_chains<T, false>), dim3((unsigned)idx->fnb[l]), dim3(256), 0, s, fpos, fdel,
+                           fbat, ca, (const double *)nullptr, beta, wtab, (C *)y);
+      pi = (size_t)p->mc_end[pi] - 1;
       continue;
     }
     if (chains && p->chain[pi] >= 2) {

@@ -578,6 +578,65 @@ int comb_group(hs_pot_s *P, bool rename) {
   return 0;
 }
 
+// Consecutive chains along one axis (outside the combination's group) that read only
+// memory no chain of the group writes, and whose kept outputs are none of the group's
+// inputs, run as one launch over the axis's fibre batches, chain after chain.
+void multi_chain_groups(hs_pot_s *P) {
+  const std::vector<hs::PassOp> &pg = P->prog;
+  const int n = (int)pg.size();
+  P->mc_end.assign(n, 0);
+  int i = 0;
+  while (i < n) {
+    if (pg[i].kind != 0 || P->chain[i] < 1 || (P->cg_op >= 0 && i > P->cg_op && i < P->cg_end)) {
+      ++i;
+      continue;
+    }
+    // extend while the next chain is on the same axis and independent of the group so far
+    std::vector<int> in, out;
+    bool term = false;
+    int e = i, nch = 0;
+    while (e < n && pg[e].kind == 0 && P->chain[e] >= 1 && pg[e].axis == pg[i].axis && nch < hs::kCombChains &&
+           !(P->cg_op >= 0 && e > P->cg_op && e < P->cg_end)) {
+      const int K = P->chain[e];
+      std::vector<int> cin{pg[e].src};
+      if (pg[e].prev >= 0) cin.push_back(pg[e].prev);
+      bool t = false;
+      for (int q = e; q < e + K; ++q) {
+        if (pg[q].plus >= 0) cin.push_back(pg[q].plus);
+        t |= pg[q].term != -1;
+      }
+      std::vector<int> cdst;
+      for (int q = e; q < e + K; ++q) cdst.push_back(pg[q].dst);
+      // inputs of the new chain: not written by the group so far (any step, kept or not);
+      // its writes: none of the group's inputs, its own included
+      bool ok = true;
+      std::vector<int> all_in = in;
+      all_in.insert(all_in.end(), cin.begin(), cin.end());
+      for (int v : cin)
+        for (int d : out) ok &= v != d;
+      for (int d : cdst)
+        for (int v : all_in) ok &= v != d;
+      if ((t || term) && std::find(all_in.begin(), all_in.end(), 1) != all_in.end()) ok = false;
+      std::vector<int> uniq = all_in;
+      std::sort(uniq.begin(), uniq.end());
+      uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+      if ((int)uniq.size() > hs::kCombChains) ok = false;
+      if (!ok) break;
+      in = all_in;
+      out.insert(out.end(), cdst.begin(), cdst.end());
+      term |= t;
+      e += K;
+      ++nch;
+    }
+    if (nch >= 2) {
+      P->mc_end[i] = e;
+      i = e;
+    } else {
+      i += std::max(1, P->chain[i]);
+    }
+  }
+}
+
 }  // namespace
 
 namespace hs {
@@ -629,6 +688,7 @@ int32_t compile_potential(hs_pot_s *P) {
     analyse_chains(P);
     comb_group(P, false);
   }
+  multi_chain_groups(P);
   // device block layout
   int64_t off = 0;
   auto take = [&](int64_t bytes) {
