@@ -394,9 +394,23 @@ k_hh_tiles(IndexDev ix, const double *__restrict__ hh, const typename V2<T>::t *
 }
 
 // ---- generic passes -------------------------------------------------------------------
+// The dense coefficient matrix M[o][i] of the split program's combination, summed from
+// the (input, term) table as k_combine_dense sums it; one workgroup, every thread.
+__device__ __forceinline__ void comb_matrix_block(int nout, const int32_t *__restrict__ ctab,
+                                                  const double *__restrict__ beta, double *__restrict__ M) {
+  for (int k = threadIdx.x; k < nout * kCombRegs; k += blockDim.x) M[k] = 0.0;
+  __syncthreads();
+  const int32_t *cptr = ctab, *cidx = ctab + nout + 1, *cterm = cidx + ctab[nout];
+  for (int o = threadIdx.x; o < nout; o += blockDim.x)
+    for (int e = cptr[o]; e < cptr[o + 1]; ++e) M[o * kCombRegs + cidx[e]] += beta[cterm[e]];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_diag(IndexDev ix, const typename V2<T>::t *__restrict__ x, typename V2<T>::t *__restrict__ y) {
+k_diag(IndexDev ix, const typename V2<T>::t *__restrict__ x, typename V2<T>::t *__restrict__ y, int nout,
+       const int32_t *__restrict__ ctab, const double *__restrict__ beta, double *__restrict__ M) {
+  // block 0 also builds the combination's dense coefficient matrix when M is given
+  if (M && blockIdx.x == 0) comb_matrix_block(nout, ctab, beta, M);
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= ix.size) return;
   const int32_t t0 = ix.rowtile[r];
@@ -571,18 +585,8 @@ struct CombChainArgs {
   typename V2<T>::t *out[kCombChains][kChainMax];
 };
 
-// The dense coefficient matrix M[o][i] of the combination, summed from the (input, term)
-// table as k_combine_dense sums it, once per H application (one workgroup).
-__global__ void __launch_bounds__(256)
-k_comb_matrix(int nout, const int32_t *__restrict__ ctab, const double *__restrict__ beta, double *__restrict__ M) {
-  for (int k = threadIdx.x; k < nout * kCombRegs; k += blockDim.x) M[k] = 0.0;
-  __syncthreads();
-  const int32_t *cptr = ctab, *cidx = ctab + nout + 1, *cterm = cidx + ctab[nout];
-  for (int o = threadIdx.x; o < nout; o += blockDim.x)
-    for (int e = cptr[o]; e < cptr[o + 1]; ++e) M[o * kCombRegs + cidx[e]] += beta[cterm[e]];
-}
-
-// M is read with addresses uniform across the workgroup (scalar loads, no LDS).  With
+// M (built by the diagonal's first workgroup) is read with addresses uniform across the
+// workgroup (scalar loads, no LDS).  With
 // COMB = false the same kernel runs a group of independent chains along one axis whose
 // inputs all come from memory (no combination), one after the other on each batch.
 template <typename T, bool COMB>
@@ -851,14 +855,22 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
     if (k == 1) return (C *)y;
     return (C *)((uint8_t *)ws + (int64_t)(k - 2) * stride);
   };
-  hipLaunchKernelGGL(k_diag<T>, dim3(g), dim3(256), 0, s, ix, (const C *)x, (C *)y);
   // (fibres built after the last upload are not in the device block yet: not used)
   const bool chains = idx->fibres && idx->fibres_uploaded && p->chain.size() == p->prog.size();
+  const bool fuse_comb = chains && p->cg_op >= 0 && (int)p->cg_wt.size() <= kCombChains;
+  // the fused combination's coefficient matrix, after the slots in the workspace; the
+  // diagonal's first workgroup builds it
+  double *Mg = fuse_comb ? reinterpret_cast<double *>(static_cast<uint8_t *>(ws) +
+                                                       align_up(idx->size * (int64_t)sizeof(C), 256) *
+                                                           std::max(0, p->nslots_vec - 2))
+                         : nullptr;
+  hipLaunchKernelGGL(k_diag<T>, dim3(g), dim3(256), 0, s, ix, (const C *)x, (C *)y, (int)p->cout_slot.size(),
+                     (const int32_t *)(pb + p->off_comb), beta, Mg);
   const uint8_t *ib = static_cast<const uint8_t *>(idx_dev);
   const T *wtab = sizeof(T) == 8 ? (const T *)ix.wtab : (const T *)ix.wtabf;
   for (size_t pi = 0; pi < p->prog.size(); ++pi) {
     const PassOp &op = p->prog[pi];
-    if (chains && (int)pi == p->cg_op && (int)p->cg_wt.size() <= kCombChains) {
+    if (fuse_comb && (int)pi == p->cg_op) {
       // the combination and the chains after it along one axis: one launch
       CombChainArgs<T> ca{};
       ca.nin = (int32_t)p->cin_slot.size();
@@ -900,11 +912,6 @@ static int32_t apply_impl(const hs_index_s *idx, const void *idx_dev, const hs_p
       const uint64_t *fpos = reinterpret_cast<const uint64_t *>(ib + idx->off_fpos) + idx->fpos0[l];
       const uint32_t *fdel = reinterpret_cast<const uint32_t *>(ib + idx->off_fdel) + idx->fpos0[l];
       const int64_t *fbat = reinterpret_cast<const int64_t *>(ib + idx->off_fbat) + idx->fbat0[l];
-      double *Mg = reinterpret_cast<double *>(static_cast<uint8_t *>(ws) +
-                                              align_up(idx->size * (int64_t)sizeof(C), 256) *
-                                                  std::max(0, p->nslots_vec - 2));
-      hipLaunchKernelGGL(k_comb_matrix, dim3(1), dim3(256), 0, s, ca.nout, (const int32_t *)(pb + p->off_comb), beta,
-                         Mg);
       if (idx->fnb[l] > 0)
         hipLaunchKernelGGL((k_comb_chains<T, true>), dim3((unsigned)idx->fnb[l]), dim3(256), 0, s, fpos, fdel, fbat,
                            ca, (const double *)Mg, beta, wtab, (C *)y);
