@@ -106,9 +106,11 @@ int32_t hs_index_device_bytes(hs_index idx, int64_t *bytes);
 int32_t hs_index_upload(hs_index idx, void *dev, int64_t bytes, void *stream);
 /* Fibres of every axis for chained recurrence passes (an addition to paper Sec. 3.2,
  * eq. Horner, whose passes apply the basis's three-term recurrence along one axis at a
- * time): the generic program's chains of passes along one axis then run as one launch
- * over that axis's fibres (rows differing in k_l alone) instead of one launch per pass,
- * with results equal bit for bit.  Appends about 8 bytes per row and axis to the device
+ * time): the generic program's chains of passes along one axis, and the split form's
+ * combination with the chains that follow it, then run as single launches over that
+ * axis's fibres (rows differing in k_l alone) instead of one launch per pass, with
+ * results equal bit for bit.  The fibres serve only once the block carrying them is
+ * uploaded; an index without them keeps one launch per pass.  Appends about 12 bytes per row and axis to the device
  * block: call it before hs_index_device_bytes and hs_index_upload (a block sized or
  * uploaded before must be sized and uploaded again).  Idempotent.  HS_E_OVERFLOW for
  * sets of 2^31 rows or more, fibres longer than 65535 rows, or lists beyond 16 GiB;
