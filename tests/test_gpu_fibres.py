@@ -43,7 +43,8 @@ def total_degree_terms(N, D, seed):
 # axes are prefix axes, whose batches are laid out k-major)
 CASES = [(2, 4096, "hyperbolic", "herm", 6), (3, 2048, "hyperbolic", "cheb", 5), (4, 512, "hyperbolic", "herm", 6),
          (3, 40, "box", "mono", 4), (4, 24, "total_degree", "herm", 5), (5, 256, "hyperbolic", "herm", 4),
-         (3, 1500, "hyperbolic_d1", "herm", 6), (4, 1024, "hyperbolic_d1", "cheb", 6)]
+         (3, 1500, "hyperbolic_d1", "herm", 6), (4, 1024, "hyperbolic_d1", "cheb", 6),
+         (3, 300, "list", "herm", 5), (3, 200, "padded", "mono", 4)]
 
 
 def make_index(hs, N, B, kind, fibres):
@@ -53,6 +54,10 @@ def make_index(hs, N, B, kind, fibres):
         return hs.Index(N, B, total_degree=True, fibres=fibres)
     if kind == "hyperbolic_d1":
         return hs.Index(N, B, tile_dim=1, fibres=fibres)
+    if kind == "list":  # the hyperbolic cross given row by row (tile dimension 0)
+        return hs.Index(N, rows=hs.Index(N, B, upload=False).multi_indices(), fibres=fibres)
+    if kind == "padded":
+        return hs.Index(N, B, pad=2, fibres=fibres)
     return hs.Index(N, B, fibres=fibres)
 
 
