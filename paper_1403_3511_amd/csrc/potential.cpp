@@ -488,8 +488,12 @@ int comb_group(hs_pot_s *P, bool rename) {
       break;
     }
   if (c < 0 || (int)P->cin_slot.size() > hs::kCombRegs || (int)P->cout_slot.size() > hs::kMaxComb) return -1;
-  for (int s : P->cin_slot)
+  for (int s : P->cin_slot) {
     if (s == 1) return -1;
+    // an output written through over an input would race with other workgroups' reads
+    for (int o : P->cout_slot)
+      if (o == s) return -1;
+  }
   for (int i = c + 1; i < n; ++i)
     if (pg[i].kind == 2) return -1;  // one combination per program
   if (c + 1 >= n || pg[c + 1].kind != 0 || P->chain[c + 1] < 1) return -1;

@@ -195,3 +195,27 @@ def test_fibre_magnus4_step_equals_the_passes(hs):
     hs.step_magnus4(fib, pot, b, 0.0, h, m)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("seed", range(9))
+def test_random_generic_potentials_with_fibres(hs, seed):
+    """The random potentials of test_gpu_generic.py (trie and split programs, three bases,
+    N = 2..5, terms accumulated into y along the way): with fibres the same bit for bit."""
+    import torch
+    from tests.test_gpu_generic import random_case
+    N, B, basis, scale, degs, coefs = random_case(seed)
+    pot = hs.Pot(N, [(float(cf), d) for cf, d in zip(coefs, degs)], basis=basis, scale=scale)
+    plain = hs.Index(N, B)
+    for td in (0, 1):
+        fib = hs.Index(N, B, tile_dim=td, fibres=True)
+        if td == 1:
+            plain_td = hs.Index(N, B, tile_dim=1)
+        else:
+            plain_td = plain
+        rng = np.random.default_rng(seed)
+        c = torch.from_numpy(rng.standard_normal(fib.size) + 1j * rng.standard_normal(fib.size)).to("cuda")
+        y0, y1 = torch.empty_like(c), torch.empty_like(c)
+        hs.apply_h(plain_td, pot, c, y0)
+        hs.apply_h(fib, pot, c, y1)
+        torch.cuda.synchronize()
+        assert torch.equal(y0, y1), f"seed {seed}, tile dimension {td}"
